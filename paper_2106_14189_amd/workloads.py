@@ -1,0 +1,294 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module holds mesh geometry, random draws and load descriptions only --
+none of the DJ-TLED arithmetic -- so that the GPU path and the CPU oracle can
+be fed the same inputs.  The paper's own meshes (a cube with circular
+cut-outs, Sec. 5.1; a brain mesh, Sec. 6) are not available; these stand in:
+
+* ``cube_mesh``: a jittered structured grid of voxels, each split into six
+  linear tetrahedra (Kuhn/Freudenthal split, conforming) or kept as one
+  8-node hexahedron.  Node orders follow the conventions of the library:
+  T4 with positive det under h = (1 - xi - eta - zeta, xi, eta, zeta); H8 in
+  (---, +--, ++-, -+-, --+, +-+, +++, -++) order.
+* ``ellipsoid_mesh``: voxelised ellipsoid, Kuhn-split, interior jitter.
+* load descriptions: bottom face fixed, top face z-displacement ramped.
+
+Seeds follow ``210614189 + 1000 * config + instance``.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED_BASE = 210614189
+
+T4, H8 = 4, 8
+NH, TI = 0, 1
+RAMP_NONE, RAMP_LINEAR, RAMP_SMOOTH = 0, 1, 2
+
+
+def seed_for(config: int, instance: int = 0) -> int:
+    return SEED_BASE + 1000 * config + instance
+
+
+@dataclass
+class Mesh:
+    X: np.ndarray            # (N, 3) float64 reference coordinates
+    conn: np.ndarray         # (E, ne) int32
+    bottom: np.ndarray       # node ids on the z = min face
+    top: np.ndarray          # node ids on the z = max face
+    height: float = 0.0
+
+    @property
+    def ne(self) -> int:
+        return int(self.conn.shape[1])
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.X.shape[0])
+
+    @property
+    def n_elems(self) -> int:
+        return int(self.conn.shape[0])
+
+
+@dataclass
+class Material:
+    model: int
+    E: np.ndarray                       # (E,) Young's modulus [Pa]
+    nu: np.ndarray                      # (E,) Poisson's ratio
+    rho: float = 1000.0
+    eta_ratio: np.ndarray | None = None  # (E,) fibre stiffness ratio (TI)
+    fibre: np.ndarray | None = None      # (E, 3) unit fibre directions (TI)
+    hg_kappa: float = 0.1
+
+
+@dataclass
+class Loads:
+    bc_node: np.ndarray                 # (nb,) int32
+    bc_mask: np.ndarray                 # (nb,) int32, bit k = component k constrained
+    bc_target: np.ndarray               # (nb, 3) float64 target displacement at ramp end
+    ramp: int = RAMP_SMOOTH
+    t_ramp: float = 0.0
+    R: np.ndarray | None = None         # (N, 3) external nodal forces or None
+
+
+@dataclass
+class Workload:
+    name: str
+    mesh: Mesh
+    material: Material
+    loads: Loads
+    dt_factor: float = 0.9
+    alpha: float = 0.0
+    n_steps: int = 0
+    fp64: bool = False
+    seed: int = 0
+    extra: dict = field(default_factory=dict)
+
+
+# Kuhn split: the six tetrahedra of a voxel follow the monotone lattice paths
+# from corner (0,0,0) to (1,1,1).  Odd permutations get their last two
+# vertices swapped so every tetrahedron is positively oriented.
+_PERMS = [((0, 1, 2), +1), ((0, 2, 1), -1), ((1, 0, 2), -1),
+          ((1, 2, 0), +1), ((2, 0, 1), +1), ((2, 1, 0), -1)]
+_H8_CORNERS = [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1), (1, 1, 1), (0, 1, 1)]
+
+
+def _kuhn_tets():
+    tets = []
+    for perm, sign in _PERMS:
+        c = [0, 0, 0]
+        verts = [tuple(c)]
+        for ax in perm:
+            c[ax] += 1
+            verts.append(tuple(c))
+        if sign < 0:
+            verts[2], verts[3] = verts[3], verts[2]
+        tets.append(verts)
+    return tets
+
+
+def _grid_conn(nx, ny, nz, elem, voxel_mask=None):
+    def nid(i, j, k):
+        return i + (nx + 1) * (j + (ny + 1) * k)
+
+    i, j, k = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    i = i.transpose(2, 1, 0).ravel()
+    j = j.transpose(2, 1, 0).ravel()
+    k = k.transpose(2, 1, 0).ravel()
+    if voxel_mask is not None:
+        keep = voxel_mask[i, j, k]
+        i, j, k = i[keep], j[keep], k[keep]
+    if elem == H8:
+        cols = [nid(i + a, j + b, k + c) for (a, b, c) in _H8_CORNERS]
+        return np.stack(cols, axis=1).astype(np.int32)
+    per = []
+    for verts in _kuhn_tets():
+        per.append(np.stack([nid(i + a, j + b, k + c) for (a, b, c) in verts], axis=1))
+    # voxel-major: the 6 tets of one voxel are consecutive
+    return np.stack(per, axis=1).reshape(-1, 4).astype(np.int32)
+
+
+def cube_mesh(n: int, h: float, elem: int = T4, jitter: float = 0.05, seed: int = 0,
+              permute: bool = False) -> Mesh:
+    """n^3 voxels of side h.  Interior nodes are jittered uniformly by
+    +-jitter*h per coordinate; boundary nodes move only tangentially, so the
+    faces stay planar and the total volume stays (n h)^3."""
+    rng = np.random.default_rng(seed)
+    g = np.arange(n + 1)
+    kk, jj, ii = np.meshgrid(g, g, g, indexing="ij")
+    idx = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1)      # node id = i + (n+1)(j + (n+1)k)
+    X = idx.astype(np.float64) * h
+    if jitter > 0:
+        d = rng.uniform(-jitter * h, jitter * h, size=X.shape)
+        on_bnd = (idx == 0) | (idx == n)
+        d[on_bnd] = 0.0
+        X = X + d
+    conn = _grid_conn(n, n, n, elem)
+    bottom = np.nonzero(idx[:, 2] == 0)[0]
+    top = np.nonzero(idx[:, 2] == n)[0]
+    mesh = Mesh(X=X, conn=conn, bottom=bottom.astype(np.int32), top=top.astype(np.int32), height=n * h)
+    if permute:
+        mesh = permute_mesh(mesh, rng)
+    return mesh
+
+
+def permute_mesh(mesh: Mesh, rng) -> Mesh:
+    """Random relabelling of nodes and elements (mimics unstructured ordering)."""
+    N, E = mesh.n_nodes, mesh.n_elems
+    pn = rng.permutation(N)            # new id -> old id
+    inv = np.empty(N, np.int64)
+    inv[pn] = np.arange(N)             # old id -> new id
+    pe = rng.permutation(E)
+    X = mesh.X[pn]
+    conn = inv[mesh.conn[pe]].astype(np.int32)
+    return Mesh(X=X, conn=conn, bottom=np.sort(inv[mesh.bottom]).astype(np.int32),
+                top=np.sort(inv[mesh.top]).astype(np.int32), height=mesh.height)
+
+
+def signed_volume6(X, conn):
+    """6 x the signed volume of each tetrahedron (mesh validity check only)."""
+    a, b, c, d = (X[conn[:, i]] for i in range(4))
+    return np.einsum("ij,ij->i", b - a, np.cross(c - a, d - a))
+
+
+def ellipsoid_mesh(semi=(0.05, 0.04, 0.03), target_elems=1_200_000, jitter=0.15, seed=0,
+                   permute=True) -> Mesh:
+    """Voxelised ellipsoid: voxels whose centre lies inside are kept and
+    Kuhn-split; interior nodes are jittered by +-jitter*h (re-drawn where a
+    tetrahedron would lose positive orientation)."""
+    rng = np.random.default_rng(seed)
+    a, b, c = semi
+    vol = 4.0 / 3.0 * np.pi * a * b * c
+    h = (vol / (target_elems / 6.0)) ** (1.0 / 3.0)
+    n = [int(np.ceil(2 * s / h)) + 2 for s in semi]
+    lo = np.array([-s for s in semi]) - h
+    ci = (np.arange(n[0]) + 0.5) * h + lo[0]
+    cj = (np.arange(n[1]) + 0.5) * h + lo[1]
+    ck = (np.arange(n[2]) + 0.5) * h + lo[2]
+    I, J, K = np.meshgrid(ci, cj, ck, indexing="ij")
+    inside = (I / a) ** 2 + (J / b) ** 2 + (K / c) ** 2 <= 1.0
+    conn_full = _grid_conn(n[0], n[1], n[2], T4, inside)
+    used = np.unique(conn_full)
+    remap = -np.ones((n[0] + 1) * (n[1] + 1) * (n[2] + 1), np.int64)
+    remap[used] = np.arange(len(used))
+    conn = remap[conn_full].astype(np.int32)
+    gi = used % (n[0] + 1)
+    gj = (used // (n[0] + 1)) % (n[1] + 1)
+    gk = used // ((n[0] + 1) * (n[1] + 1))
+    X = np.stack([gi, gj, gk], axis=1).astype(np.float64) * h + lo
+    # boundary nodes: those belonging to a voxel face that is not shared
+    counts = np.zeros(len(used), np.int64)
+    np.add.at(counts, conn.ravel(), 1)
+    interior = counts == 24  # a Kuhn-interior node touches 24 tetrahedra
+    if jitter > 0:
+        for _ in range(8):
+            d = rng.uniform(-jitter * h, jitter * h, size=X.shape)
+            d[~interior] = 0.0
+            Xn = X + d
+            bad = signed_volume6(Xn, conn) <= 0.05 * h ** 3
+            if not bad.any():
+                X = Xn
+                break
+            # keep the draw except at nodes of bad elements
+            badn = np.unique(conn[bad])
+            d[badn] = 0.0
+            Xn = X + d
+            if (signed_volume6(Xn, conn) > 0).all():
+                X = Xn
+                break
+    zmin = X[:, 2].min()
+    bottom = np.nonzero((X[:, 2] < -0.8 * c) & ~interior)[0]
+    top = np.nonzero((X[:, 2] > 0.8 * c) & ~interior)[0]
+    mesh = Mesh(X=X, conn=conn, bottom=bottom.astype(np.int32), top=top.astype(np.int32),
+                height=float(X[:, 2].max() - zmin))
+    mesh.surface = np.nonzero(~interior)[0].astype(np.int32)
+    mesh.h = h
+    if permute:
+        pn = rng.permutation(mesh.n_nodes)
+        inv = np.empty(mesh.n_nodes, np.int64)
+        inv[pn] = np.arange(mesh.n_nodes)
+        pe = rng.permutation(mesh.n_elems)
+        m2 = Mesh(X=mesh.X[pn], conn=inv[mesh.conn[pe]].astype(np.int32),
+                  bottom=np.sort(inv[mesh.bottom]).astype(np.int32),
+                  top=np.sort(inv[mesh.top]).astype(np.int32), height=mesh.height)
+        m2.surface = np.sort(inv[mesh.surface]).astype(np.int32)
+        m2.h = h
+        mesh = m2
+    return mesh
+
+
+def compression_loads(mesh: Mesh, strain: float = -0.2, ramp=RAMP_SMOOTH, t_ramp=0.0) -> Loads:
+    """Bottom face fixed in all components; top face z-displacement ramped to
+    strain * height (x and y free)."""
+    nb = len(mesh.bottom)
+    nt = len(mesh.top)
+    bc_node = np.concatenate([mesh.bottom, mesh.top]).astype(np.int32)
+    bc_mask = np.concatenate([np.full(nb, 7), np.full(nt, 4)]).astype(np.int32)
+    tgt = np.zeros((nb + nt, 3))
+    tgt[nb:, 2] = strain * mesh.height
+    return Loads(bc_node=bc_node, bc_mask=bc_mask, bc_target=tgt, ramp=ramp, t_ramp=t_ramp)
+
+
+def uniform_material(n_elems, E, nu, rho=1000.0, model=NH, rng=None, eta_ratio_range=(2.0, 10.0)):
+    E = np.broadcast_to(np.asarray(E, np.float64), (n_elems,)).copy()
+    nu = np.broadcast_to(np.asarray(nu, np.float64), (n_elems,)).copy()
+    mat = Material(model=model, E=E, nu=nu, rho=rho)
+    if model == TI:
+        rng = rng or np.random.default_rng(0)
+        v = rng.normal(size=(n_elems, 3))
+        mat.fibre = v / np.linalg.norm(v, axis=1, keepdims=True)
+        mat.eta_ratio = rng.uniform(*eta_ratio_range, size=n_elems)
+    return mat
+
+
+# ---------------------------------------------------------------------------
+# The benchmark configurations
+# ---------------------------------------------------------------------------
+
+def config0(seed_offset: int = 0) -> Workload:
+    """10^3 voxels of 0.01 m, 6 tets each (6000 T4 / 1331 nodes), NH E=3000 Pa,
+    nu=0.45, rho=1000; bottom fixed, top z ramped smoothly to -20 % of the
+    height over the run; dt = 0.9 x critical; 2000 steps; FP64."""
+    seed = seed_for(0) + seed_offset
+    mesh = cube_mesh(10, 0.01, T4, jitter=0.05, seed=seed)
+    mat = uniform_material(mesh.n_elems, 3000.0, 0.45, 1000.0)
+    loads = compression_loads(mesh, -0.2, RAMP_SMOOTH)
+    # damping: alpha = 2 omega_hat, omega_hat = pi c_s / (2 L) with c_s = sqrt(mu / rho)
+    return Workload("cube10_t4_nh_fp64", mesh, mat, loads, 0.9, alpha=32.0, n_steps=2000, fp64=True, seed=seed)
+
+
+def config1(elem: int = T4, n: int = 64, n_steps: int = 1000, seed_offset: int = 0) -> Workload:
+    """64^3 voxels over a 0.1 m cube as 1,572,864 T4 or 262,144 H8 (274,625
+    nodes); E ~ U[2, 6] kPa per element, nu = 0.45, rho = 1000; jitter +-5 %;
+    elements and nodes randomly permuted; config-0 compression load; FP32."""
+    seed = seed_for(1) + seed_offset + (0 if elem == T4 else 500)
+    rng = np.random.default_rng(seed + 7)
+    mesh = cube_mesh(n, 0.1 / n, elem, jitter=0.05, seed=seed, permute=True)
+    E = rng.uniform(2000.0, 6000.0, size=mesh.n_elems)
+    mat = uniform_material(mesh.n_elems, E, 0.45, 1000.0)
+    loads = compression_loads(mesh, -0.2, RAMP_SMOOTH)
+    name = f"cube{n}_{'t4' if elem == T4 else 'h8'}_nh_fp32"
+    return Workload(name, mesh, mat, loads, 0.9, alpha=37.0, n_steps=n_steps, fp64=False, seed=seed)
