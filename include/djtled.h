@@ -1,0 +1,200 @@
+/*
+ * djtled.h -- C ABI of the MI355X DJ-TLED library (libdjtled.so).
+ *
+ * Implements the time step of the direct Jacobian total Lagrangian explicit
+ * dynamics method (Zhang, arXiv 2106.14189) on one AMD Instinct MI355X
+ * (gfx950):
+ *   (a) element nodal forces from the precomputed Jacobian constants and the
+ *       gathered nodal displacements (Sec. 2.2, Eq. 10; Table 3 neo-Hookean and
+ *       transversely isotropic rows; invariants of Table 1),
+ *   (b) reduction of the element forces to the nodes (the sum of Eq. 13),
+ *   (c) central-difference explicit integration with lumped mass-proportional
+ *       damping (Eq. 13) and displacement boundary conditions, under the
+ *       critical step of Eq. 14.
+ *
+ * Conventions shared by every entry point
+ *   - Host pointers are read during the call only; the library never keeps or
+ *     frees caller memory.  Device pointers must be device memory of the
+ *     context's GPU (hipMalloc or a framework allocator).
+ *   - Node and element indices are the caller's; the library reorders
+ *     internally (space-filling-curve order) and permutes at call entry and exit.
+ *   - Device vectors of nodal quantities are n_nodes x 3, row-major (x, y, z of
+ *     node 0, then node 1, ...), in the context's precision (float for
+ *     DJ_FP32, double for DJ_FP64).
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Return codes: DJ_OK (0), DJ_CONVERGED (1, informational), or a negative
+ *     DJ_ERR_*.  djtled_last_error() returns a thread-local message for the
+ *     last failing call on the calling thread.
+ */
+#ifndef DJTLED_H
+#define DJTLED_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DJ_OK 0
+#define DJ_CONVERGED 1
+#define DJ_ERR_ARG (-1)          /* invalid argument (null pointer, bad size or enum) */
+#define DJ_ERR_BAD_MESH (-2)     /* node index out of range, or det(0J) <= 0 (Eq. 3 / Eq. 12) */
+#define DJ_ERR_INVERTED (-3)     /* run-time volume ratio J <= 0 (Eq. 12) */
+#define DJ_ERR_NONFINITE (-4)    /* a force or displacement became NaN / Inf */
+#define DJ_ERR_UNSUPPORTED (-5)  /* element type / model / precision not built */
+#define DJ_ERR_UNSTABLE_DT (-6)  /* dt above the critical step of Eq. 14 without override */
+#define DJ_ERR_HIP (-7)          /* a HIP runtime call failed (message has the hipError_t) */
+#define DJ_ERR_BARRIER (-8)      /* the persistent kernel's grid barrier timed out */
+
+enum { DJ_T4 = 4, DJ_H8 = 8 };                 /* linear tetrahedron, 8-node hexahedron */
+enum { DJ_NH = 0, DJ_TI = 1 };                 /* neo-Hookean, transversely isotropic NH */
+enum { DJ_FP32 = 0, DJ_FP64 = 1 };
+enum { DJ_RAMP_NONE = 0, DJ_RAMP_LINEAR = 1, DJ_RAMP_SMOOTH = 2 };
+enum { DJ_MODE_FIXED = 0, DJ_MODE_RELAX = 1 };
+
+/* Mesh (host memory).  T4 nodes follow h = (1 - xi - eta - zeta, xi, eta,
+   zeta) with det(0J) > 0; H8 nodes follow (---, +--, ++-, -+-, --+, +-+, +++,
+   -++) in natural coordinates. */
+typedef struct {
+    int32_t n_nodes;
+    int32_t n_elems;
+    int32_t elem_type;      /* DJ_T4 or DJ_H8 */
+    const double *X;        /* n_nodes x 3 reference coordinates [m] */
+    const int32_t *conn;    /* n_elems x elem_type node indices */
+} djtled_mesh;
+
+/* Material (host memory).  mu = E / (2 (1 + nu)), kappa = E / (3 (1 - 2 nu)).
+   Per-element arrays may be NULL, in which case the *_uniform value is used. */
+typedef struct {
+    int32_t model;          /* DJ_NH or DJ_TI (Table 3) */
+    const double *E;        /* n_elems Young's modulus [Pa] or NULL */
+    const double *nu;       /* n_elems Poisson's ratio or NULL */
+    double E_uniform, nu_uniform;
+    double rho;             /* mass density [kg / m^3] */
+    const double *eta_ratio;   /* DJ_TI: eta_a / mu per element, or NULL */
+    double eta_ratio_uniform;
+    const double *fibre;    /* DJ_TI: n_elems x 3 fibre directions a (normalised internally) */
+    double hg_kappa;        /* DJ_H8: hourglass coefficient (Flanagan-Belytschko form); <0 -> 0.1 */
+} djtled_material;
+
+/* Solver parameters. */
+typedef struct {
+    int32_t precision;      /* DJ_FP32 or DJ_FP64 */
+    double dt;              /* time step [s]; 0 -> dt_factor x critical step (Eq. 14) */
+    double dt_factor;       /* <= 0 -> 0.9 */
+    double alpha;           /* mass-proportional damping D = alpha M [1/s] (Eq. 13) */
+    int32_t allow_unstable_dt;  /* nonzero: accept dt above the critical step */
+    int32_t chunk_elems;    /* elements per workgroup tile; 0 -> automatic */
+    int32_t variant;        /* kernel variant index (autotuner); 0 -> default */
+    int32_t device;         /* HIP device ordinal; < 0 -> current device */
+} djtled_params;
+
+typedef struct djtled_ctx djtled_ctx;
+typedef struct djtled_loadset djtled_loadset;
+
+/*
+ * djtled_precompute -- Algorithm 1, pre-computation.
+ * Validates the mesh, reorders it, and builds on the GPU (FP64) every
+ * per-element constant the run time needs: the Jacobian 0J (Eq. 3) and its
+ * inverse, whose columns are the shape-function derivatives dh/dX of Eq. 6,
+ * the volume 0V, the constant I1m = 2 0V 0J^-T 0J^-1 (Eq. 37) kept through
+ * 0J^-1, and for DJ_TI the fibre factor of I4m (Eq. 45); for DJ_H8 the
+ * hourglass vectors; the lumped nodal masses and the critical step (Eq. 14).
+ * On success *out owns every device buffer of the context.
+ * Errors: DJ_ERR_ARG, DJ_ERR_BAD_MESH, DJ_ERR_UNSUPPORTED, DJ_ERR_UNSTABLE_DT, DJ_ERR_HIP.
+ */
+int djtled_precompute(const djtled_mesh *mesh, const djtled_material *material,
+                      const djtled_params *params, djtled_ctx **out);
+
+/* Frees the context and its device memory (waits for the device first). */
+int djtled_destroy(djtled_ctx *ctx);
+
+typedef struct {
+    int32_t n_nodes, n_elems, elem_type, model, precision;
+    double dt, dt_crit, alpha;
+    int32_t n_chunks, chunk_elems, n_copies, n_shared_copies, grid_blocks, block_threads, variant;
+    double bytes_per_step;     /* algorithmic HBM bytes of one fused step */
+    double elem_bytes;         /* per-element part of bytes_per_step */
+    double mass_total;         /* sum of lumped masses [kg] */
+} djtled_info_t;
+
+/* Fills *out with sizes, the time step and the traffic model. */
+int djtled_info(const djtled_ctx *ctx, djtled_info_t *out);
+
+/*
+ * djtled_forces -- internal nodal forces sum_e F^(e)(u) (Eq. 13), each element
+ * force from Table 3 (plus hourglass control for H8).  u_dev, f_dev: device,
+ * n_nodes x 3.  No boundary condition is applied.  Asynchronous on stream.
+ * Errors: DJ_ERR_ARG, DJ_ERR_HIP.
+ */
+int djtled_forces(djtled_ctx *ctx, const void *u_dev, void *f_dev, void *stream);
+
+/* Loads (host memory): displacement boundary conditions and external forces. */
+typedef struct {
+    int32_t n_bc;
+    const int32_t *bc_node;   /* n_bc node indices */
+    const int32_t *bc_mask;   /* n_bc masks: bit k set = component k prescribed */
+    const double *bc_target;  /* n_bc x 3 target displacement at the end of the ramp */
+    int32_t ramp;             /* DJ_RAMP_* : s(t) = 1, t / t_ramp, or the quintic smoothstep */
+    double t_ramp;            /* ramp duration [s] */
+    const double *R;          /* n_nodes x 3 external nodal forces [N] (Eq. 13), or NULL */
+} djtled_loads;
+
+/* Uploads a load case to the device (synchronous).  The load set belongs to
+   the context and is freed with it or by djtled_loadset_destroy. */
+int djtled_loadset_create(djtled_ctx *ctx, const djtled_loads *loads, djtled_loadset **out);
+int djtled_loadset_destroy(djtled_loadset *ls);
+
+/* Caller-owned explicit state: u^n and u^{n-1} (device, n_nodes x 3) and n. */
+typedef struct {
+    void *u_cur;
+    void *u_prev;
+    int64_t step;
+} djtled_state;
+
+typedef struct {
+    int32_t mode;             /* DJ_MODE_FIXED or DJ_MODE_RELAX (dynamic relaxation) */
+    double tol;               /* RELAX: stop when the residual is <= tol */
+    int32_t check_every;      /* RELAX: residual period in steps (>= 1) */
+} djtled_step_opts;
+
+typedef struct {
+    int32_t code;             /* DJ_OK, DJ_CONVERGED or DJ_ERR_* */
+    int32_t steps_done;       /* steps completed by this call */
+    int64_t error_step;       /* global step of a run-time error, else -1 */
+    int32_t error_elem;       /* caller element index of DJ_ERR_INVERTED, else -1 */
+    double residual;          /* last residual evaluated (RELAX), else NaN */
+} djtled_status;
+
+/*
+ * djtled_step -- n_steps explicit steps of Eq. 13 in ONE persistent kernel
+ * launch: per step, element forces (Table 3) -> node reduction -> central
+ * difference with damping -> displacement BCs, with one grid barrier per step.
+ *   u^{n+1} = u^n + B' (u^n - u^{n-1}) + A_i (R_i - F_i(u^n)),
+ *   B' = (2 - alpha dt) / (2 + alpha dt),  A_i = 2 dt^2 / ((2 + alpha dt) m_i),
+ * then prescribed components are set to s(t_{n+1}) * target.
+ * RELAX: every check_every steps, once the ramp is complete, the residual
+ * |(F - R)_free|_2 / |F_constrained|_2 of u^n is evaluated and the run stops
+ * without advancing when it is <= tol (code DJ_CONVERGED).
+ * On return state->u_cur / u_prev / step hold the last completed step; on
+ * DJ_ERR_INVERTED that is the step before the failing one.  loads may be NULL
+ * (free body, no external force).  Synchronises `stream` to read the status.
+ */
+int djtled_step(djtled_ctx *ctx, djtled_state *state, const djtled_loadset *loads, int32_t n_steps,
+                const djtled_step_opts *opts, djtled_status *out, void *stream);
+
+/*
+ * djtled_export_constants -- copies per-element constants to host memory in
+ * caller element order, in FP64: V[n_elems], dhdX[n_elems x 3 x elem_type]
+ * (row i = d h_a / d X_i, Eq. 6), and the lumped masses mass[n_nodes] in
+ * caller node order.  Any output pointer may be NULL.  Synchronous.
+ */
+int djtled_export_constants(djtled_ctx *ctx, double *V, double *dhdX, double *mass);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *djtled_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DJTLED_H */

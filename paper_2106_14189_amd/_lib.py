@@ -1,0 +1,118 @@
+"""ctypes binding of libdjtled.so (argument marshalling only).
+
+Every call goes straight to the C ABI declared in ``include/djtled.h``; the
+names are the same.  PyTorch supplies device memory and streams.  There is no
+fallback: if the library is missing or fails to load, importing this module
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdjtled.so")
+
+DJ_OK, DJ_CONVERGED = 0, 1
+DJ_ERR_ARG, DJ_ERR_BAD_MESH, DJ_ERR_INVERTED, DJ_ERR_NONFINITE = -1, -2, -3, -4
+DJ_ERR_UNSUPPORTED, DJ_ERR_UNSTABLE_DT, DJ_ERR_HIP, DJ_ERR_BARRIER = -5, -6, -7, -8
+DJ_T4, DJ_H8 = 4, 8
+DJ_NH, DJ_TI = 0, 1
+DJ_FP32, DJ_FP64 = 0, 1
+DJ_RAMP_NONE, DJ_RAMP_LINEAR, DJ_RAMP_SMOOTH = 0, 1, 2
+DJ_MODE_FIXED, DJ_MODE_RELAX = 0, 1
+
+ERROR_NAMES = {0: "DJ_OK", 1: "DJ_CONVERGED", -1: "DJ_ERR_ARG", -2: "DJ_ERR_BAD_MESH", -3: "DJ_ERR_INVERTED",
+               -4: "DJ_ERR_NONFINITE", -5: "DJ_ERR_UNSUPPORTED", -6: "DJ_ERR_UNSTABLE_DT", -7: "DJ_ERR_HIP",
+               -8: "DJ_ERR_BARRIER"}
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+_vp = ctypes.c_void_p
+
+
+class djtled_mesh(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int32), ("n_elems", ctypes.c_int32), ("elem_type", ctypes.c_int32),
+                ("X", _dp), ("conn", _ip)]
+
+
+class djtled_material(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("E", _dp), ("nu", _dp), ("E_uniform", ctypes.c_double),
+                ("nu_uniform", ctypes.c_double), ("rho", ctypes.c_double), ("eta_ratio", _dp),
+                ("eta_ratio_uniform", ctypes.c_double), ("fibre", _dp), ("hg_kappa", ctypes.c_double)]
+
+
+class djtled_params(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("dt", ctypes.c_double), ("dt_factor", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("allow_unstable_dt", ctypes.c_int32), ("chunk_elems", ctypes.c_int32),
+                ("variant", ctypes.c_int32), ("device", ctypes.c_int32)]
+
+
+class djtled_info_t(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int32), ("n_elems", ctypes.c_int32), ("elem_type", ctypes.c_int32),
+                ("model", ctypes.c_int32), ("precision", ctypes.c_int32), ("dt", ctypes.c_double),
+                ("dt_crit", ctypes.c_double), ("alpha", ctypes.c_double), ("n_chunks", ctypes.c_int32),
+                ("chunk_elems", ctypes.c_int32), ("n_copies", ctypes.c_int32), ("n_shared_copies", ctypes.c_int32),
+                ("grid_blocks", ctypes.c_int32), ("block_threads", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("bytes_per_step", ctypes.c_double), ("elem_bytes", ctypes.c_double),
+                ("mass_total", ctypes.c_double)]
+
+
+class djtled_loads(ctypes.Structure):
+    _fields_ = [("n_bc", ctypes.c_int32), ("bc_node", _ip), ("bc_mask", _ip), ("bc_target", _dp),
+                ("ramp", ctypes.c_int32), ("t_ramp", ctypes.c_double), ("R", _dp)]
+
+
+class djtled_state(ctypes.Structure):
+    _fields_ = [("u_cur", _vp), ("u_prev", _vp), ("step", ctypes.c_int64)]
+
+
+class djtled_step_opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("tol", ctypes.c_double), ("check_every", ctypes.c_int32)]
+
+
+class djtled_status(ctypes.Structure):
+    _fields_ = [("code", ctypes.c_int32), ("steps_done", ctypes.c_int32), ("error_step", ctypes.c_int64),
+                ("error_elem", ctypes.c_int32), ("residual", ctypes.c_double)]
+
+
+EXPORTS = {
+    "djtled_precompute": (ctypes.c_int, [ctypes.POINTER(djtled_mesh), ctypes.POINTER(djtled_material),
+                                         ctypes.POINTER(djtled_params), ctypes.POINTER(_vp)]),
+    "djtled_destroy": (ctypes.c_int, [_vp]),
+    "djtled_info": (ctypes.c_int, [_vp, ctypes.POINTER(djtled_info_t)]),
+    "djtled_forces": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "djtled_loadset_create": (ctypes.c_int, [_vp, ctypes.POINTER(djtled_loads), ctypes.POINTER(_vp)]),
+    "djtled_loadset_destroy": (ctypes.c_int, [_vp]),
+    "djtled_step": (ctypes.c_int, [_vp, ctypes.POINTER(djtled_state), _vp, ctypes.c_int32,
+                                   ctypes.POINTER(djtled_step_opts), ctypes.POINTER(djtled_status), _vp]),
+    "djtled_export_constants": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
+    "djtled_last_error": (ctypes.c_char_p, []),
+}
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"libdjtled.so not built at {path}; run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = load()
+
+
+class DJError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = lib.djtled_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {ERROR_NAMES.get(code, code)}: {msg}")
+
+
+def check(code: int, where: str) -> int:
+    if code < 0:
+        raise DJError(code, where)
+    return code

@@ -1,0 +1,636 @@
+// C ABI of libdjtled: validation, mesh reordering and partitioning, device
+// buffers, and the entry points declared in include/djtled.h.  All numerical
+// work of the method runs in the HIP kernels (djtled_kernels.hip); this file
+// only builds index structures and moves buffers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "djtled_internal.h"
+
+using namespace dj;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define DJ_HIP(call)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess) return fail(DJ_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(Ctx &c, T **p, size_t n) {
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T));
+    if (e == hipSuccess) {
+        c.allocs.push_back(q);
+        *p = static_cast<T *>(q);
+    }
+    return e;
+}
+
+template <typename T>
+hipError_t upload(Ctx &c, T **p, const std::vector<T> &v) {
+    hipError_t e = dalloc(c, p, v.size());
+    if (e != hipSuccess) return e;
+    if (!v.empty()) e = hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    return e;
+}
+
+void free_all(Ctx *c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    for (void *p : c->loadsets) {
+        LoadSet *ls = static_cast<LoadSet *>(p);
+        hipFree(ls->d_flags);
+        hipFree(ls->d_ru);
+        delete ls;
+    }
+    for (void *p : c->allocs) hipFree(p);
+    if (c->h_status) hipHostFree(c->h_status);
+    if (c->h_res) hipHostFree(c->h_res);
+    delete c;
+}
+
+// 21-bit spread for 3-D Morton codes
+uint64_t spread3(uint64_t x) {
+    x &= 0x1fffffULL;
+    x = (x | x << 32) & 0x1f00000000ffffULL;
+    x = (x | x << 16) & 0x1f0000ff0000ffULL;
+    x = (x | x << 8) & 0x100f00f00f00f00fULL;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ULL;
+    x = (x | x << 2) & 0x1249249249249249ULL;
+    return x;
+}
+
+struct TempBufs {
+    std::vector<void *> v;
+    ~TempBufs() {
+        for (void *p : v) hipFree(p);
+    }
+    template <typename T>
+    hipError_t up(T **p, const std::vector<T> &h) {
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, std::max<size_t>(h.size(), 1) * sizeof(T));
+        if (e != hipSuccess) return e;
+        v.push_back(q);
+        *p = static_cast<T *>(q);
+        if (!h.empty()) e = hipMemcpy(q, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+        return e;
+    }
+};
+
+int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djtled_params *prm) {
+    const int N = mesh->n_nodes, E = mesh->n_elems, NE = mesh->elem_type;
+    c.n_nodes = N;
+    c.n_elems = E;
+    c.ne = NE;
+    c.model = mat->model;
+    c.prec = prm->precision;
+    c.rho = mat->rho;
+    c.alpha = prm->alpha;
+    c.hg_kappa = mat->hg_kappa < 0 ? 0.1 : mat->hg_kappa;
+    c.variant = prm->variant;
+    const Variant var = variants(NE, c.prec)[c.variant];
+    c.block = var.block;
+    c.ept = var.ept;
+    c.cmax = var.block * var.ept;
+
+    // ---- reorder: elements by the Morton code of their centroid, nodes by first touch
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int n = 0; n < N; n++)
+        for (int k = 0; k < 3; k++) {
+            lo[k] = std::min(lo[k], mesh->X[3 * n + k]);
+            hi[k] = std::max(hi[k], mesh->X[3 * n + k]);
+        }
+    double span = 0;
+    for (int k = 0; k < 3; k++) span = std::max(span, hi[k] - lo[k]);
+    if (!(span > 0)) span = 1.0;
+    std::vector<uint64_t> code(E);
+    for (int e = 0; e < E; e++) {
+        double cc[3] = {0, 0, 0};
+        for (int a = 0; a < NE; a++)
+            for (int k = 0; k < 3; k++) cc[k] += mesh->X[3 * mesh->conn[int64_t(NE) * e + a] + k];
+        uint64_t q[3];
+        for (int k = 0; k < 3; k++) {
+            double t = (cc[k] / NE - lo[k]) / span;
+            q[k] = uint64_t(std::min(std::max(t, 0.0), 1.0) * 2097151.0);
+        }
+        code[e] = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[2]) << 2);
+    }
+    c.elem_perm.resize(E);
+    std::iota(c.elem_perm.begin(), c.elem_perm.end(), 0);
+    std::stable_sort(c.elem_perm.begin(), c.elem_perm.end(), [&](int a, int b) { return code[a] < code[b]; });
+    std::vector<int32_t> node_new(N, -1);
+    c.node_perm.clear();
+    c.node_perm.reserve(N);
+    std::vector<int32_t> conn(int64_t(E) * NE);
+    for (int e = 0; e < E; e++) {
+        const int o = c.elem_perm[e];
+        for (int a = 0; a < NE; a++) {
+            const int n = mesh->conn[int64_t(NE) * o + a];
+            if (node_new[n] < 0) {
+                node_new[n] = int32_t(c.node_perm.size());
+                c.node_perm.push_back(n);
+            }
+            conn[int64_t(NE) * e + a] = node_new[n];
+        }
+    }
+    for (int n = 0; n < N; n++)
+        if (node_new[n] < 0) {
+            node_new[n] = int32_t(c.node_perm.size());
+            c.node_perm.push_back(n);
+        }
+
+    // ---- node -> element incidence (internal ids, ascending element)
+    std::vector<int32_t> deg(N, 0);
+    for (int64_t i = 0; i < int64_t(E) * NE; i++) deg[conn[i]]++;
+    std::vector<int32_t> ne_off(N + 1, 0);
+    for (int n = 0; n < N; n++) ne_off[n + 1] = ne_off[n] + deg[n];
+    std::vector<int32_t> ne_list(ne_off[N]);
+    {
+        std::vector<int32_t> fill(ne_off.begin(), ne_off.end() - 1);
+        for (int e = 0; e < E; e++)
+            for (int a = 0; a < NE; a++) ne_list[fill[conn[int64_t(NE) * e + a]]++] = e;
+    }
+    for (int e = 0; e < E; e++)
+        for (int a = 0; a < NE; a++)
+            for (int b = a + 1; b < NE; b++)
+                if (conn[int64_t(NE) * e + a] == conn[int64_t(NE) * e + b])
+                    return fail(DJ_ERR_BAD_MESH, "element " + std::to_string(c.elem_perm[e]) + " repeats a node");
+
+    // ---- grid size from occupancy, then balanced chunks
+    int bpc = 0;
+    size_t lds = 0;
+    DJ_HIP(occupancy(NE, c.model, c.prec, c.variant, &bpc, &lds));
+    hipDeviceProp_t prop;
+    DJ_HIP(hipGetDeviceProperties(&prop, c.device));
+    if (bpc < 1) return fail(DJ_ERR_UNSUPPORTED, "kernel variant does not fit on a compute unit");
+    const int gmax = bpc * prop.multiProcessorCount;
+    int C = c.cmax;
+    if (prm->chunk_elems > 0) C = std::min(prm->chunk_elems, c.cmax);
+    else C = std::min(c.cmax, std::max(64, (E + gmax - 1) / gmax));
+    int64_t nch = (E + C - 1) / C;
+    if (nch > gmax) nch = (nch + gmax - 1) / gmax * gmax;  // whole rounds of the resident grid
+    if (nch > E) nch = E;
+    c.chunk_elems = int((E + nch - 1) / nch);
+    c.grid = int(std::min<int64_t>(nch, gmax));
+
+    // ---- chunks, node copies, local CSR, shared-node lists
+    std::vector<ChunkDesc> chunks(nch);
+    std::vector<int32_t> lcsr_off(1, 0);
+    std::vector<uint16_t> lcsr_slot;
+    std::vector<uint32_t> flags;
+    std::vector<int32_t> copy_node;  // internal node id of each copy
+    std::vector<int32_t> node_copies_off(N + 1, 0);
+    std::vector<int32_t> local_of(N, -1), in_chunk(N, 0);
+    std::vector<std::vector<int32_t>> node_copies(N);
+    lcsr_slot.reserve(int64_t(E) * NE);
+    for (int64_t ch = 0; ch < nch; ch++) {
+        const int eb = int(ch * E / nch), ee = int((ch + 1) * E / nch);
+        if (ee - eb > c.cmax) return fail(DJ_ERR_ARG, "internal: chunk exceeds capacity");
+        std::vector<int32_t> touched;
+        for (int e = eb; e < ee; e++)
+            for (int a = 0; a < NE; a++) {
+                const int n = conn[int64_t(NE) * e + a];
+                if (in_chunk[n]++ == 0) touched.push_back(n);
+            }
+        std::vector<int32_t> interior, shared;
+        for (int n : touched) (in_chunk[n] == deg[n] ? interior : shared).push_back(n);
+        ChunkDesc d{};
+        d.elem_begin = eb;
+        d.elem_count = ee - eb;
+        d.copy_begin = int32_t(copy_node.size());
+        d.copy_count = int32_t(touched.size());
+        d.n_interior = int32_t(interior.size());
+        chunks[ch] = d;
+        std::vector<int32_t> order(interior);
+        order.insert(order.end(), shared.begin(), shared.end());
+        for (size_t i = 0; i < order.size(); i++) local_of[order[i]] = int32_t(i);
+        // slots of each local node, in (element, node) order
+        std::vector<int32_t> cnt(order.size(), 0);
+        for (int e = eb; e < ee; e++)
+            for (int a = 0; a < NE; a++) cnt[local_of[conn[int64_t(NE) * e + a]]]++;
+        const int64_t base = lcsr_slot.size();
+        std::vector<int64_t> pos(order.size());
+        int64_t acc = base;
+        for (size_t i = 0; i < order.size(); i++) {
+            pos[i] = acc;
+            acc += cnt[i];
+        }
+        lcsr_slot.resize(acc);
+        for (int e = eb; e < ee; e++)
+            for (int a = 0; a < NE; a++) {
+                const int li = local_of[conn[int64_t(NE) * e + a]];
+                lcsr_slot[pos[li]++] = uint16_t(a * c.cmax + (e - eb));
+            }
+        int64_t o = base;
+        for (size_t i = 0; i < order.size(); i++) {
+            o += cnt[i];
+            lcsr_off.push_back(int32_t(o));
+            const int n = order[i];
+            const int l = int32_t(copy_node.size());
+            copy_node.push_back(n);
+            flags.push_back(i >= interior.size() ? FLAG_SHARED : 0u);
+            node_copies[n].push_back(l);
+        }
+        for (int n : touched) {
+            in_chunk[n] = 0;
+            local_of[n] = -1;
+        }
+    }
+    const int64_t L = copy_node.size();
+    if (L >= (int64_t(1) << 31) || lcsr_slot.size() >= (size_t(1) << 31))
+        return fail(DJ_ERR_UNSUPPORTED, "mesh too large for 32-bit copy indices");
+    std::vector<int32_t> sh_beg(L, 0), sh_list, cnode(L);
+    int n_shared = 0;
+    for (int n = 0; n < N; n++) {
+        const auto &cp = node_copies[n];
+        if (cp.empty()) continue;
+        flags[cp[0]] |= FLAG_CANON;
+        if (cp.size() > 1) {
+            if (cp.size() > 255) return fail(DJ_ERR_UNSUPPORTED, "node shared by more than 255 chunks");
+            const int32_t b = int32_t(sh_list.size());
+            for (int32_t l : cp) {
+                sh_beg[l] = b;
+                flags[l] |= uint32_t(cp.size()) << FLAG_NCOPY_SHIFT;
+                n_shared++;
+            }
+            sh_list.insert(sh_list.end(), cp.begin(), cp.end());
+        }
+    }
+    for (int64_t l = 0; l < L; l++) cnode[l] = c.node_perm[copy_node[l]];
+    c.n_shared_copies = n_shared;
+    c.h_flags = flags;
+    c.h_copy_node = copy_node;
+
+    // ---- device buffers
+    const size_t ts = c.prec == DJ_FP32 ? 4 : 8;
+    const int NP = n_planes(NE, c.model);
+    c.topo.estride = (int64_t(E) + 63) / 64 * 64;
+    c.topo.n_chunks = int32_t(nch);
+    c.topo.n_copies = int32_t(L);
+    c.topo.cmax = c.cmax;
+    ChunkDesc *d_chunks;
+    int32_t *d_lcsr_off, *d_sh_beg, *d_sh_list, *d_cnode;
+    uint16_t *d_lcsr_slot;
+    uint32_t *d_flags;
+    DJ_HIP(upload(c, &d_chunks, chunks));
+    DJ_HIP(upload(c, &d_lcsr_off, lcsr_off));
+    DJ_HIP(upload(c, &d_lcsr_slot, lcsr_slot));
+    DJ_HIP(upload(c, &d_flags, flags));
+    DJ_HIP(upload(c, &d_sh_beg, sh_beg));
+    DJ_HIP(upload(c, &d_sh_list, sh_list));
+    DJ_HIP(upload(c, &d_cnode, cnode));
+    DJ_HIP(upload(c, &c.d_inode, copy_node));
+    DJ_HIP(upload(c, &c.d_elem_perm, c.elem_perm));
+    DJ_HIP(upload(c, &c.d_node_perm, c.node_perm));
+    c.topo.chunks = d_chunks;
+    c.topo.lcsr_off = d_lcsr_off;
+    c.topo.lcsr_slot = d_lcsr_slot;
+    c.topo.flags = d_flags;
+    c.topo.sh_beg = d_sh_beg;
+    c.topo.sh_list = d_sh_list;
+    c.topo.cnode = d_cnode;
+    unsigned char *p;
+    DJ_HIP(dalloc(c, &p, size_t(NP) * c.topo.estride * ts));
+    c.d_elem = p;
+    DJ_HIP(hipMemset(c.d_elem, 0, size_t(NP) * c.topo.estride * ts));
+    c.topo.elem = c.d_elem;
+    DJ_HIP(dalloc(c, &p, L * ts));
+    c.d_acoef = p;
+    c.topo.acoef = c.d_acoef;
+    for (int b = 0; b < 3; b++) {
+        DJ_HIP(dalloc(c, &p, 3 * L * ts));
+        c.d_ubuf[b] = p;
+    }
+    DJ_HIP(dalloc(c, &p, 6 * L * ts));
+    c.d_part = p;
+    DJ_HIP(dalloc(c, &c.d_bar, 2));
+    DJ_HIP(dalloc(c, &c.d_status, 8));
+    DJ_HIP(dalloc(c, &c.d_red, size_t(4) * c.grid + 2));
+    DJ_HIP(hipMemset(c.d_bar, 0, 2 * sizeof(uint32_t)));
+    DJ_HIP(dalloc(c, &c.d_V64, E));
+    DJ_HIP(dalloc(c, &c.d_jinv64, size_t(9) * E));
+    DJ_HIP(dalloc(c, &c.d_mass64, N));
+    DJ_HIP(hipHostMalloc(reinterpret_cast<void **>(&c.h_status), 8 * sizeof(int32_t), hipHostMallocDefault));
+    DJ_HIP(hipHostMalloc(reinterpret_cast<void **>(&c.h_res), sizeof(double), hipHostMallocDefault));
+
+    // ---- per-element inputs in internal order; pre-computation on the GPU (FP64)
+    std::vector<double> Xi(size_t(3) * N), Ei(E), nui(E), etai, fibi;
+    for (int n = 0; n < N; n++)
+        for (int k = 0; k < 3; k++) Xi[3 * size_t(n) + k] = mesh->X[3 * size_t(c.node_perm[n]) + k];
+    for (int e = 0; e < E; e++) {
+        const int o = c.elem_perm[e];
+        Ei[e] = mat->E ? mat->E[o] : mat->E_uniform;
+        nui[e] = mat->nu ? mat->nu[o] : mat->nu_uniform;
+        if (!(Ei[e] > 0) || !(nui[e] > -1.0 && nui[e] < 0.5))
+            return fail(DJ_ERR_ARG, "element " + std::to_string(o) + ": need E > 0 and -1 < nu < 0.5");
+    }
+    if (c.model == DJ_TI) {
+        etai.resize(E);
+        fibi.resize(size_t(3) * E);
+        for (int e = 0; e < E; e++) {
+            const int o = c.elem_perm[e];
+            etai[e] = mat->eta_ratio ? mat->eta_ratio[o] : mat->eta_ratio_uniform;
+            for (int k = 0; k < 3; k++) fibi[3 * size_t(e) + k] = mat->fibre[3 * size_t(o) + k];
+        }
+    }
+    TempBufs tb;
+    double *dX, *dE, *dnu, *deta = nullptr, *dfib = nullptr, *ddt;
+    int32_t *dconn, *dbad, *dneoff, *dnelist;
+    DJ_HIP(tb.up(&dX, Xi));
+    DJ_HIP(tb.up(&dconn, conn));
+    DJ_HIP(tb.up(&dE, Ei));
+    DJ_HIP(tb.up(&dnu, nui));
+    if (c.model == DJ_TI) {
+        DJ_HIP(tb.up(&deta, etai));
+        DJ_HIP(tb.up(&dfib, fibi));
+    }
+    const double inf = std::numeric_limits<double>::infinity();
+    DJ_HIP(tb.up(&ddt, std::vector<double>{inf}));
+    DJ_HIP(tb.up(&dbad, std::vector<int32_t>{0}));
+    DJ_HIP(tb.up(&dneoff, ne_off));
+    DJ_HIP(tb.up(&dnelist, ne_list));
+    DJ_HIP(launch_precompute(c, dX, dconn, dE, dnu, deta, dfib, ddt, dbad, nullptr));
+    int32_t bad = 0;
+    double dtc = 0;
+    DJ_HIP(hipMemcpy(&bad, dbad, sizeof(int32_t), hipMemcpyDeviceToHost));
+    DJ_HIP(hipMemcpy(&dtc, ddt, sizeof(double), hipMemcpyDeviceToHost));
+    if (bad) return fail(DJ_ERR_BAD_MESH, std::to_string(bad) + " element(s) with det(0J) <= 0 or zero fibre");
+    c.dt_crit = dtc;
+    const double fac = prm->dt_factor > 0 ? prm->dt_factor : 0.9;
+    c.dt = prm->dt > 0 ? prm->dt : fac * dtc;
+    if (c.dt > dtc && !prm->allow_unstable_dt)
+        return fail(DJ_ERR_UNSTABLE_DT, "dt " + std::to_string(c.dt) + " exceeds the critical step " + std::to_string(dtc));
+    DJ_HIP(launch_mass_acoef(c, dneoff, dnelist, nullptr));
+    std::vector<double> m(N);
+    DJ_HIP(hipMemcpy(m.data(), c.d_mass64, N * sizeof(double), hipMemcpyDeviceToHost));
+    c.mass_total = std::accumulate(m.begin(), m.end(), 0.0);
+    DJ_HIP(hipDeviceSynchronize());
+
+    // ---- traffic model of one fused step (bytes that must cross HBM once)
+    double eb = double(NP) * ts;                         // element planes
+    double slots = double(lcsr_slot.size()) * 2 + double(L + 1) * 4;
+    double copies = double(L) * (10.0 * ts + 4.0);       // u^n, u^{n-1}, u^{n+1}, A, flags
+    double sh = 0;
+    for (int64_t l = 0; l < L; l++)
+        if (flags[l] & FLAG_SHARED) {
+            const int k = (flags[l] >> FLAG_NCOPY_SHIFT) & 255;
+            sh += 3.0 * ts + k * (3.0 * ts + 4.0) + 4.0;  // write, read k partials + ids, sh_beg
+        }
+    c.bytes_per_step = eb * E + slots + copies + sh + double(nch) * sizeof(ChunkDesc);
+    c.elem_bytes = eb;
+    return DJ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *djtled_last_error(void) { return g_err.c_str(); }
+
+int djtled_precompute(const djtled_mesh *mesh, const djtled_material *mat, const djtled_params *prm,
+                      djtled_ctx **out) {
+    g_err.clear();
+    if (!mesh || !mat || !prm || !out) return fail(DJ_ERR_ARG, "null argument");
+    *out = nullptr;
+    if (mesh->n_nodes <= 0 || mesh->n_elems <= 0 || !mesh->X || !mesh->conn)
+        return fail(DJ_ERR_ARG, "empty mesh or null arrays");
+    if (mesh->elem_type != DJ_T4 && mesh->elem_type != DJ_H8) return fail(DJ_ERR_UNSUPPORTED, "elem_type must be 4 or 8");
+    if (mat->model != DJ_NH && mat->model != DJ_TI) return fail(DJ_ERR_UNSUPPORTED, "model must be DJ_NH or DJ_TI");
+    if (prm->precision != DJ_FP32 && prm->precision != DJ_FP64) return fail(DJ_ERR_UNSUPPORTED, "precision");
+    if (!(mat->rho > 0)) return fail(DJ_ERR_ARG, "rho must be > 0");
+    if (mat->model == DJ_TI && !mat->fibre) return fail(DJ_ERR_ARG, "DJ_TI needs fibre directions");
+    if (!(prm->alpha >= 0) || !(prm->dt >= 0)) return fail(DJ_ERR_ARG, "alpha and dt must be >= 0");
+    if (prm->variant < 0 || prm->variant >= int(variants(mesh->elem_type, prm->precision).size()))
+        return fail(DJ_ERR_ARG, "unknown kernel variant");
+    if (prm->chunk_elems < 0) return fail(DJ_ERR_ARG, "chunk_elems must be >= 0");
+    const int64_t nconn = int64_t(mesh->n_elems) * mesh->elem_type;
+    for (int64_t i = 0; i < nconn; i++)
+        if (mesh->conn[i] < 0 || mesh->conn[i] >= mesh->n_nodes)
+            return fail(DJ_ERR_BAD_MESH, "node index out of range in element " + std::to_string(i / mesh->elem_type));
+    for (int64_t i = 0; i < 3 * int64_t(mesh->n_nodes); i++)
+        if (!std::isfinite(mesh->X[i])) return fail(DJ_ERR_BAD_MESH, "non-finite coordinate");
+    Ctx *c = new Ctx();
+    int dev = prm->device;
+    if (dev < 0) {
+        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    }
+    c->device = dev;
+    if (hipSetDevice(dev) != hipSuccess) {
+        delete c;
+        return fail(DJ_ERR_HIP, "hipSetDevice failed");
+    }
+    int rc = build(*c, mesh, mat, prm);
+    if (rc != DJ_OK) {
+        std::string msg = g_err;
+        free_all(c);
+        g_err = msg;
+        return rc;
+    }
+    *out = reinterpret_cast<djtled_ctx *>(c);
+    return DJ_OK;
+}
+
+int djtled_destroy(djtled_ctx *ctx) {
+    if (!ctx) return fail(DJ_ERR_ARG, "null context");
+    free_all(reinterpret_cast<Ctx *>(ctx));
+    return DJ_OK;
+}
+
+int djtled_info(const djtled_ctx *ctx, djtled_info_t *o) {
+    if (!ctx || !o) return fail(DJ_ERR_ARG, "null argument");
+    const Ctx &c = *reinterpret_cast<const Ctx *>(ctx);
+    o->n_nodes = c.n_nodes;
+    o->n_elems = c.n_elems;
+    o->elem_type = c.ne;
+    o->model = c.model;
+    o->precision = c.prec;
+    o->dt = c.dt;
+    o->dt_crit = c.dt_crit;
+    o->alpha = c.alpha;
+    o->n_chunks = c.topo.n_chunks;
+    o->chunk_elems = c.chunk_elems;
+    o->n_copies = c.topo.n_copies;
+    o->n_shared_copies = c.n_shared_copies;
+    o->grid_blocks = c.grid;
+    o->block_threads = c.block;
+    o->variant = c.variant;
+    o->bytes_per_step = c.bytes_per_step;
+    o->elem_bytes = c.elem_bytes;
+    o->mass_total = c.mass_total;
+    return DJ_OK;
+}
+
+int djtled_forces(djtled_ctx *ctx, const void *u_dev, void *f_dev, void *stream) {
+    if (!ctx || !u_dev || !f_dev) return fail(DJ_ERR_ARG, "null argument");
+    Ctx &c = *reinterpret_cast<Ctx *>(ctx);
+    DJ_HIP(hipSetDevice(c.device));
+    DJ_HIP(launch_forces(c, u_dev, f_dev, static_cast<hipStream_t>(stream)));
+    return DJ_OK;
+}
+
+int djtled_loadset_create(djtled_ctx *ctx, const djtled_loads *ld, djtled_loadset **out) {
+    if (!ctx || !ld || !out) return fail(DJ_ERR_ARG, "null argument");
+    *out = nullptr;
+    Ctx &c = *reinterpret_cast<Ctx *>(ctx);
+    if (ld->n_bc < 0 || (ld->n_bc > 0 && (!ld->bc_node || !ld->bc_mask || !ld->bc_target)))
+        return fail(DJ_ERR_ARG, "bad boundary-condition arrays");
+    if (ld->ramp < DJ_RAMP_NONE || ld->ramp > DJ_RAMP_SMOOTH || !(ld->t_ramp >= 0))
+        return fail(DJ_ERR_ARG, "bad ramp");
+    std::vector<int32_t> bc_of(c.n_nodes, -1);
+    for (int j = 0; j < ld->n_bc; j++) {
+        const int n = ld->bc_node[j];
+        if (n < 0 || n >= c.n_nodes) return fail(DJ_ERR_ARG, "boundary-condition node out of range");
+        if (ld->bc_mask[j] & ~7) return fail(DJ_ERR_ARG, "boundary-condition mask must be within 0..7");
+        bc_of[n] = j;
+    }
+    const int64_t L = c.topo.n_copies;
+    std::vector<uint32_t> fl(c.h_flags);
+    std::vector<double> ru(3 * L, 0.0);
+    for (int64_t l = 0; l < L; l++) {
+        const int n = c.node_perm[c.h_copy_node[l]];
+        const int j = bc_of[n];
+        const uint32_t mask = j >= 0 ? uint32_t(ld->bc_mask[j]) : 0u;
+        if (mask == 0 && !ld->R) continue;
+        fl[l] |= mask | FLAG_RU;
+        for (int k = 0; k < 3; k++)
+            ru[k * L + l] = ((mask >> k) & 1u) ? ld->bc_target[3 * j + k] : (ld->R ? ld->R[3 * size_t(n) + k] : 0.0);
+    }
+    LoadSet *ls = new LoadSet();
+    ls->ctx = &c;
+    ls->ramp = ld->ramp;
+    ls->t_ramp = ld->t_ramp;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&ls->d_flags), L * sizeof(uint32_t));
+    const size_t ts = c.prec == DJ_FP32 ? 4 : 8;
+    if (e == hipSuccess) e = hipMalloc(&ls->d_ru, 3 * L * ts);
+    if (e == hipSuccess) e = hipMemcpy(ls->d_flags, fl.data(), L * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        if (c.prec == DJ_FP32) {
+            std::vector<float> rf(ru.begin(), ru.end());
+            e = hipMemcpy(ls->d_ru, rf.data(), rf.size() * 4, hipMemcpyHostToDevice);
+        } else {
+            e = hipMemcpy(ls->d_ru, ru.data(), ru.size() * 8, hipMemcpyHostToDevice);
+        }
+    }
+    if (e != hipSuccess) {
+        hipFree(ls->d_flags);
+        hipFree(ls->d_ru);
+        delete ls;
+        return fail(DJ_ERR_HIP, std::string("loadset upload: ") + hipGetErrorString(e));
+    }
+    c.loadsets.push_back(ls);
+    *out = reinterpret_cast<djtled_loadset *>(ls);
+    return DJ_OK;
+}
+
+int djtled_loadset_destroy(djtled_loadset *p) {
+    if (!p) return fail(DJ_ERR_ARG, "null load set");
+    LoadSet *ls = reinterpret_cast<LoadSet *>(p);
+    Ctx &c = *ls->ctx;
+    auto it = std::find(c.loadsets.begin(), c.loadsets.end(), static_cast<void *>(ls));
+    if (it == c.loadsets.end()) return fail(DJ_ERR_ARG, "unknown load set");
+    c.loadsets.erase(it);
+    hipDeviceSynchronize();
+    hipFree(ls->d_flags);
+    hipFree(ls->d_ru);
+    delete ls;
+    return DJ_OK;
+}
+
+int djtled_step(djtled_ctx *ctx, djtled_state *st, const djtled_loadset *lsp, int32_t n_steps,
+                const djtled_step_opts *opts, djtled_status *out, void *stream) {
+    if (!ctx || !st || !st->u_cur || !st->u_prev) return fail(DJ_ERR_ARG, "null argument");
+    if (n_steps < 0) return fail(DJ_ERR_ARG, "n_steps must be >= 0");
+    Ctx &c = *reinterpret_cast<Ctx *>(ctx);
+    const LoadSet *ls = reinterpret_cast<const LoadSet *>(lsp);
+    if (ls && ls->ctx != &c) return fail(DJ_ERR_ARG, "load set belongs to another context");
+    djtled_step_opts def{DJ_MODE_FIXED, 0.0, 1};
+    const djtled_step_opts &o = opts ? *opts : def;
+    if (o.mode != DJ_MODE_FIXED && o.mode != DJ_MODE_RELAX) return fail(DJ_ERR_ARG, "bad mode");
+    if (o.mode == DJ_MODE_RELAX && o.check_every < 1) return fail(DJ_ERR_ARG, "check_every must be >= 1");
+    DJ_HIP(hipSetDevice(c.device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    StepArgs a;
+    a.flags = ls ? ls->d_flags : c.topo.flags;
+    a.ru = ls ? ls->d_ru : nullptr;
+    a.has_loads = ls ? 1 : 0;
+    a.ramp = ls ? ls->ramp : DJ_RAMP_NONE;
+    a.t_ramp = ls ? ls->t_ramp : 0.0;
+    a.dt = c.dt;
+    a.bprime = (2.0 - c.alpha * c.dt) / (2.0 + c.alpha * c.dt);
+    a.step0 = st->step;
+    a.n_steps = n_steps;
+    a.relax = o.mode == DJ_MODE_RELAX;
+    a.tol = o.tol;
+    a.check_every = std::max(1, o.check_every);
+    a.cur0 = 0;
+    for (int b = 0; b < 3; b++) a.ubuf[b] = c.d_ubuf[b];
+    a.part = c.d_part;
+    a.u_out_cur = st->u_cur;
+    a.u_out_prev = st->u_prev;
+    a.bar = c.d_bar;
+    a.status = c.d_status;
+    a.red = c.d_red;
+    a.res_out = c.d_red + size_t(4) * c.grid;
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    DJ_HIP(hipMemcpyAsync(a.res_out, &nan, sizeof(double), hipMemcpyHostToDevice, s));
+    DJ_HIP(launch_step(c, a, st->u_cur, st->u_prev, s));
+    DJ_HIP(hipMemcpyAsync(c.h_status, c.d_status, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    DJ_HIP(hipMemcpyAsync(c.h_res, a.res_out, sizeof(double), hipMemcpyDeviceToHost, s));
+    DJ_HIP(hipStreamSynchronize(s));
+    djtled_status r;
+    r.code = c.h_status[4] ? DJ_ERR_BARRIER : c.h_status[0];
+    r.steps_done = c.h_status[1];
+    r.error_step = -1;
+    r.error_elem = -1;
+    r.residual = *c.h_res;
+    if (r.code == DJ_ERR_BARRIER) {
+        r.steps_done = 0;
+        g_err = "persistent kernel grid barrier timed out";
+    } else if (r.code == DJ_ERR_INVERTED || r.code == DJ_ERR_NONFINITE) {
+        r.error_step = st->step + c.h_status[3];
+        const int ie = c.h_status[2];
+        r.error_elem = (ie >= 0 && ie < c.n_elems) ? c.elem_perm[ie] : -1;
+        g_err = (r.code == DJ_ERR_INVERTED ? "element inverted (J <= 0) at step " : "non-finite value at step ") +
+                std::to_string(r.error_step);
+    }
+    st->step += r.steps_done;
+    if (out) *out = r;
+    return r.code;
+}
+
+int djtled_export_constants(djtled_ctx *ctx, double *V, double *dhdX, double *mass) {
+    if (!ctx) return fail(DJ_ERR_ARG, "null context");
+    Ctx &c = *reinterpret_cast<Ctx *>(ctx);
+    DJ_HIP(hipSetDevice(c.device));
+    double *dV = nullptr, *dB = nullptr, *dM = nullptr;
+    TempBufs tb;
+    if (V) DJ_HIP(tb.up(&dV, std::vector<double>(c.n_elems)));
+    if (dhdX) DJ_HIP(tb.up(&dB, std::vector<double>(size_t(c.n_elems) * 3 * c.ne)));
+    if (mass) DJ_HIP(tb.up(&dM, std::vector<double>(c.n_nodes)));
+    DJ_HIP(launch_export(c, dV, dB, dM, nullptr));
+    DJ_HIP(hipDeviceSynchronize());
+    if (V) DJ_HIP(hipMemcpy(V, dV, sizeof(double) * c.n_elems, hipMemcpyDeviceToHost));
+    if (dhdX) DJ_HIP(hipMemcpy(dhdX, dB, sizeof(double) * c.n_elems * 3 * c.ne, hipMemcpyDeviceToHost));
+    if (mass) DJ_HIP(hipMemcpy(mass, dM, sizeof(double) * c.n_nodes, hipMemcpyDeviceToHost));
+    return DJ_OK;
+}
+
+}  // extern "C"

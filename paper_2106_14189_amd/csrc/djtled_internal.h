@@ -1,0 +1,146 @@
+// Internal declarations shared by the host side (djtled_api.cpp) and the HIP
+// kernels (djtled_kernels.hip) of libdjtled.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/djtled.h"
+
+namespace dj {
+
+// Per-copy flag bits.  A "copy" is one chunk's private instance of a node:
+// every chunk keeps the state of all nodes its elements touch.
+enum : uint32_t {
+    FLAG_BC_MASK = 7u,     // bit k: component k prescribed
+    FLAG_SHARED = 8u,      // node has copies in more than one chunk
+    FLAG_CANON = 16u,      // the copy that writes the node to caller arrays
+    FLAG_RU = 32u,         // the loads hold a value for this node (R or BC target)
+    FLAG_NCOPY_SHIFT = 8u  // bits 8..15: number of copies of a shared node
+};
+
+// One chunk = a contiguous range of (reordered) elements processed by one
+// workgroup, plus its private node copies [copy_begin, copy_begin + copy_count);
+// the first n_interior copies are nodes touched by this chunk only.
+struct ChunkDesc {
+    int32_t elem_begin, elem_count, copy_begin, copy_count;
+    int32_t n_interior, pad0, pad1, pad2;
+};
+
+// Element-constant plane indices.  Each plane holds one scalar per element
+// (structure of arrays, element stride `estride`).
+template <int NE, int MODEL>
+struct Planes {
+    static constexpr int JINV = 0;                        // 0J^-1, row-major 3 x 3
+    static constexpr int MUV = 9;                         // mu * 0V
+    static constexpr int KAV = 10;                        // kappa * 0V
+    static constexpr int FIB = 11;                        // TI: unit fibre a (3)
+    static constexpr int ETAV = 14;                       // TI: eta_a * 0V
+    static constexpr int HG = (MODEL == DJ_TI) ? 15 : 11; // H8: g_alpha (4 x 3)
+    static constexpr int KHG = HG + 12;                   // H8: hourglass stiffness
+    static constexpr int N = (NE == 8) ? KHG + 1 : HG;    // number of planes
+};
+
+inline int n_planes(int ne, int model) {
+    int n = (model == DJ_TI) ? 15 : 11;
+    return ne == 8 ? n + 13 : n;
+}
+
+// Kernel variants (threads per workgroup, elements per thread); the chunk
+// capacity is block * ept elements.
+struct Variant {
+    int block, ept;
+};
+const std::vector<Variant> &variants(int ne, int prec);
+
+// Everything the kernels need, as device pointers.
+struct DevTopo {
+    const ChunkDesc *chunks = nullptr;
+    int32_t n_chunks = 0;
+    int32_t n_copies = 0;
+    int32_t cmax = 0;           // chunk capacity (slot stride in LDS)
+    const int32_t *lcsr_off = nullptr;   // n_copies + 1
+    const uint16_t *lcsr_slot = nullptr; // slot = a * cmax + local element
+    const uint32_t *flags = nullptr;
+    const int32_t *sh_beg = nullptr;     // shared copies: start in sh_list
+    const int32_t *sh_list = nullptr;    // copy ids of each shared node, ascending chunk
+    const int32_t *cnode = nullptr;      // caller node index of each copy
+    const void *elem = nullptr;          // element planes (context precision)
+    int64_t estride = 0;
+    const void *acoef = nullptr;         // per copy A_i = 2 dt^2 / ((2 + alpha dt) m_i)
+};
+
+struct StepArgs {
+    const uint32_t *flags = nullptr;  // per copy: topology flags | load bits
+    const void *ru = nullptr;   // loads: 3 planes over copies (BC target or R), or null
+    int32_t has_loads = 0;
+    int32_t ramp = DJ_RAMP_NONE;
+    double t_ramp = 0.0;
+    double dt = 0.0;
+    double bprime = 0.0;        // (2 - alpha dt) / (2 + alpha dt)
+    int64_t step0 = 0;
+    int32_t n_steps = 0;
+    int32_t relax = 0;
+    double tol = 0.0;
+    int32_t check_every = 1;
+    int32_t cur0 = 0;           // buffer index of u^n at entry (prev = cur0 + 2 mod 3)
+    void *ubuf[3] = {nullptr, nullptr, nullptr};  // each: 3 planes over copies
+    void *part = nullptr;       // partial forces: 2 parities x 3 planes x n_copies
+    void *u_out_cur = nullptr;  // caller arrays written at the end
+    void *u_out_prev = nullptr;
+    uint32_t *bar = nullptr;    // [0] arrival count, [1] generation
+    int32_t *status = nullptr;  // [0] code [1] steps done [2] error element (internal) [3] error step offset
+                                // [4] barrier abort [5..6] per-parity error words
+    double *red = nullptr;      // residual partials: 2 parities x grid x 2
+    double *res_out = nullptr;  // last residual
+};
+
+struct Ctx {
+    int device = 0;
+    int n_nodes = 0, n_elems = 0, ne = 4, model = DJ_NH, prec = DJ_FP32;
+    int variant = 0, block = 256, ept = 4, cmax = 1024, grid = 1, chunk_elems = 0;
+    double dt = 0, dt_crit = 0, alpha = 0, rho = 0, hg_kappa = 0.1, mass_total = 0;
+    int n_shared_copies = 0;
+    double bytes_per_step = 0, elem_bytes = 0;
+    std::vector<int32_t> elem_perm;  // internal element -> caller element
+    std::vector<int32_t> node_perm;  // internal node -> caller node
+    DevTopo topo;
+    // device allocations owned by the context
+    std::vector<void *> allocs;
+    void *d_elem = nullptr, *d_acoef = nullptr;
+    void *d_ubuf[3] = {nullptr, nullptr, nullptr};
+    void *d_part = nullptr;
+    uint32_t *d_bar = nullptr;
+    int32_t *d_status = nullptr;
+    double *d_red = nullptr;
+    double *d_V64 = nullptr, *d_jinv64 = nullptr, *d_mass64 = nullptr;
+    int32_t *d_elem_perm = nullptr, *d_node_perm = nullptr, *d_inode = nullptr;
+    int32_t *h_status = nullptr;     // pinned
+    double *h_res = nullptr;         // pinned
+    std::vector<uint32_t> h_flags;   // topology flags per copy
+    std::vector<int32_t> h_copy_node;  // internal node of each copy
+    std::vector<void *> loadsets;
+};
+
+struct LoadSet {
+    Ctx *ctx = nullptr;
+    uint32_t *d_flags = nullptr;     // topology flags | BC mask | FLAG_RU
+    void *d_ru = nullptr;
+    int ramp = DJ_RAMP_NONE;
+    double t_ramp = 0.0;
+};
+
+// ---- kernel launchers (djtled_kernels.hip) ----
+hipError_t occupancy(int ne, int model, int prec, int variant, int *blocks_per_cu, size_t *lds_bytes);
+hipError_t launch_precompute(Ctx &c, const double *dX, const int32_t *dconn, const double *dE, const double *dnu,
+                             const double *deta, const double *dfib, double *d_dtmin, int32_t *d_bad,
+                             hipStream_t s);
+hipError_t launch_mass_acoef(Ctx &c, const int32_t *d_ne_off, const int32_t *d_ne_list, hipStream_t s);
+hipError_t launch_forces(Ctx &c, const void *u, void *f, hipStream_t s);
+hipError_t launch_step(Ctx &c, const StepArgs &a, const void *u_cur_in, const void *u_prev_in, hipStream_t s);
+hipError_t launch_export(Ctx &c, double *d_V, double *d_dhdX, double *d_mass, hipStream_t s);
+
+}  // namespace dj

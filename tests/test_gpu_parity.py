@@ -1,0 +1,280 @@
+"""GPU parity of the HIP DJ-TLED path (through the C ABI) against the FP64 oracle.
+
+Tolerances (stated with each test):
+  * per-step nodal force, FP32: max|f_gpu - f_ora| / max|f_ora| <= 1e-5 on the
+    same input u (the state rounded to FP32); FP64: <= 1e-12 + 1e-15 / strain.
+    The second term is the oracle's own rounding: it evaluates Table 3
+    literally, whose O(1) terms cancel to an O(strain) force, so its relative
+    error is about 1e-16 / strain (1e-11 at strain 1e-5).
+  * after a full run, FP32: max|u_gpu - u_ora| / max|u_ora| <= 1e-4;
+    FP64: <= 1e-10
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2106_14189_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def S():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2106_14189_amd import solver
+    return solver
+
+
+def _case(elem, model, n=6, seed=1, permute=True, jitter=0.05):
+    rng = np.random.default_rng(seed)
+    mesh = W.cube_mesh(n, 0.1 / n, elem, jitter=jitter, seed=seed, permute=permute)
+    E = rng.uniform(2000.0, 6000.0, mesh.n_elems)
+    kw = {}
+    if model == W.TI:
+        v = rng.normal(size=(mesh.n_elems, 3))
+        kw = dict(eta_ratio=rng.uniform(2.0, 10.0, mesh.n_elems), fibre=v / np.linalg.norm(v, axis=1, keepdims=True))
+    return mesh, E, 0.45, kw, rng
+
+
+def _smooth_u(mesh, rng, amp):
+    X = mesh.X / 0.1
+    u = np.stack([np.sin(3 * X[:, 1] + 1) * X[:, 2], np.cos(2 * X[:, 0]) * X[:, 2] ** 2, -X[:, 2] * (1 + X[:, 0])], 1)
+    return amp * 0.1 * u + amp * 0.1 * 0.02 * rng.normal(size=u.shape)
+
+
+def _solver(S, mesh, E, nu, model, kw, prec, **extra):
+    return S.Solver(mesh.X, mesh.conn, E, nu, model=model, precision=prec, **kw, **extra)
+
+
+def _oracle(mesh, E, nu, model, kw):
+    return oracle.Oracle(mesh.X, mesh.conn, E, nu, model=model, rho=1000.0, **kw)
+
+
+@pytest.mark.parametrize("elem", [W.T4, W.H8])
+@pytest.mark.parametrize("model", [W.NH, W.TI])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("variant,chunk", [(0, 0), (0, 37), (1, 0), (2, 0), (3, 0)])
+def test_forces_parity(S, elem, model, prec, variant, chunk):
+    say(f"forces elem={elem} model={model} prec={prec} variant={variant} chunk={chunk}")
+    mesh, E, nu, kw, rng = _case(elem, model, n=7, seed=3 + variant)
+    sv = _solver(S, mesh, E, nu, model, kw, prec, variant=variant, chunk_elems=chunk)
+    ora = _oracle(mesh, E, nu, model, kw)
+    for amp in (1e-4, 0.05, 0.2):
+        u = _smooth_u(mesh, rng, amp)
+        if prec == "fp32":
+            u = u.astype(np.float32).astype(np.float64)
+        ut = torch.tensor(u, dtype=sv.dtype, device="cuda")
+        f = sv.forces(ut)
+        torch.cuda.synchronize()
+        fg = f.double().cpu().numpy()
+        fo = ora.forces(u)
+        err = np.abs(fg - fo).max() / np.abs(fo).max()
+        tol = 1e-5 if prec == "fp32" else 1e-12 + 1e-15 / amp  # strain ~ amp for this field
+        say(f"  amp={amp} rel max-norm error {err:.3e} (tol {tol})")
+        assert err <= tol
+
+
+@pytest.mark.parametrize("elem", [W.T4, W.H8])
+def test_export_constants_match_oracle(S, elem):
+    mesh, E, nu, kw, rng = _case(elem, W.NH, n=5, seed=9)
+    sv = _solver(S, mesh, E, nu, W.NH, kw, "fp32")
+    ora = _oracle(mesh, E, nu, W.NH, kw)
+    V, B, m = sv.export_constants()
+    np.testing.assert_allclose(m, ora.mass(), rtol=1e-12)
+    for e in range(0, mesh.n_elems, 17):
+        d = ora.element_constants(e)
+        np.testing.assert_allclose(V[e], d["V"], rtol=1e-12)
+        np.testing.assert_allclose(B[e], d["dhdX"], rtol=1e-10, atol=1e-10 * np.abs(d["dhdX"]).max())
+    info = sv.info()
+    np.testing.assert_allclose(info["dt_crit"], ora.dt_crit, rtol=1e-12)
+    np.testing.assert_allclose(info["dt"], 0.9 * ora.dt_crit, rtol=1e-12)
+
+
+def _run_oracle(ora, wl, n_steps, dt, alpha):
+    u = np.zeros((ora.n_nodes, 3))
+    up = np.zeros_like(u)
+    ld = wl.loads
+    rc, done, _ = ora.run(u, up, n_steps, dt, alpha, ld.bc_node, ld.bc_mask, ld.bc_target, ramp=ld.ramp,
+                          t_ramp=ld.t_ramp)
+    assert rc == 0 and done == n_steps
+    return u, up
+
+
+def _run_gpu(sv, wl, n_steps, chunks=(None,)):
+    ld = wl.loads
+    ls = sv.loadset(ld.bc_node, ld.bc_mask, ld.bc_target, ld.ramp, ld.t_ramp)
+    u, up = sv.zeros(), sv.zeros()
+    step = 0
+    parts = [n_steps] if chunks == (None,) else list(chunks)
+    for k in parts:
+        st, step = sv.step(u, up, k, ls, step0=step)
+        assert st.code == 0 and st.steps_done == k, st
+    torch.cuda.synchronize()
+    return u, up
+
+
+def test_full_run_config0_fp64(S):
+    """Config 0 in full: 6000 T4, FP64, 2000 steps; GPU vs oracle <= 1e-10."""
+    wl = W.config0()
+    mesh, mat = wl.mesh, wl.material
+    ora = oracle.Oracle(mesh.X, mesh.conn, mat.E, mat.nu, rho=mat.rho)
+    dt = 0.9 * ora.dt_crit
+    wl.loads.t_ramp = wl.n_steps * dt
+    say("config0: oracle run")
+    uo, _ = _run_oracle(ora, wl, wl.n_steps, dt, wl.alpha)
+    sv = S.from_workload(wl)
+    assert abs(sv.info()["dt"] - dt) <= 1e-15 * dt
+    say("config0: gpu run")
+    ug, _ = _run_gpu(sv, wl, wl.n_steps)
+    err = np.abs(ug.cpu().numpy() - uo).max() / np.abs(uo).max()
+    say(f"config0 rel max displacement error {err:.3e}")
+    assert err <= 1e-10
+    assert abs(uo[:, 2].min() + 0.02) < 1e-12  # the top face reached -20 %
+
+
+@pytest.mark.parametrize("elem", [W.T4, W.H8])
+@pytest.mark.parametrize("model", [W.NH, W.TI])
+def test_full_run_fp32_small(S, elem, model):
+    """FP32 run on a 10^3 cube (permuted, per-element E): <= 1e-4 after 600 steps."""
+    mesh, E, nu, kw, rng = _case(elem, model, n=10, seed=21)
+    n_steps = 600
+    ora = _oracle(mesh, E, nu, model, kw)
+    dt = 0.9 * ora.dt_crit
+    loads = W.compression_loads(mesh, -0.2, W.RAMP_SMOOTH, n_steps * dt)
+    wl = W.Workload("small", mesh, W.Material(model, E, np.full(mesh.n_elems, nu)), loads, 0.9, alpha=37.0)
+    say(f"fp32 full run elem={elem} model={model}: oracle")
+    uo, _ = _run_oracle(ora, wl, n_steps, dt, wl.alpha)
+    sv = _solver(S, mesh, E, nu, model, kw, "fp32", alpha=wl.alpha)
+    say("  gpu")
+    ug, _ = _run_gpu(sv, wl, n_steps)
+    err = np.abs(ug.double().cpu().numpy() - uo).max() / np.abs(uo).max()
+    say(f"  rel max displacement error {err:.3e}")
+    assert err <= 1e-4
+
+
+def test_determinism_and_launch_splitting(S):
+    """Bitwise: a repeated run, and n steps in one launch == the same steps over 4 launches."""
+    mesh, E, nu, kw, rng = _case(W.T4, W.NH, n=12, seed=5)
+    sv = _solver(S, mesh, E, nu, W.NH, kw, "fp32", alpha=30.0)
+    loads = W.compression_loads(mesh, -0.1, W.RAMP_SMOOTH, 300 * sv.info()["dt"])
+    wl = W.Workload("det", mesh, None, loads)
+    a, ap = _run_gpu(sv, wl, 300)
+    b, bp = _run_gpu(sv, wl, 300)
+    c, cp = _run_gpu(sv, wl, 300, chunks=(1, 99, 100, 100))
+    assert torch.equal(a, b) and torch.equal(ap, bp)
+    assert torch.equal(a, c) and torch.equal(ap, cp)
+
+
+def test_free_body_damped_recurrence(S):
+    """Uniform body force R = m g, no BCs: every node follows the closed form of
+    the damped central-difference recurrence (FP64)."""
+    mesh, E, nu, kw, rng = _case(W.H8, W.NH, n=4, seed=2, permute=True)
+    dt, alpha, n = 1e-3, 20.0, 300
+    sv = _solver(S, mesh, E, nu, W.NH, kw, "fp64", dt=dt, alpha=alpha, allow_unstable_dt=True)
+    _, _, m = sv.export_constants()
+    g = np.array([0.0, 0.0, -9.81])
+    ls = sv.loadset(R=m[:, None] * g[None, :])
+    u, up = sv.zeros(), sv.zeros()
+    st, _ = sv.step(u, up, n, ls)
+    assert st.code == 0
+    beta = g[2] * dt / alpha
+    r = (1 - alpha * dt / 2) / (1 + alpha * dt / 2)
+    exact = beta * n - beta * r * (1 - r ** n) / (1 - r)
+    uz = u[:, 2].cpu().numpy()
+    np.testing.assert_allclose(uz, exact, rtol=1e-10)
+
+
+def test_error_inverted_element(S):
+    mesh = W.cube_mesh(2, 0.01, W.T4, jitter=0.0)
+    sv = S.Solver(mesh.X, mesh.conn, 3000.0, 0.45, precision="fp64", alpha=0.0)
+    # crush: the top face pushed through the bottom within a few steps
+    top = mesh.top
+    ls = sv.loadset(top, np.full(len(top), 4), np.tile([0, 0, -0.05], (len(top), 1)), ramp=W.RAMP_NONE)
+    u, up = sv.zeros(), sv.zeros()
+    u0 = u.clone()
+    st, step = sv.step(u, up, 50, ls, raise_on_error=False)
+    assert st.code == -3 and st.name == "DJ_ERR_INVERTED", st
+    assert st.error_step == 1 and st.steps_done == 1 and 0 <= st.error_elem < mesh.n_elems
+    # the state is the last completed step (step 1: the top face prescribed)
+    assert torch.all(u[top, 2] == -0.05) and torch.equal(up, u0)
+
+
+def test_error_nonfinite_and_relaunch(S):
+    mesh = W.cube_mesh(3, 0.01, W.H8, jitter=0.05, seed=1)
+    sv = S.Solver(mesh.X, mesh.conn, 3000.0, 0.45, precision="fp32", alpha=5.0)
+    u, up = sv.zeros(), sv.zeros()
+    u[5, 1] = float("nan")
+    st, _ = sv.step(u, up, 10, None, raise_on_error=False)
+    assert st.code == -4 and st.error_step == 0
+    # the context stays usable after an error
+    u2, up2 = sv.zeros(), sv.zeros()
+    st, _ = sv.step(u2, up2, 10, None)
+    assert st.code == 0 and torch.count_nonzero(u2) == 0
+
+
+def test_error_unstable_dt_and_bad_mesh(S):
+    from paper_2106_14189_amd import _lib as L
+    mesh = W.cube_mesh(2, 0.01, W.T4, jitter=0.0)
+    with pytest.raises(L.DJError) as ei:
+        S.Solver(mesh.X, mesh.conn, 3000.0, 0.45, dt=1.0)
+    assert ei.value.code == L.DJ_ERR_UNSTABLE_DT
+    conn = mesh.conn.copy()
+    conn[3, [1, 2]] = conn[3, [2, 1]]  # negative orientation
+    with pytest.raises(L.DJError) as ei:
+        S.Solver(mesh.X, conn, 3000.0, 0.45)
+    assert ei.value.code == L.DJ_ERR_BAD_MESH
+
+
+def test_dynamic_relaxation_matches_oracle(S):
+    """RELAX mode: the GPU and the oracle converge to the same equilibrium."""
+    mesh = W.cube_mesh(4, 0.01, W.T4, jitter=0.08, seed=4, permute=True)
+    ora = oracle.Oracle(mesh.X, mesh.conn, 3000.0, 0.45)
+    dt, alpha = 0.9 * ora.dt_crit, 30.0
+    loads = W.compression_loads(mesh, -0.15, W.RAMP_SMOOTH, 300 * dt)
+    uo, upo = np.zeros((mesh.n_nodes, 3)), np.zeros((mesh.n_nodes, 3))
+    rc, done_o, res_o = ora.run(uo, upo, 100000, dt, alpha, loads.bc_node, loads.bc_mask, loads.bc_target,
+                                ramp=loads.ramp, t_ramp=loads.t_ramp, relax=True, tol=1e-8, check_every=20)
+    assert rc == 1
+    sv = S.Solver(mesh.X, mesh.conn, 3000.0, 0.45, precision="fp64", alpha=alpha)
+    ls = sv.loadset(loads.bc_node, loads.bc_mask, loads.bc_target, loads.ramp, loads.t_ramp)
+    u, up = sv.zeros(), sv.zeros()
+    st, _ = sv.step(u, up, 100000, ls, relax=True, tol=1e-8, check_every=20)
+    say(f"DR: oracle {done_o} steps r={res_o:.2e}; gpu {st.steps_done} steps r={st.residual:.2e}")
+    assert st.code == 1 and st.residual <= 1e-8
+    assert abs(st.steps_done - done_o) <= 20
+    err = np.abs(u.cpu().numpy() - uo).max() / np.abs(uo).max()
+    assert err <= 1e-7
+
+
+@pytest.mark.parametrize("elem", [W.T4, W.H8])
+def test_full_size_config1_forces_and_steps(S, elem):
+    """Config 1 at full size (1,572,864 T4 / 262,144 H8), in the launch
+    configuration the benchmark times: 100 fused steps, then the force at the
+    reached state against the oracle (<= 1e-5), and determinism of the run."""
+    wl = W.config1(elem)
+    mesh, mat = wl.mesh, wl.material
+    say(f"config1 elem={elem}: precompute")
+    sv = S.from_workload(wl)
+    dt = sv.info()["dt"]
+    wl.loads.t_ramp = wl.n_steps * dt
+    say("  gpu 100 steps x2")
+    a, ap = _run_gpu(sv, wl, 100)
+    b, bp = _run_gpu(sv, wl, 100)
+    assert torch.equal(a, b) and torch.equal(ap, bp)
+    u = a.double().cpu().numpy()
+    assert np.abs(u).max() > 0
+    say("  oracle forces at the reached state")
+    ora = oracle.Oracle(mesh.X, mesh.conn, mat.E, mat.nu, rho=mat.rho)
+    fo = ora.forces(u)
+    fg = sv.forces(a).double().cpu().numpy()
+    err = np.abs(fg - fo).max() / np.abs(fo).max()
+    say(f"  rel max-norm force error {err:.3e}")
+    assert err <= 1e-5
