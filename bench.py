@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""DJ-TLED time-step benchmark on one MI355X.
+
+Workload (synthetic, seeded): a 0.1 m cube of 64^3 voxels, meshed both as
+1,572,864 linear tetrahedra and as 262,144 one-point hexahedra with hourglass
+control (274,625 nodes each), neo-Hookean with E ~ U[2, 6] kPa per element,
+nu = 0.45, rho = 1000, jittered +-5 %, nodes and elements randomly permuted;
+bottom face fixed, top face compressed to -20 % with a smooth ramp over 1000
+steps; dt = 0.9 x the critical step; FP32.
+
+One benchmark step advances BOTH meshes by one explicit time step (element
+forces -> node reduction -> central difference with damping -> BCs).  The
+timed region runs K steps of each mesh as one persistent kernel launch per
+mesh, with the inputs resident in HBM.
+
+Prints one JSON line (see the keys below).  --gpus N > 1 is not supported:
+this build runs on a single GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2106_14189_amd", "csrc", "djtled_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "djtled_step_cube64_t4_traffic.json")
+METRIC = "DJ-TLED element-steps/sec + HBM GB/s; warm-start vs plain time-to-1e-3"
+
+
+def _src_sha() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+
+
+def _traffic(bytes_scale_steps: int):
+    """HBM bytes per launch from committed rocprofv3 PMC counters (FETCH_SIZE +
+    WRITE_SIZE, calibrated on a plain copy), or None if the kernel changed
+    since they were taken."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != _src_sha():
+        return None
+    return (t["fetch_bytes_per_step"] + t["write_bytes_per_step"]) * bytes_scale_steps
+
+
+def cpu_baseline(wls, n_steps: int) -> dict:
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
+    import numpy as np
+
+    import oracle
+
+    total_es, total_t = 0, 0.0
+    for wl in wls:
+        m, mat, ld = wl.mesh, wl.material, wl.loads
+        ora = oracle.Oracle(m.X, m.conn, mat.E, mat.nu, rho=mat.rho, hg_kappa=mat.hg_kappa)
+        dt = 0.9 * ora.dt_crit
+        u, up = np.zeros((m.n_nodes, 3)), np.zeros((m.n_nodes, 3))
+        t0 = time.perf_counter()
+        rc, done, _ = ora.run(u, up, n_steps, dt, wl.alpha, ld.bc_node, ld.bc_mask, ld.bc_target, ramp=ld.ramp,
+                              t_ramp=1000 * dt)
+        total_t += time.perf_counter() - t0
+        assert rc == 0 and done == n_steps
+        total_es += m.n_elems * n_steps
+    return {"value": total_es / total_t, "unit": "element-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_steps} steps of each mesh from rest (single-threaded FP64 C oracle, gcc -O2)",
+            "seconds": round(total_t, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--cpu-steps", type=int, default=15, help="oracle steps per mesh for cpu_baseline (0: skip)")
+    ap.add_argument("--variant", type=int, default=-1, help="kernel variant (-1: per-mesh default)")
+    ap.add_argument("--mesh", choices=["both", "t4", "h8"], default="both")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: --gpus {args.gpus} requested; this DJ-TLED build runs on one GPU only "
+              f"(multi-GPU sharding is a design note, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2106_14189_amd import solver
+    from paper_2106_14189_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    K, Wm = args.steps, args.warmup
+    elems = {"both": [W.T4, W.H8], "t4": [W.T4], "h8": [W.H8]}[args.mesh]
+    runs = []
+    for elem in elems:
+        wl = W.config1(elem)
+        kw = {} if args.variant < 0 else {"variant": args.variant}
+        sv = solver.from_workload(wl, **kw)
+        info = sv.info()
+        ld = wl.loads
+        ls = sv.loadset(ld.bc_node, ld.bc_mask, ld.bc_target, ld.ramp, 1000 * info["dt"])
+        u, up = sv.zeros(), sv.zeros()
+        st, step = sv.step(u, up, Wm, ls)
+        assert st.code == 0, st
+        runs.append(dict(elem=elem, wl=wl, sv=sv, info=info, ls=ls, u=u, up=up, step=step))
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    for r in runs:
+        st, r["step"] = r["sv"].step(r["u"], r["up"], K, r["ls"], step0=r["step"])
+        r["status"] = st
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for r in runs:
+        assert r["status"].code == 0 and r["status"].steps_done == K, r["status"]
+        assert bool(torch.isfinite(r["u"]).all())
+
+    tot_elems = sum(r["info"]["n_elems"] for r in runs)
+    value = tot_elems * K / wall
+    dom = max(runs, key=lambda r: r["status"].kernel_ms)
+    k_s = dom["status"].kernel_ms / 1000.0
+    achieved = dom["info"]["bytes_per_step"] * K / k_s / 1e9
+    traffic = _traffic(K) if dom["elem"] == W.T4 else None
+    cfg = {"workload": "cube64_" + "+".join("t4" if r["elem"] == W.T4 else "h8" for r in runs) + "_nh_fp32_compression",
+           "nodes": runs[0]["info"]["n_nodes"], "precision": "fp32", "steps_timed": K}
+    for r in runs:
+        tag = "t4" if r["elem"] == W.T4 else "h8"
+        i = r["info"]
+        km = r["status"].kernel_ms
+        cfg[f"{tag}_elems"] = i["n_elems"]
+        cfg[f"{tag}_kernel_ms_per_step"] = km / K
+        cfg[f"{tag}_element_steps_per_s"] = i["n_elems"] * K / (km / 1000.0)
+        cfg[f"{tag}_bytes_per_step"] = i["bytes_per_step"]
+        cfg[f"{tag}_bytes_per_element_step"] = i["bytes_per_step"] / i["n_elems"]
+        cfg[f"{tag}_effective_GBps"] = i["bytes_per_step"] * K / (km / 1000.0) / 1e9
+        cfg[f"{tag}_dt"] = i["dt"]
+        cfg[f"{tag}_grid"] = i["grid_blocks"]
+        cfg[f"{tag}_chunks"] = i["n_chunks"]
+        cfg[f"{tag}_chunk_elems"] = i["chunk_elems"]
+        cfg[f"{tag}_variant"] = i["variant"]
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "element-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": wall / K * 1000.0,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": cfg,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "kernel": "k_step (persistent fused DJ-TLED step), " + ("T4" if dom["elem"] == W.T4 else "H8"),
+                     "bytes_per_launch": dom["info"]["bytes_per_step"] * K,
+                     "launch_ms": dom["status"].kernel_ms},
+    }
+    if args.cpu_steps > 0:
+        out["cpu_baseline"] = cpu_baseline([r["wl"] for r in runs], args.cpu_steps)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -164,6 +164,7 @@ typedef struct {
     int64_t error_step;       /* global step of a run-time error, else -1 */
     int32_t error_elem;       /* caller element index of DJ_ERR_INVERTED, else -1 */
     double residual;          /* last residual evaluated (RELAX), else NaN */
+    double kernel_ms;         /* device time of the persistent step kernel (HIP events on `stream`) */
 } djtled_status;
 
 /*

@@ -73,7 +73,7 @@ class djtled_step_opts(ctypes.Structure):
 
 class djtled_status(ctypes.Structure):
     _fields_ = [("code", ctypes.c_int32), ("steps_done", ctypes.c_int32), ("error_step", ctypes.c_int64),
-                ("error_elem", ctypes.c_int32), ("residual", ctypes.c_double)]
+                ("error_elem", ctypes.c_int32), ("residual", ctypes.c_double), ("kernel_ms", ctypes.c_double)]
 
 
 EXPORTS = {

@@ -62,6 +62,8 @@ void free_all(Ctx *c) {
         delete ls;
     }
     for (void *p : c->allocs) hipFree(p);
+    if (c->ev0) hipEventDestroy(c->ev0);
+    if (c->ev1) hipEventDestroy(c->ev1);
     if (c->h_status) hipHostFree(c->h_status);
     if (c->h_res) hipHostFree(c->h_res);
     delete c;
@@ -330,6 +332,8 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     DJ_HIP(dalloc(c, &c.d_mass64, N));
     DJ_HIP(hipHostMalloc(reinterpret_cast<void **>(&c.h_status), 8 * sizeof(int32_t), hipHostMallocDefault));
     DJ_HIP(hipHostMalloc(reinterpret_cast<void **>(&c.h_res), sizeof(double), hipHostMallocDefault));
+    DJ_HIP(hipEventCreate(&c.ev0));
+    DJ_HIP(hipEventCreate(&c.ev1));
 
     // ---- per-element inputs in internal order; pre-computation on the GPU (FP64)
     std::vector<double> Xi(size_t(3) * N), Ei(E), nui(E), etai, fibi;
@@ -591,7 +595,7 @@ int djtled_step(djtled_ctx *ctx, djtled_state *st, const djtled_loadset *lsp, in
     a.res_out = c.d_red + size_t(4) * c.grid;
     const double nan = std::numeric_limits<double>::quiet_NaN();
     DJ_HIP(hipMemcpyAsync(a.res_out, &nan, sizeof(double), hipMemcpyHostToDevice, s));
-    DJ_HIP(launch_step(c, a, st->u_cur, st->u_prev, s));
+    DJ_HIP(launch_step(c, a, st->u_cur, st->u_prev, s, c.ev0, c.ev1));
     DJ_HIP(hipMemcpyAsync(c.h_status, c.d_status, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     DJ_HIP(hipMemcpyAsync(c.h_res, a.res_out, sizeof(double), hipMemcpyDeviceToHost, s));
     DJ_HIP(hipStreamSynchronize(s));
@@ -601,6 +605,8 @@ int djtled_step(djtled_ctx *ctx, djtled_state *st, const djtled_loadset *lsp, in
     r.error_step = -1;
     r.error_elem = -1;
     r.residual = *c.h_res;
+    float ms = 0.0f;
+    r.kernel_ms = hipEventElapsedTime(&ms, c.ev0, c.ev1) == hipSuccess ? double(ms) : -1.0;
     if (r.code == DJ_ERR_BARRIER) {
         r.steps_done = 0;
         g_err = "persistent kernel grid barrier timed out";

@@ -120,6 +120,7 @@ struct Ctx {
     int32_t *d_elem_perm = nullptr, *d_node_perm = nullptr, *d_inode = nullptr;
     int32_t *h_status = nullptr;     // pinned
     double *h_res = nullptr;         // pinned
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // brackets the persistent kernel
     std::vector<uint32_t> h_flags;   // topology flags per copy
     std::vector<int32_t> h_copy_node;  // internal node of each copy
     std::vector<void *> loadsets;
@@ -140,7 +141,8 @@ hipError_t launch_precompute(Ctx &c, const double *dX, const int32_t *dconn, con
                              hipStream_t s);
 hipError_t launch_mass_acoef(Ctx &c, const int32_t *d_ne_off, const int32_t *d_ne_list, hipStream_t s);
 hipError_t launch_forces(Ctx &c, const void *u, void *f, hipStream_t s);
-hipError_t launch_step(Ctx &c, const StepArgs &a, const void *u_cur_in, const void *u_prev_in, hipStream_t s);
+hipError_t launch_step(Ctx &c, const StepArgs &a, const void *u_cur_in, const void *u_prev_in, hipStream_t s,
+                       hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_export(Ctx &c, double *d_V, double *d_dhdX, double *d_mass, hipStream_t s);
 
 }  // namespace dj

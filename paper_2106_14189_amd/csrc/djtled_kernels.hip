@@ -613,9 +613,13 @@ __global__ void __launch_bounds__(BLOCK) k_step(DevTopo tp, StepArgs a) {
                 break;  // u^n is the converged state; u^{n+1} is discarded
             }
         }
+        // shared copies written above by one thread are read by another in the
+        // next step's scatter (and in the final write-out)
+        __syncthreads();
         cur = nxt;
         done = s + 1;
     }
+    __syncthreads();
     if (code == DJ_ERR_BARRIER) return;  // status[4] is set; the caller's state is left untouched
     if (code != DJ_OK && code != DJ_CONVERGED) done = s;  // the failing step is not completed
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -853,7 +857,8 @@ struct Inst {
                            c.topo, sp);
         return hipGetLastError();
     }
-    static hipError_t step(Ctx &c, const StepArgs &a, const void *u_cur_in, const void *u_prev_in, hipStream_t s) {
+    static hipError_t step(Ctx &c, const StepArgs &a, const void *u_cur_in, const void *u_prev_in, hipStream_t s,
+                           hipEvent_t ev0, hipEvent_t ev1) {
         const int L = c.topo.n_copies, B = 256;
         hipLaunchKernelGGL(k_reset_sync, dim3(1), dim3(64), 0, s, c.d_bar, c.d_status);
         hipError_t e = hipGetLastError();
@@ -870,8 +875,12 @@ struct Inst {
         e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_step<T, NE, MODEL, BLOCK, EPT>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(C::LDS));
         if (e != hipSuccess) return e;
-        return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_step<T, NE, MODEL, BLOCK, EPT>),
-                                          dim3(c.grid), dim3(BLOCK), args, C::LDS, s);
+        if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
+        e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_step<T, NE, MODEL, BLOCK, EPT>),
+                                       dim3(c.grid), dim3(BLOCK), args, C::LDS, s);
+        if (e != hipSuccess) return e;
+        if (ev1) e = hipEventRecord(ev1, s);
+        return e;
     }
 };
 
@@ -915,9 +924,10 @@ hipError_t launch_forces(Ctx &c, const void *u, void *f, hipStream_t s) {
     return dispatch(c.prec, c.ne, c.model, c.variant, [&](auto inst) { return decltype(inst)::forces(c, u, f, s); });
 }
 
-hipError_t launch_step(Ctx &c, const StepArgs &a, const void *u_cur_in, const void *u_prev_in, hipStream_t s) {
+hipError_t launch_step(Ctx &c, const StepArgs &a, const void *u_cur_in, const void *u_prev_in, hipStream_t s,
+                       hipEvent_t ev0, hipEvent_t ev1) {
     return dispatch(c.prec, c.ne, c.model, c.variant,
-                    [&](auto inst) { return decltype(inst)::step(c, a, u_cur_in, u_prev_in, s); });
+                    [&](auto inst) { return decltype(inst)::step(c, a, u_cur_in, u_prev_in, s, ev0, ev1); });
 }
 
 template <typename T>

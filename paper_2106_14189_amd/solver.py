@@ -36,6 +36,7 @@ class Status:
     error_step: int
     error_elem: int
     residual: float
+    kernel_ms: float
 
     @property
     def name(self) -> str:
@@ -149,7 +150,7 @@ class Solver:
         out = L.djtled_status()
         code = L.lib.djtled_step(self.handle, ctypes.byref(st), loads.handle if loads else None, int(n_steps),
                                  ctypes.byref(opts), ctypes.byref(out), _stream(stream))
-        status = Status(out.code, out.steps_done, out.error_step, out.error_elem, out.residual)
+        status = Status(out.code, out.steps_done, out.error_step, out.error_elem, out.residual, out.kernel_ms)
         if code < 0 and raise_on_error:
             raise L.DJError(code, "djtled_step")
         return status, st.step
