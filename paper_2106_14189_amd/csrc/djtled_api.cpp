@@ -323,10 +323,10 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     }
     DJ_HIP(dalloc(c, &p, 6 * L * ts));
     c.d_part = p;
-    DJ_HIP(dalloc(c, &c.d_bar, 2));
+    DJ_HIP(dalloc(c, &c.d_bar, size_t(c.grid + 16) * 32));  // barrier flags, one 128-B line each
     DJ_HIP(dalloc(c, &c.d_status, 8));
     DJ_HIP(dalloc(c, &c.d_red, size_t(4) * c.grid + 2));
-    DJ_HIP(hipMemset(c.d_bar, 0, 2 * sizeof(uint32_t)));
+    DJ_HIP(hipMemset(c.d_bar, 0, size_t(c.grid + 16) * 32 * sizeof(uint32_t)));
     DJ_HIP(dalloc(c, &c.d_V64, E));
     DJ_HIP(dalloc(c, &c.d_jinv64, size_t(9) * E));
     DJ_HIP(dalloc(c, &c.d_mass64, N));

@@ -91,7 +91,7 @@ struct StepArgs {
     void *part = nullptr;       // partial forces: 2 parities x 3 planes x n_copies
     void *u_out_cur = nullptr;  // caller arrays written at the end
     void *u_out_prev = nullptr;
-    uint32_t *bar = nullptr;    // [0] arrival count, [1] generation
+    uint32_t *bar = nullptr;    // barrier flags: (grid + 16) x 32 uint32
     int32_t *status = nullptr;  // [0] code [1] steps done [2] error element (internal) [3] error step offset
                                 // [4] barrier abort [5..6] per-parity error words
     double *red = nullptr;      // residual partials: 2 parities x grid x 2

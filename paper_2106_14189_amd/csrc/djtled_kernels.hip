@@ -71,6 +71,18 @@ __device__ __forceinline__ double ramp_value(int ramp, double t, double t_ramp) 
     return tau * tau * tau * (10.0 - 15.0 * tau + 6.0 * tau * tau);
 }
 
+// Device-scope relaxed store / load: write through to, and read from, the
+// coherence point shared by all XCDs (used for every value one workgroup
+// publishes to another).
+template <typename T>
+__device__ __forceinline__ void st_dev(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T ld_dev(const T *p) {
+    return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ---------------------------------------------------------------------------
 // element force (register-resident).  cst: the element's planes.  u: nodal
 // displacements.  F: nodal forces.  Returns J.
@@ -369,9 +381,9 @@ struct Chunk {
                 f[2] += lz[slot];
             }
             if (i >= ch.n_interior) {  // shared node: publish the partial sum
-                sp.pp[0][l] = f[0];
-                sp.pp[1][l] = f[1];
-                sp.pp[2][l] = f[2];
+                st_dev(&sp.pp[0][l], f[0]);
+                st_dev(&sp.pp[1][l], f[1]);
+                st_dev(&sp.pp[2][l], f[2]);
                 continue;
             }
             if constexpr (MODE == 0) {
@@ -399,9 +411,9 @@ struct Chunk {
             T f[3] = {T(0), T(0), T(0)};
             for (int q = 0; q < cnt; q++) {
                 const int src = tp.sh_list[b + q];
-                f[0] += sp.pp[0][src];
-                f[1] += sp.pp[1][src];
-                f[2] += sp.pp[2][src];
+                f[0] += ld_dev(&sp.pp[0][src]);
+                f[1] += ld_dev(&sp.pp[1][src]);
+                f[2] += ld_dev(&sp.pp[2][src]);
             }
             if constexpr (MODE == 0) {
                 const int n = tp.cnode[l];
@@ -444,40 +456,65 @@ __device__ __forceinline__ void block_sum2(double &x, double &y, double *sred) {
 }
 
 // ---------------------------------------------------------------------------
-// grid barrier for the persistent kernel (all workgroups co-resident:
-// cooperative launch).  Vector atomics only; bounded spin so that a fault in
-// co-residency ends in DJ_ERR_BARRIER instead of a hang.
+// Cross-workgroup communication.  On gfx950 the L2 of each XCD is not coherent
+// with the others, and agent-scope fences write back / invalidate whole L2s
+// (tens of microseconds with hundreds of workgroups).  So every value one
+// workgroup publishes to another (partial node forces, residual partials,
+// flags) is stored and loaded with device-scope relaxed atomics, which write
+// through to and read from the coherence point; a thread waits for its own
+// stores to be acknowledged before its workgroup signals arrival.
 // ---------------------------------------------------------------------------
-constexpr unsigned SPIN_LIMIT = 1u << 22;
 
-__device__ __forceinline__ bool grid_barrier(uint32_t *bar, uint32_t nblocks, uint32_t &epoch, int32_t *status) {
+constexpr unsigned SPIN_LIMIT = 1u << 24;
+constexpr int N_RELEASE = 16;   // release-flag copies, one cache line apart
+constexpr int FLAG_STRIDE = 32; // uint32 per flag slot (128 B)
+
+// Grid barrier for the persistent kernel (all workgroups co-resident through
+// a cooperative launch).  Arrival: one flag per workgroup; workgroup 0 polls
+// them all and then raises N_RELEASE release flags.  Bounded spins: a broken
+// co-residency ends in DJ_ERR_BARRIER instead of a hang.
+//   sync[0 .. G*FLAG_STRIDE)        arrival flags
+//   sync[G*FLAG_STRIDE ...)         release flags
+//   status[4]                       abort flag
+__device__ __forceinline__ bool grid_barrier(uint32_t *sync, uint32_t nblocks, uint32_t &epoch, int32_t *status) {
     __shared__ int s_ok;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's published stores are complete
     __syncthreads();
+    const uint32_t target = epoch + 1u;
+    uint32_t *rel = sync + size_t(nblocks) * FLAG_STRIDE;
     if (threadIdx.x == 0) {
-        int ok = 1;
-        const uint32_t target = epoch + 1u;
-        const uint32_t prev = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == nblocks - 1u) {
-            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&bar[1], target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+        s_ok = 1;
+        st_dev(&sync[size_t(blockIdx.x) * FLAG_STRIDE], target);
+    }
+    if (blockIdx.x == 0) {
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < nblocks; i += blockDim.x) {
             unsigned spins = 0;
-            while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != target) {
-                __builtin_amdgcn_s_sleep(2);
-                if (++spins > SPIN_LIMIT ||
-                    __hip_atomic_load(&status[4], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                    __hip_atomic_store(&status[4], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
+            while (ld_dev(&sync[size_t(i) * FLAG_STRIDE]) != target) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > SPIN_LIMIT || ld_dev(&status[4]) != 0) {
+                    st_dev(&status[4], 1);
+                    s_ok = 0;
                     break;
                 }
             }
         }
-        epoch = target;
-        s_ok = ok;
+        __syncthreads();
+        if (threadIdx.x < N_RELEASE && s_ok) st_dev(&rel[threadIdx.x * FLAG_STRIDE], target);
+    } else if (threadIdx.x == 0) {
+        const uint32_t *r = &rel[(blockIdx.x % N_RELEASE) * FLAG_STRIDE];
+        unsigned spins = 0;
+        while (ld_dev(r) != target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > SPIN_LIMIT || ld_dev(&status[4]) != 0) {
+                st_dev(&status[4], 1);
+                s_ok = 0;
+                break;
+            }
+        }
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    epoch = target;
     return s_ok != 0;
 }
 
@@ -528,8 +565,7 @@ __global__ void __launch_bounds__(BLOCK) k_step(DevTopo tp, StepArgs a) {
     T *lds = reinterpret_cast<T *>(smem);
     const int64_t L = tp.n_copies;
     const uint32_t G = gridDim.x;
-    uint32_t epoch = 0;
-    if (threadIdx.x == 0) epoch = __hip_atomic_load(&a.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t epoch = 0;  // the flags are cleared before every launch
     T *ub[3] = {static_cast<T *>(a.ubuf[0]), static_cast<T *>(a.ubuf[1]), static_cast<T *>(a.ubuf[2])};
     T *part = static_cast<T *>(a.part);
     const T *ru = static_cast<const T *>(a.ru);
@@ -588,8 +624,8 @@ __global__ void __launch_bounds__(BLOCK) k_step(DevTopo tp, StepArgs a) {
             block_sum2<BLOCK>(x, y, sred);
             double *red = a.red + size_t(s & 1) * 2 * G;
             if (threadIdx.x == 0) {
-                red[2 * blockIdx.x] = x;
-                red[2 * blockIdx.x + 1] = y;
+                st_dev(&red[2 * blockIdx.x], x);
+                st_dev(&red[2 * blockIdx.x + 1], y);
             }
             if (!grid_barrier(a.bar, G, epoch, a.status)) {
                 code = DJ_ERR_BARRIER;
@@ -598,8 +634,8 @@ __global__ void __launch_bounds__(BLOCK) k_step(DevTopo tp, StepArgs a) {
             // every workgroup reduces all partials in the same order
             double sx = 0, sy = 0;
             for (uint32_t g = threadIdx.x; g < G; g += BLOCK) {
-                sx += red[2 * g];
-                sy += red[2 * g + 1];
+                sx += ld_dev(&red[2 * g]);
+                sy += ld_dev(&red[2 * g + 1]);
             }
             block_sum2<BLOCK>(sx, sy, sred);
             if (threadIdx.x == 0) {
@@ -804,13 +840,11 @@ __global__ void k_export_mass(const double *__restrict__ mass, const int32_t *__
     out[nperm[n]] = mass[n];
 }
 
-__global__ void k_reset_sync(uint32_t *bar, int32_t *status) {
-    if (threadIdx.x == 0) {
-        bar[0] = 0u;
-        bar[1] = 0u;
-        for (int i = 0; i < 8; i++) status[i] = 0;
-        status[2] = -1;
-    }
+// clears the barrier flags and the status words before a persistent launch
+// (a kernel rather than a memset, so that the sequence can be graph-captured)
+__global__ void k_reset_sync(uint32_t *sync, int n_sync, int32_t *status) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_sync; i += gridDim.x * blockDim.x) sync[i] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < 8) status[threadIdx.x] = threadIdx.x == 2 ? -1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -860,7 +894,8 @@ struct Inst {
     static hipError_t step(Ctx &c, const StepArgs &a, const void *u_cur_in, const void *u_prev_in, hipStream_t s,
                            hipEvent_t ev0, hipEvent_t ev1) {
         const int L = c.topo.n_copies, B = 256;
-        hipLaunchKernelGGL(k_reset_sync, dim3(1), dim3(64), 0, s, c.d_bar, c.d_status);
+        const int n_sync = (c.grid + N_RELEASE) * FLAG_STRIDE;
+        hipLaunchKernelGGL(k_reset_sync, dim3((n_sync + 255) / 256), dim3(256), 0, s, c.d_bar, n_sync, c.d_status);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         T *dcur = static_cast<T *>(c.d_ubuf[a.cur0]);
