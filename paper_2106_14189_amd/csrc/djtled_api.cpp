@@ -111,6 +111,7 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     const Variant var = variants(NE, c.prec)[c.variant];
     c.block = var.block;
     c.ept = var.ept;
+    c.mcopy = var.mcopy;
     c.cmax = var.block * var.ept;
 
     // ---- reorder: elements by the Morton code of their centroid, nodes by first touch
@@ -187,22 +188,35 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     int C = c.cmax;
     if (prm->chunk_elems > 0) C = std::min(prm->chunk_elems, c.cmax);
     else C = std::min(c.cmax, std::max(64, (E + gmax - 1) / gmax));
-    int64_t nch = (E + C - 1) / C;
+
+    // ---- chunks, node copies, local CSR, shared-node partial groups.  A chunk
+    // may hold at most mcopy * block node copies; larger meshes per chunk are
+    // re-partitioned with smaller chunks.
+    int64_t nch = 0;
+    std::vector<ChunkDesc> chunks;
+    std::vector<uint32_t> crange;
+    std::vector<uint16_t> lcsr_slot;
+    std::vector<uint32_t> flags;
+    std::vector<int32_t> copy_node;  // internal node id of each copy
+    std::vector<int32_t> local_of(N, -1), in_chunk(N, 0);
+    std::vector<std::vector<int32_t>> node_copies(N);
+    int max_copies = 0;
+    for (int attempt = 0;; attempt++) {
+    nch = (E + C - 1) / C;
     if (nch > gmax) nch = (nch + gmax - 1) / gmax * gmax;  // whole rounds of the resident grid
     if (nch > E) nch = E;
     c.chunk_elems = int((E + nch - 1) / nch);
     c.grid = int(std::min<int64_t>(nch, gmax));
-
-    // ---- chunks, node copies, local CSR, shared-node lists
-    std::vector<ChunkDesc> chunks(nch);
-    std::vector<int32_t> lcsr_off(1, 0);
-    std::vector<uint16_t> lcsr_slot;
-    std::vector<uint32_t> flags;
-    std::vector<int32_t> copy_node;  // internal node id of each copy
-    std::vector<int32_t> node_copies_off(N + 1, 0);
-    std::vector<int32_t> local_of(N, -1), in_chunk(N, 0);
-    std::vector<std::vector<int32_t>> node_copies(N);
-    lcsr_slot.reserve(int64_t(E) * NE);
+    if ((nch + c.grid - 1) / c.grid > 32)
+        return fail(DJ_ERR_UNSUPPORTED, "mesh needs more than 32 chunks per workgroup; use a larger variant");
+    chunks.assign(nch, ChunkDesc{});
+    crange.clear();
+    lcsr_slot.clear();
+    flags.clear();
+    copy_node.clear();
+    for (auto &v : node_copies) v.clear();
+    lcsr_slot.reserve(int64_t(E) * NE + 8 * nch);
+    max_copies = 0;
     for (int64_t ch = 0; ch < nch; ch++) {
         const int eb = int(ch * E / nch), ee = int((ch + 1) * E / nch);
         if (ee - eb > c.cmax) return fail(DJ_ERR_ARG, "internal: chunk exceeds capacity");
@@ -214,13 +228,17 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
             }
         std::vector<int32_t> interior, shared;
         for (int n : touched) (in_chunk[n] == deg[n] ? interior : shared).push_back(n);
+        while (lcsr_slot.size() % 8) lcsr_slot.push_back(0);
         ChunkDesc d{};
         d.elem_begin = eb;
         d.elem_count = ee - eb;
         d.copy_begin = int32_t(copy_node.size());
         d.copy_count = int32_t(touched.size());
         d.n_interior = int32_t(interior.size());
+        d.slot_begin = int32_t(lcsr_slot.size());
+        d.n_slots = NE * (ee - eb);
         chunks[ch] = d;
+        max_copies = std::max(max_copies, d.copy_count);
         std::vector<int32_t> order(interior);
         order.insert(order.end(), shared.begin(), shared.end());
         for (size_t i = 0; i < order.size(); i++) local_of[order[i]] = int32_t(i);
@@ -228,23 +246,21 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
         std::vector<int32_t> cnt(order.size(), 0);
         for (int e = eb; e < ee; e++)
             for (int a = 0; a < NE; a++) cnt[local_of[conn[int64_t(NE) * e + a]]]++;
-        const int64_t base = lcsr_slot.size();
-        std::vector<int64_t> pos(order.size());
-        int64_t acc = base;
+        std::vector<int32_t> pos(order.size());
+        int32_t acc = 0;
         for (size_t i = 0; i < order.size(); i++) {
             pos[i] = acc;
+            crange.push_back(uint32_t(acc) | (uint32_t(cnt[i]) << 16));
             acc += cnt[i];
         }
-        lcsr_slot.resize(acc);
+        const int64_t base = lcsr_slot.size();
+        lcsr_slot.resize(base + acc);
         for (int e = eb; e < ee; e++)
             for (int a = 0; a < NE; a++) {
                 const int li = local_of[conn[int64_t(NE) * e + a]];
-                lcsr_slot[pos[li]++] = uint16_t(a * c.cmax + (e - eb));
+                lcsr_slot[base + pos[li]++] = uint16_t(a * c.cmax + (e - eb));
             }
-        int64_t o = base;
         for (size_t i = 0; i < order.size(); i++) {
-            o += cnt[i];
-            lcsr_off.push_back(int32_t(o));
             const int n = order[i];
             const int l = int32_t(copy_node.size());
             copy_node.push_back(n);
@@ -256,28 +272,34 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
             local_of[n] = -1;
         }
     }
+    while (lcsr_slot.size() % 8) lcsr_slot.push_back(0);
+    if (max_copies <= c.mcopy * c.block) break;
+    if (attempt >= 12 || C <= 8)
+        return fail(DJ_ERR_UNSUPPORTED, "a chunk touches " + std::to_string(max_copies) +
+                                            " nodes, above the kernel's per-chunk capacity");
+    C = std::max(8, int(double(C) * 0.9 * c.mcopy * c.block / max_copies));
+    }
     const int64_t L = copy_node.size();
     if (L >= (int64_t(1) << 31) || lcsr_slot.size() >= (size_t(1) << 31))
         return fail(DJ_ERR_UNSUPPORTED, "mesh too large for 32-bit copy indices");
-    std::vector<int32_t> sh_beg(L, 0), sh_list, cnode(L);
-    int n_shared = 0;
+    // shared nodes: copies of one node form a contiguous partial group, in ascending chunk order
+    std::vector<int32_t> pidx(L, 0), cnode(L);
+    int32_t n_part = 0;
     for (int n = 0; n < N; n++) {
         const auto &cp = node_copies[n];
         if (cp.empty()) continue;
         flags[cp[0]] |= FLAG_CANON;
         if (cp.size() > 1) {
             if (cp.size() > 255) return fail(DJ_ERR_UNSUPPORTED, "node shared by more than 255 chunks");
-            const int32_t b = int32_t(sh_list.size());
-            for (int32_t l : cp) {
-                sh_beg[l] = b;
-                flags[l] |= uint32_t(cp.size()) << FLAG_NCOPY_SHIFT;
-                n_shared++;
+            for (size_t j = 0; j < cp.size(); j++) {
+                pidx[cp[j]] = n_part;
+                flags[cp[j]] |= (uint32_t(cp.size()) << FLAG_NCOPY_SHIFT) | (uint32_t(j) << FLAG_RANK_SHIFT);
             }
-            sh_list.insert(sh_list.end(), cp.begin(), cp.end());
+            n_part += int32_t(cp.size());
         }
     }
     for (int64_t l = 0; l < L; l++) cnode[l] = c.node_perm[copy_node[l]];
-    c.n_shared_copies = n_shared;
+    c.n_shared_copies = n_part;
     c.h_flags = flags;
     c.h_copy_node = copy_node;
 
@@ -287,27 +309,27 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     c.topo.estride = (int64_t(E) + 63) / 64 * 64;
     c.topo.n_chunks = int32_t(nch);
     c.topo.n_copies = int32_t(L);
+    c.topo.n_part = n_part;
     c.topo.cmax = c.cmax;
     ChunkDesc *d_chunks;
-    int32_t *d_lcsr_off, *d_sh_beg, *d_sh_list, *d_cnode;
+    int32_t *d_pidx, *d_cnode;
+    uint32_t *d_crange;
     uint16_t *d_lcsr_slot;
     uint32_t *d_flags;
     DJ_HIP(upload(c, &d_chunks, chunks));
-    DJ_HIP(upload(c, &d_lcsr_off, lcsr_off));
+    DJ_HIP(upload(c, &d_crange, crange));
     DJ_HIP(upload(c, &d_lcsr_slot, lcsr_slot));
     DJ_HIP(upload(c, &d_flags, flags));
-    DJ_HIP(upload(c, &d_sh_beg, sh_beg));
-    DJ_HIP(upload(c, &d_sh_list, sh_list));
+    DJ_HIP(upload(c, &d_pidx, pidx));
     DJ_HIP(upload(c, &d_cnode, cnode));
     DJ_HIP(upload(c, &c.d_inode, copy_node));
     DJ_HIP(upload(c, &c.d_elem_perm, c.elem_perm));
     DJ_HIP(upload(c, &c.d_node_perm, c.node_perm));
     c.topo.chunks = d_chunks;
-    c.topo.lcsr_off = d_lcsr_off;
+    c.topo.crange = d_crange;
     c.topo.lcsr_slot = d_lcsr_slot;
     c.topo.flags = d_flags;
-    c.topo.sh_beg = d_sh_beg;
-    c.topo.sh_list = d_sh_list;
+    c.topo.pidx = d_pidx;
     c.topo.cnode = d_cnode;
     unsigned char *p;
     DJ_HIP(dalloc(c, &p, size_t(NP) * c.topo.estride * ts));
@@ -321,7 +343,7 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
         DJ_HIP(dalloc(c, &p, 3 * L * ts));
         c.d_ubuf[b] = p;
     }
-    DJ_HIP(dalloc(c, &p, 6 * L * ts));
+    DJ_HIP(dalloc(c, &p, 6 * size_t(std::max(n_part, 1)) * ts));
     c.d_part = p;
     DJ_HIP(dalloc(c, &c.d_bar, size_t(c.grid + 16) * 32));  // barrier flags, one 128-B line each
     DJ_HIP(dalloc(c, &c.d_status, 8));
@@ -388,17 +410,23 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     c.mass_total = std::accumulate(m.begin(), m.end(), 0.0);
     DJ_HIP(hipDeviceSynchronize());
 
-    // ---- traffic model of one fused step (bytes that must cross HBM once)
-    double eb = double(NP) * ts;                         // element planes
-    double slots = double(lcsr_slot.size()) * 2 + double(L + 1) * 4;
-    double copies = double(L) * (10.0 * ts + 4.0);       // u^n, u^{n-1}, u^{n+1}, A, flags
-    double sh = 0;
-    for (int64_t l = 0; l < L; l++)
+    // ---- traffic model of one fused step: bytes that must cross HBM once per step
+    //   elements : NP planes + NE slot entries (uint16)
+    //   interior copies : slot range, flags, u^n, u^{n-1}, A (read), u^{n+1} (write)
+    //   shared copies   : slot range, flags, partial index, u^n (element phase);
+    //                     partial write; then flags, partial index, A, u^n, u^{n-1},
+    //                     the node's cnt partials (read) and u^{n+1} (write)
+    double eb = double(NP) * ts + 2.0 * NE;
+    double interior = 0, shared = 0;
+    for (int64_t l = 0; l < L; l++) {
         if (flags[l] & FLAG_SHARED) {
             const int k = (flags[l] >> FLAG_NCOPY_SHIFT) & 255;
-            sh += 3.0 * ts + k * (3.0 * ts + 4.0) + 4.0;  // write, read k partials + ids, sh_beg
+            shared += (4 + 4 + 4 + 3 * ts) + 3 * ts + (4 + 4 + ts + 6 * ts + k * 3.0 * ts + 3 * ts);
+        } else {
+            interior += 4 + 4 + 6 * ts + ts + 3 * ts;
         }
-    c.bytes_per_step = eb * E + slots + copies + sh + double(nch) * sizeof(ChunkDesc);
+    }
+    c.bytes_per_step = eb * E + interior + shared + double(nch) * sizeof(ChunkDesc);
     c.elem_bytes = eb;
     return DJ_OK;
 }

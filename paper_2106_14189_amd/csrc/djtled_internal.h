@@ -15,19 +15,22 @@ namespace dj {
 // Per-copy flag bits.  A "copy" is one chunk's private instance of a node:
 // every chunk keeps the state of all nodes its elements touch.
 enum : uint32_t {
-    FLAG_BC_MASK = 7u,     // bit k: component k prescribed
-    FLAG_SHARED = 8u,      // node has copies in more than one chunk
-    FLAG_CANON = 16u,      // the copy that writes the node to caller arrays
-    FLAG_RU = 32u,         // the loads hold a value for this node (R or BC target)
-    FLAG_NCOPY_SHIFT = 8u  // bits 8..15: number of copies of a shared node
+    FLAG_BC_MASK = 7u,       // bit k: component k prescribed
+    FLAG_SHARED = 8u,        // node has copies in more than one chunk
+    FLAG_CANON = 16u,        // the copy that writes the node to caller arrays
+    FLAG_RU = 32u,           // the loads hold a value for this node (R or BC target)
+    FLAG_NCOPY_SHIFT = 8u,   // bits 8..15: number of copies of a shared node
+    FLAG_RANK_SHIFT = 16u    // bits 16..23: this copy's rank among them (ascending chunk)
 };
 
 // One chunk = a contiguous range of (reordered) elements processed by one
 // workgroup, plus its private node copies [copy_begin, copy_begin + copy_count);
-// the first n_interior copies are nodes touched by this chunk only.
+// the first n_interior copies are nodes touched by this chunk only.  The
+// chunk's node -> slot lists occupy lcsr_slot[slot_begin, slot_begin + n_slots)
+// (slot_begin is a multiple of 8 so the lists load as 16-byte vectors).
 struct ChunkDesc {
     int32_t elem_begin, elem_count, copy_begin, copy_count;
-    int32_t n_interior, pad0, pad1, pad2;
+    int32_t n_interior, slot_begin, n_slots, pad;
 };
 
 // Element-constant plane indices.  Each plane holds one scalar per element
@@ -52,7 +55,7 @@ inline int n_planes(int ne, int model) {
 // Kernel variants (threads per workgroup, elements per thread); the chunk
 // capacity is block * ept elements.
 struct Variant {
-    int block, ept;
+    int block, ept, mcopy;  // mcopy: node copies per thread a chunk may hold
 };
 const std::vector<Variant> &variants(int ne, int prec);
 
@@ -62,12 +65,13 @@ struct DevTopo {
     int32_t n_chunks = 0;
     int32_t n_copies = 0;
     int32_t cmax = 0;           // chunk capacity (slot stride in LDS)
-    const int32_t *lcsr_off = nullptr;   // n_copies + 1
+    const uint32_t *crange = nullptr;    // per copy: first slot-list entry (relative to the
+                                         // chunk's slot_begin) | entry count << 16
     const uint16_t *lcsr_slot = nullptr; // slot = a * cmax + local element
     const uint32_t *flags = nullptr;
-    const int32_t *sh_beg = nullptr;     // shared copies: start in sh_list
-    const int32_t *sh_list = nullptr;    // copy ids of each shared node, ascending chunk
+    const int32_t *pidx = nullptr;       // shared copies: start of the node's partial group
     const int32_t *cnode = nullptr;      // caller node index of each copy
+    int32_t n_part = 0;                  // partial-force entries (one per shared copy)
     const void *elem = nullptr;          // element planes (context precision)
     int64_t estride = 0;
     const void *acoef = nullptr;         // per copy A_i = 2 dt^2 / ((2 + alpha dt) m_i)
@@ -88,7 +92,7 @@ struct StepArgs {
     int32_t check_every = 1;
     int32_t cur0 = 0;           // buffer index of u^n at entry (prev = cur0 + 2 mod 3)
     void *ubuf[3] = {nullptr, nullptr, nullptr};  // each: 3 planes over copies
-    void *part = nullptr;       // partial forces: 2 parities x 3 planes x n_copies
+    void *part = nullptr;       // partial forces: 2 parities x 3 planes x n_part
     void *u_out_cur = nullptr;  // caller arrays written at the end
     void *u_out_prev = nullptr;
     uint32_t *bar = nullptr;    // barrier flags: (grid + 16) x 32 uint32
@@ -101,7 +105,7 @@ struct StepArgs {
 struct Ctx {
     int device = 0;
     int n_nodes = 0, n_elems = 0, ne = 4, model = DJ_NH, prec = DJ_FP32;
-    int variant = 0, block = 256, ept = 4, cmax = 1024, grid = 1, chunk_elems = 0;
+    int variant = 0, block = 256, ept = 4, mcopy = 2, cmax = 1024, grid = 1, chunk_elems = 0;
     double dt = 0, dt_crit = 0, alpha = 0, rho = 0, hg_kappa = 0.1, mass_total = 0;
     int n_shared_copies = 0;
     double bytes_per_step = 0, elem_bytes = 0;

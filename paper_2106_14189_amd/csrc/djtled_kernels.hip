@@ -244,10 +244,10 @@ __device__ __forceinline__ T element_force(const T *__restrict__ cst, const T (&
 // ---------------------------------------------------------------------------
 template <typename T>
 struct StepPtrs {
-    const T *uc[3];   // u^n planes
+    const T *uc[3];   // u^n planes (over copies)
     const T *up[3];   // u^{n-1}
     T *un[3];         // u^{n+1}
-    T *pp[3];         // partial-force planes of this step's parity
+    T *pp[3];         // partial-force planes of this step's parity (over partial entries)
     const uint32_t *flags;
     const T *ru[3];   // load planes (null if no loads)
     const T *acoef;
@@ -265,22 +265,20 @@ struct PhaseOut {
 
 // u^{n+1} = u^n + B'(u^n - u^{n-1}) + A (R - F); prescribed components = s(t) target
 template <typename T>
-__device__ __forceinline__ void node_update(int l, uint32_t fl, const T (&f)[3], const StepPtrs<T> &sp, PhaseOut &po) {
-    const T A = sp.acoef[l];
+__device__ __forceinline__ void node_update(int l, uint32_t fl, const T (&f)[3], const T (&uc)[3], const T (&up)[3],
+                                            T A, const T (&rv)[3], const StepPtrs<T> &sp, PhaseOut &po) {
     bool fin = true;
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-        const T uc = sp.uc[k][l], up = sp.up[k][l];
         const bool pres = (fl >> k) & 1u;
-        const T rv = (fl & FLAG_RU) ? sp.ru[k][l] : T(0);
         T un;
         if (pres) {
-            un = sp.sval * rv;
+            un = sp.sval * rv[k];
             if (sp.want_res && (fl & FLAG_CANON)) po.den += double(f[k]) * double(f[k]);
         } else {
-            un = uc + sp.bprime * (uc - up) + A * (rv - f[k]);
+            un = uc[k] + sp.bprime * (uc[k] - up[k]) + A * (rv[k] - f[k]);
             if (sp.want_res && (fl & FLAG_CANON)) {
-                const double d = double(f[k]) - double(rv);
+                const double d = double(f[k]) - double(rv[k]);
                 po.num += d * d;
             }
         }
@@ -294,27 +292,33 @@ __device__ __forceinline__ void node_update(int l, uint32_t fl, const T (&f)[3],
 }
 
 // ---------------------------------------------------------------------------
-// Chunk element phase: scatter node copies into LDS slots, compute element
-// forces, gather node sums.  Interior copies are finished at once (force
-// output or update); shared copies publish their partial sums.
+// Chunk element phase.  Everything the chunk needs is requested in one round
+// (element planes, the chunk's node -> slot lists as 16-byte vectors, and the
+// per-copy data), then: slot lists to LDS; scatter u^n of the copies into the
+// element slots; element forces written back into the slots; node sums in
+// fixed list order.  Interior copies are finished at once (force output or
+// update); shared copies publish their partial sum into their node's group.
 // ---------------------------------------------------------------------------
-template <typename T, int NE, int MODEL, int BLOCK, int EPT>
+template <typename T, int NE, int MODEL, int BLOCK, int EPT, int MC>
 struct Chunk {
     static constexpr int CMAX = BLOCK * EPT;
     static constexpr int NP = Planes<NE, MODEL>::N;
-    static constexpr size_t LDS = size_t(3) * NE * CMAX * sizeof(T);
+    static constexpr int NV = (NE * CMAX / 8 + BLOCK - 1) / BLOCK;  // 16-byte slot vectors per thread
+    static constexpr size_t LDS_VAL = size_t(3) * NE * CMAX * sizeof(T);
+    static constexpr size_t LDS = LDS_VAL + size_t(NE) * CMAX * sizeof(uint16_t);
 
     // MODE 0: forces to the caller array; MODE 1: time-step update
     template <int MODE>
-    __device__ static void element_phase(const DevTopo &tp, const ChunkDesc &ch, const StepPtrs<T> &sp, T *lds,
-                                         PhaseOut &po) {
+    __device__ static void element_phase(const DevTopo &tp, const ChunkDesc &ch, const StepPtrs<T> &sp,
+                                         unsigned char *smem, PhaseOut &po) {
         const int tid = threadIdx.x;
-        T *lx = lds;
-        T *ly = lds + NE * CMAX;
-        T *lz = lds + 2 * NE * CMAX;
+        T *lx = reinterpret_cast<T *>(smem);
+        T *ly = lx + NE * CMAX;
+        T *lz = lx + 2 * NE * CMAX;
+        uint16_t *ls = reinterpret_cast<uint16_t *>(smem + LDS_VAL);
         const T *__restrict__ ep = static_cast<const T *>(tp.elem);
         const int64_t es = tp.estride;
-        // 1. element-constant loads first: their latency overlaps the scatter
+        // ---- one round of requests
         T cst[EPT][NP];
 #pragma unroll
         for (int j = 0; j < EPT; j++) {
@@ -325,20 +329,69 @@ struct Chunk {
                 for (int q = 0; q < NP; q++) cst[j][q] = __builtin_nontemporal_load(src + q * es);
             }
         }
-        // 2. scatter u^n of the chunk's node copies into the element slots
-        for (int i = tid; i < ch.copy_count; i += BLOCK) {
-            const int l = ch.copy_begin + i;
-            const T x = sp.uc[0][l], y = sp.uc[1][l], z = sp.uc[2][l];
-            const int b = tp.lcsr_off[l], e2 = tp.lcsr_off[l + 1];
-            for (int s = b; s < e2; s++) {
-                const int slot = tp.lcsr_slot[s];
-                lx[slot] = x;
-                ly[slot] = y;
-                lz[slot] = z;
+        const uint4 *sv_src = reinterpret_cast<const uint4 *>(tp.lcsr_slot + ch.slot_begin);
+        uint4 sv[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            const int q = tid + v * BLOCK;
+            if (q * 8 < ch.n_slots) sv[v] = sv_src[q];
+        }
+        uint32_t cr[MC], fl[MC];
+        int pb[MC];
+        T ux[MC][3], upv[MC][3], A[MC];
+#pragma unroll
+        for (int m = 0; m < MC; m++) {
+            const int i = tid + m * BLOCK;
+            if (i < ch.copy_count) {
+                const int l = ch.copy_begin + i;
+                cr[m] = tp.crange[l];
+                fl[m] = sp.flags[l];
+#pragma unroll
+                for (int k = 0; k < 3; k++) ux[m][k] = sp.uc[k][l];
+                if (i >= ch.n_interior) {
+                    pb[m] = tp.pidx[l];
+                } else if (MODE == 1) {
+#pragma unroll
+                    for (int k = 0; k < 3; k++) upv[m][k] = sp.up[k][l];
+                    A[m] = sp.acoef[l];
+                }
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            const int q = tid + v * BLOCK;
+            if (q * 8 < ch.n_slots) reinterpret_cast<uint4 *>(ls)[q] = sv[v];
+        }
+        // loads (BC targets / forces) of interior copies, needed only at the update
+        T rv[MC][3];
+#pragma unroll
+        for (int m = 0; m < MC; m++) {
+            const int i = tid + m * BLOCK;
+#pragma unroll
+            for (int k = 0; k < 3; k++) rv[m][k] = T(0);
+            if (MODE == 1 && i < ch.n_interior && (fl[m] & FLAG_RU)) {
+                const int l = ch.copy_begin + i;
+#pragma unroll
+                for (int k = 0; k < 3; k++) rv[m][k] = sp.ru[k][l];
             }
         }
         __syncthreads();
-        // 3. element forces, written back into the same slots
+        // ---- scatter u^n into the element slots
+#pragma unroll
+        for (int m = 0; m < MC; m++) {
+            const int i = tid + m * BLOCK;
+            if (i < ch.copy_count) {
+                const int b = cr[m] & 0xffffu, n = cr[m] >> 16;
+                for (int s = b; s < b + n; s++) {
+                    const int slot = ls[s];
+                    lx[slot] = ux[m][0];
+                    ly[slot] = ux[m][1];
+                    lz[slot] = ux[m][2];
+                }
+            }
+        }
+        __syncthreads();
+        // ---- element forces, written back into the same slots
 #pragma unroll
         for (int j = 0; j < EPT; j++) {
             const int e = tid + j * BLOCK;
@@ -369,59 +422,110 @@ struct Chunk {
             }
         }
         __syncthreads();
-        // 4. node sums in fixed (CSR) order
-        for (int i = tid; i < ch.copy_count; i += BLOCK) {
-            const int l = ch.copy_begin + i;
-            const int b = tp.lcsr_off[l], e2 = tp.lcsr_off[l + 1];
-            T f[3] = {T(0), T(0), T(0)};
-            for (int s = b; s < e2; s++) {
-                const int slot = tp.lcsr_slot[s];
-                f[0] += lx[slot];
-                f[1] += ly[slot];
-                f[2] += lz[slot];
-            }
-            if (i >= ch.n_interior) {  // shared node: publish the partial sum
-                st_dev(&sp.pp[0][l], f[0]);
-                st_dev(&sp.pp[1][l], f[1]);
-                st_dev(&sp.pp[2][l], f[2]);
-                continue;
-            }
-            if constexpr (MODE == 0) {
-                const int n = tp.cnode[l];
-                sp.fout[3 * n] = f[0];
-                sp.fout[3 * n + 1] = f[1];
-                sp.fout[3 * n + 2] = f[2];
-            } else {
-                node_update<T>(l, sp.flags[l], f, sp, po);
+        // ---- node sums in fixed (list) order; finish interior, publish shared
+#pragma unroll
+        for (int m = 0; m < MC; m++) {
+            const int i = tid + m * BLOCK;
+            if (i < ch.copy_count) {
+                const int b = cr[m] & 0xffffu, n = cr[m] >> 16;
+                T f[3] = {T(0), T(0), T(0)};
+                for (int s = b; s < b + n; s++) {
+                    const int slot = ls[s];
+                    f[0] += lx[slot];
+                    f[1] += ly[slot];
+                    f[2] += lz[slot];
+                }
+                const int l = ch.copy_begin + i;
+                if (i >= ch.n_interior) {
+                    const int q = pb[m] + int((fl[m] >> FLAG_RANK_SHIFT) & 255u);
+                    st_dev(&sp.pp[0][q], f[0]);
+                    st_dev(&sp.pp[1][q], f[1]);
+                    st_dev(&sp.pp[2][q], f[2]);
+                } else if constexpr (MODE == 0) {
+                    const int nd = tp.cnode[l];
+                    sp.fout[3 * nd] = f[0];
+                    sp.fout[3 * nd + 1] = f[1];
+                    sp.fout[3 * nd + 2] = f[2];
+                } else {
+                    node_update<T>(l, fl[m], f, ux[m], upv[m], A[m], rv[m], sp, po);
+                }
             }
         }
         __syncthreads();  // LDS is reused by the next chunk
     }
 
-    // Shared copies of one chunk: sum the partials of all copies of the node
-    // in ascending chunk order, then finish as above.
-    template <int MODE>
-    __device__ static void shared_phase(const DevTopo &tp, const ChunkDesc &ch, const StepPtrs<T> &sp, PhaseOut &po) {
-        for (int i = ch.n_interior + threadIdx.x; i < ch.copy_count; i += BLOCK) {
-            const int l = ch.copy_begin + i;
-            const uint32_t fl = sp.flags[l];
-            if (MODE == 0 && !(fl & FLAG_CANON)) continue;
-            const int cnt = (fl >> FLAG_NCOPY_SHIFT) & 255u;
-            const int b = tp.sh_beg[l];
-            T f[3] = {T(0), T(0), T(0)};
-            for (int q = 0; q < cnt; q++) {
-                const int src = tp.sh_list[b + q];
-                f[0] += ld_dev(&sp.pp[0][src]);
-                f[1] += ld_dev(&sp.pp[1][src]);
-                f[2] += ld_dev(&sp.pp[2][src]);
+    // Shared copies of up to KB chunks: round A (copy data) for all, round B
+    // (the node's partial group) for all, then sum in rank order and finish.
+    template <int MODE, int KB>
+    __device__ static void shared_batch(const DevTopo &tp, const ChunkDesc *chs, int nb, int pass,
+                                        const StepPtrs<T> &sp, PhaseOut &po) {
+        constexpr int UNR = 4;
+        uint32_t fl[KB];
+        int pb[KB], li[KB];
+        bool ok[KB];
+        T uc[KB][3], up[KB][3], rv[KB][3], A[KB];
+#pragma unroll
+        for (int kb = 0; kb < KB; kb++) {
+            ok[kb] = false;
+            if (kb < nb) {
+                const ChunkDesc &ch = chs[kb];
+                const int i = ch.n_interior + threadIdx.x + pass * BLOCK;
+                if (i < ch.copy_count) {
+                    const int l = ch.copy_begin + i;
+                    li[kb] = l;
+                    ok[kb] = true;
+                    fl[kb] = sp.flags[l];
+                    pb[kb] = tp.pidx[l];
+                    if (MODE == 1) {
+                        A[kb] = sp.acoef[l];
+#pragma unroll
+                        for (int k = 0; k < 3; k++) {
+                            uc[kb][k] = sp.uc[k][l];
+                            up[kb][k] = sp.up[k][l];
+                            rv[kb][k] = sp.ru[0] ? sp.ru[k][l] : T(0);
+                        }
+                    }
+                }
             }
+        }
+        T px[KB][UNR][3];
+#pragma unroll
+        for (int kb = 0; kb < KB; kb++) {
+            if (ok[kb]) {
+                const int cnt = (fl[kb] >> FLAG_NCOPY_SHIFT) & 255u;
+#pragma unroll
+                for (int q = 0; q < UNR; q++)
+                    if (q < cnt)
+#pragma unroll
+                        for (int k = 0; k < 3; k++) px[kb][q][k] = ld_dev(&sp.pp[k][pb[kb] + q]);
+            }
+        }
+#pragma unroll
+        for (int kb = 0; kb < KB; kb++) {
+            if (!ok[kb]) continue;
+            const int cnt = (fl[kb] >> FLAG_NCOPY_SHIFT) & 255u;
+            T f[3] = {T(0), T(0), T(0)};
+#pragma unroll
+            for (int q = 0; q < UNR; q++)
+                if (q < cnt)
+#pragma unroll
+                    for (int k = 0; k < 3; k++) f[k] += px[kb][q][k];
+            for (int q = UNR; q < cnt; q++)
+#pragma unroll
+                for (int k = 0; k < 3; k++) f[k] += ld_dev(&sp.pp[k][pb[kb] + q]);
+            const int l = li[kb];
             if constexpr (MODE == 0) {
-                const int n = tp.cnode[l];
-                sp.fout[3 * n] = f[0];
-                sp.fout[3 * n + 1] = f[1];
-                sp.fout[3 * n + 2] = f[2];
+                if (fl[kb] & FLAG_CANON) {
+                    const int nd = tp.cnode[l];
+                    sp.fout[3 * nd] = f[0];
+                    sp.fout[3 * nd + 1] = f[1];
+                    sp.fout[3 * nd + 2] = f[2];
+                }
             } else {
-                node_update<T>(l, fl, f, sp, po);
+                if (!(fl[kb] & FLAG_RU))
+#pragma unroll
+                    for (int k = 0; k < 3; k++) rv[kb][k] = T(0);
+                node_update<T>(l, fl[kb], f, uc[kb], up[kb], A[kb], rv[kb], sp, po);
             }
         }
     }
@@ -535,38 +639,48 @@ __global__ void k_scatter_in(const int32_t *__restrict__ cnode, int n_copies, co
     }
 }
 
-template <typename T, int NE, int MODEL, int BLOCK, int EPT>
+template <typename T, int NE, int MODEL, int BLOCK, int EPT, int MC>
 __global__ void __launch_bounds__(BLOCK) k_forces_elem(DevTopo tp, StepPtrs<T> sp) {
-    using C = Chunk<T, NE, MODEL, BLOCK, EPT>;
+    using C = Chunk<T, NE, MODEL, BLOCK, EPT, MC>;
     extern __shared__ __align__(16) unsigned char smem[];
     PhaseOut po{0.0, 0.0, 0, -1};
     const ChunkDesc ch = tp.chunks[blockIdx.x];
-    C::template element_phase<0>(tp, ch, sp, reinterpret_cast<T *>(smem), po);
+    C::template element_phase<0>(tp, ch, sp, smem, po);
 }
 
-template <typename T, int NE, int MODEL, int BLOCK, int EPT>
+template <typename T, int NE, int MODEL, int BLOCK, int EPT, int MC>
 __global__ void __launch_bounds__(BLOCK) k_forces_shared(DevTopo tp, StepPtrs<T> sp) {
-    using C = Chunk<T, NE, MODEL, BLOCK, EPT>;
+    using C = Chunk<T, NE, MODEL, BLOCK, EPT, MC>;
     PhaseOut po{0.0, 0.0, 0, -1};
     const ChunkDesc ch = tp.chunks[blockIdx.x];
-    C::template shared_phase<0>(tp, ch, sp, po);
+    for (int pass = 0; ch.n_interior + pass * BLOCK < ch.copy_count; pass++)
+        C::template shared_batch<0, 1>(tp, &ch, 1, pass, sp, po);
 }
 
 // The persistent multi-step kernel: n_steps x {element phase of every owned
 // chunk -> grid barrier -> shared-node phase}, one barrier per step (plus one
 // on residual-check steps).  All workgroups take every decision from values
 // published before a common barrier, so they leave the loop together.
-template <typename T, int NE, int MODEL, int BLOCK, int EPT>
+constexpr int KMAX = 32;  // chunks per workgroup
+
+template <typename T, int NE, int MODEL, int BLOCK, int EPT, int MC>
 __global__ void __launch_bounds__(BLOCK) k_step(DevTopo tp, StepArgs a) {
-    using C = Chunk<T, NE, MODEL, BLOCK, EPT>;
+    using C = Chunk<T, NE, MODEL, BLOCK, EPT, MC>;
+    constexpr int KB = 4;  // chunks per shared-phase batch
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double sred[2 * (BLOCK / 64)];
     __shared__ int s_flag;
-    T *lds = reinterpret_cast<T *>(smem);
+    __shared__ ChunkDesc s_ch[KMAX];
     const int64_t L = tp.n_copies;
+    const int64_t NPART = tp.n_part;
     const uint32_t G = gridDim.x;
+    const int nmine = int(blockIdx.x) < tp.n_chunks ? (tp.n_chunks - int(blockIdx.x) + int(G) - 1) / int(G) : 0;
+    for (int k = threadIdx.x; k < nmine; k += BLOCK) s_ch[k] = tp.chunks[blockIdx.x + k * G];
+    __syncthreads();
     uint32_t epoch = 0;  // the flags are cleared before every launch
-    T *ub[3] = {static_cast<T *>(a.ubuf[0]), static_cast<T *>(a.ubuf[1]), static_cast<T *>(a.ubuf[2])};
+    T *const ub0 = static_cast<T *>(a.ubuf[0]), *const ub1 = static_cast<T *>(a.ubuf[1]),
+            *const ub2 = static_cast<T *>(a.ubuf[2]);
+    auto ub = [&](int i) { return i == 0 ? ub0 : (i == 1 ? ub1 : ub2); };  // no runtime-indexed array
     T *part = static_cast<T *>(a.part);
     const T *ru = static_cast<const T *>(a.ru);
     int cur = a.cur0;
@@ -579,10 +693,10 @@ __global__ void __launch_bounds__(BLOCK) k_step(DevTopo tp, StepArgs a) {
         const bool check = a.relax && (s % a.check_every) == 0 && ramp_value(a.ramp, double(n) * a.dt, a.t_ramp) >= 1.0;
         StepPtrs<T> sp;
         for (int k = 0; k < 3; k++) {
-            sp.uc[k] = ub[cur] + k * L;
-            sp.up[k] = ub[prv] + k * L;
-            sp.un[k] = ub[nxt] + k * L;
-            sp.pp[k] = part + ((s & 1) * 3 + k) * L;
+            sp.uc[k] = ub(cur) + k * L;
+            sp.up[k] = ub(prv) + k * L;
+            sp.un[k] = ub(nxt) + k * L;
+            sp.pp[k] = part + ((s & 1) * 3 + k) * NPART;
             sp.ru[k] = ru ? ru + k * L : nullptr;
         }
         sp.flags = a.flags;
@@ -592,10 +706,7 @@ __global__ void __launch_bounds__(BLOCK) k_step(DevTopo tp, StepArgs a) {
         sp.want_res = check;
         sp.fout = nullptr;
         PhaseOut po{0.0, 0.0, 0, -1};
-        for (int c = blockIdx.x; c < tp.n_chunks; c += G) {
-            const ChunkDesc ch = tp.chunks[c];
-            C::template element_phase<1>(tp, ch, sp, lds, po);
-        }
+        for (int k = 0; k < nmine; k++) C::template element_phase<1>(tp, s_ch[k], sp, smem, po);
         // Errors of step s go to the error word of parity s & 1, which nobody
         // writes again before every workgroup has read it after this barrier.
         int32_t *errw = &a.status[5 + (s & 1)];
@@ -609,15 +720,20 @@ __global__ void __launch_bounds__(BLOCK) k_step(DevTopo tp, StepArgs a) {
             code = DJ_ERR_BARRIER;
             break;
         }
-        if (threadIdx.x == 0) s_flag = __hip_atomic_load(errw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0) s_flag = ld_dev(errw);
         __syncthreads();
         if (s_flag != 0) {
             code = s_flag;
             break;
         }
-        for (int c = blockIdx.x; c < tp.n_chunks; c += G) {
-            const ChunkDesc ch = tp.chunks[c];
-            C::template shared_phase<1>(tp, ch, sp, po);
+        for (int k0 = 0; k0 < nmine; k0 += KB) {
+            const int nb = min(KB, nmine - k0);
+            for (int pass = 0;; pass++) {
+                bool more = false;
+                for (int kb = 0; kb < nb; kb++) more |= s_ch[k0 + kb].n_interior + pass * BLOCK < s_ch[k0 + kb].copy_count;
+                if (!more) break;
+                C::template shared_batch<1, KB>(tp, s_ch + k0, nb, pass, sp, po);
+            }
         }
         if (check) {
             double x = po.num, y = po.den;
@@ -666,16 +782,16 @@ __global__ void __launch_bounds__(BLOCK) k_step(DevTopo tp, StepArgs a) {
     const int prv = (cur + 2) % 3;
     T *oc = static_cast<T *>(a.u_out_cur);
     T *op = static_cast<T *>(a.u_out_prev);
-    for (int c = blockIdx.x; c < tp.n_chunks; c += G) {
-        const ChunkDesc ch = tp.chunks[c];
+    for (int k = 0; k < nmine; k++) {
+        const ChunkDesc ch = s_ch[k];
         for (int i = threadIdx.x; i < ch.copy_count; i += BLOCK) {
             const int l = ch.copy_begin + i;
             if (!(tp.flags[l] & FLAG_CANON)) continue;
             const int nd = tp.cnode[l];
 #pragma unroll
-            for (int k = 0; k < 3; k++) {
-                oc[3 * nd + k] = ub[cur][k * L + l];
-                op[3 * nd + k] = ub[prv][k * L + l];
+            for (int c3 = 0; c3 < 3; c3++) {
+                oc[3 * nd + c3] = ub(cur)[c3 * L + l];
+                op[3 * nd + c3] = ub(prv)[c3 * L + l];
             }
         }
     }
@@ -851,12 +967,12 @@ __global__ void k_reset_sync(uint32_t *sync, int n_sync, int32_t *status) {
 // Dispatch over (precision, element type, model, variant)
 // ---------------------------------------------------------------------------
 
-template <typename T, int NE, int MODEL, int BLOCK, int EPT>
+template <typename T, int NE, int MODEL, int BLOCK, int EPT, int MC>
 struct Inst {
-    using C = Chunk<T, NE, MODEL, BLOCK, EPT>;
+    using C = Chunk<T, NE, MODEL, BLOCK, EPT, MC>;
     static hipError_t occ(int *bpc, size_t *lds) {
         *lds = C::LDS;
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, k_step<T, NE, MODEL, BLOCK, EPT>, BLOCK, C::LDS);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, k_step<T, NE, MODEL, BLOCK, EPT, MC>, BLOCK, C::LDS);
     }
     static hipError_t forces(Ctx &c, const void *u, void *f, hipStream_t s) {
         const int L = c.topo.n_copies, B = 256;
@@ -871,7 +987,7 @@ struct Inst {
             sp.uc[k] = u0 + int64_t(k) * L;
             sp.up[k] = nullptr;
             sp.un[k] = nullptr;
-            sp.pp[k] = part + int64_t(k) * L;
+            sp.pp[k] = part + int64_t(k) * std::max(c.topo.n_part, 1);
             sp.ru[k] = nullptr;
         }
         sp.flags = c.topo.flags;
@@ -880,14 +996,14 @@ struct Inst {
         sp.sval = T(0);
         sp.want_res = false;
         sp.fout = static_cast<T *>(f);
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_forces_elem<T, NE, MODEL, BLOCK, EPT>),
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_forces_elem<T, NE, MODEL, BLOCK, EPT, MC>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(C::LDS));
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_forces_elem<T, NE, MODEL, BLOCK, EPT>), dim3(c.topo.n_chunks), dim3(BLOCK), C::LDS, s,
-                           c.topo, sp);
+        hipLaunchKernelGGL((k_forces_elem<T, NE, MODEL, BLOCK, EPT, MC>), dim3(c.topo.n_chunks), dim3(BLOCK), C::LDS,
+                           s, c.topo, sp);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_forces_shared<T, NE, MODEL, BLOCK, EPT>), dim3(c.topo.n_chunks), dim3(BLOCK), 0, s,
+        hipLaunchKernelGGL((k_forces_shared<T, NE, MODEL, BLOCK, EPT, MC>), dim3(c.topo.n_chunks), dim3(BLOCK), 0, s,
                            c.topo, sp);
         return hipGetLastError();
     }
@@ -907,11 +1023,11 @@ struct Inst {
         DevTopo tp = c.topo;
         StepArgs aa = a;
         void *args[] = {&tp, &aa};
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_step<T, NE, MODEL, BLOCK, EPT>),
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_step<T, NE, MODEL, BLOCK, EPT, MC>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(C::LDS));
         if (e != hipSuccess) return e;
         if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
-        e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_step<T, NE, MODEL, BLOCK, EPT>),
+        e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_step<T, NE, MODEL, BLOCK, EPT, MC>),
                                        dim3(c.grid), dim3(BLOCK), args, C::LDS, s);
         if (e != hipSuccess) return e;
         if (ev1) e = hipEventRecord(ev1, s);
@@ -919,15 +1035,27 @@ struct Inst {
     }
 };
 
+// Kernel variants per (precision, element type): {threads, elements per thread, copies per thread}
+constexpr Variant VAR_T4F[4] = {{256, 4, 2}, {256, 2, 2}, {512, 2, 2}, {128, 4, 2}};
+constexpr Variant VAR_H8F[4] = {{256, 2, 4}, {256, 1, 4}, {512, 1, 3}, {128, 2, 4}};
+constexpr Variant VAR_T4D[4] = {{256, 2, 2}, {256, 1, 2}, {512, 1, 2}, {128, 2, 2}};
+constexpr Variant VAR_H8D[4] = {{256, 1, 4}, {128, 1, 4}, {512, 1, 3}, {128, 2, 4}};
+
+template <typename T, int NE>
+constexpr const Variant *var_table() {
+    return sizeof(T) == 4 ? (NE == 4 ? VAR_T4F : VAR_H8F) : (NE == 4 ? VAR_T4D : VAR_H8D);
+}
+
+template <typename T, int NE, int MODEL, int V>
+using InstV = Inst<T, NE, MODEL, var_table<T, NE>()[V].block, var_table<T, NE>()[V].ept, var_table<T, NE>()[V].mcopy>;
+
 template <typename T, int NE, int MODEL, typename F>
 static hipError_t with_variant(int v, F &&f) {
-    constexpr bool dbl = sizeof(T) == 8;
-    constexpr int E0 = NE == 4 ? (dbl ? 2 : 4) : (dbl ? 1 : 2);
     switch (v) {
-        case 0: return f(Inst<T, NE, MODEL, 256, E0>());
-        case 1: return f(Inst<T, NE, MODEL, 256, 2 * E0>());
-        case 2: return f(Inst<T, NE, MODEL, 512, E0>());
-        case 3: return f(Inst<T, NE, MODEL, 128, E0>());
+        case 0: return f(InstV<T, NE, MODEL, 0>());
+        case 1: return f(InstV<T, NE, MODEL, 1>());
+        case 2: return f(InstV<T, NE, MODEL, 2>());
+        case 3: return f(InstV<T, NE, MODEL, 3>());
         default: return hipErrorInvalidValue;
     }
 }
@@ -943,10 +1071,8 @@ static hipError_t dispatch(int prec, int ne, int model, int v, F &&f) {
 }
 
 const std::vector<Variant> &variants(int ne, int prec) {
-    static const std::vector<Variant> t4f = {{256, 4}, {256, 8}, {512, 4}, {128, 4}};
-    static const std::vector<Variant> h8f = {{256, 2}, {256, 4}, {512, 2}, {128, 2}};
-    static const std::vector<Variant> t4d = {{256, 2}, {256, 4}, {512, 2}, {128, 2}};
-    static const std::vector<Variant> h8d = {{256, 1}, {256, 2}, {512, 1}, {128, 1}};
+    static const std::vector<Variant> t4f(VAR_T4F, VAR_T4F + 4), h8f(VAR_H8F, VAR_H8F + 4);
+    static const std::vector<Variant> t4d(VAR_T4D, VAR_T4D + 4), h8d(VAR_H8D, VAR_H8D + 4);
     if (prec == DJ_FP32) return ne == 4 ? t4f : h8f;
     return ne == 4 ? t4d : h8d;
 }
