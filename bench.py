@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=15, help="oracle steps per mesh for cpu_baseline (0: skip)")
     ap.add_argument("--variant", type=int, default=-1, help="kernel variant (-1: per-mesh default)")
     ap.add_argument("--mesh", choices=["both", "t4", "h8"], default="both")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="after the run, copy a 256 MiB buffer 4 times (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -164,6 +166,13 @@ def main():
                      "bytes_per_launch": dom["info"]["bytes_per_step"] * K,
                      "launch_ms": dom["status"].kernel_ms},
     }
+    if args.copy_calib:
+        x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")  # 256 MiB
+        y = torch.empty_like(x)
+        for _ in range(4):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        out["copy_calib_bytes"] = x.numel() * 4
     if args.cpu_steps > 0:
         out["cpu_baseline"] = cpu_baseline([r["wl"] for r in runs], args.cpu_steps)
     else:

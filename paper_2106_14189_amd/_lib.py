@@ -10,6 +10,11 @@ from __future__ import annotations
 import ctypes
 import os
 
+# PyTorch bundles its own HIP runtime under the same soname as the system one
+# (libamdhip64.so.7); importing torch first makes libdjtled.so bind to that
+# single runtime, which then serves both torch tensors and the library.
+import torch  # noqa: F401
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdjtled.so")
 

@@ -195,7 +195,8 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     int64_t nch = 0;
     std::vector<ChunkDesc> chunks;
     std::vector<uint32_t> crange;
-    std::vector<uint16_t> lcsr_slot;
+    std::vector<uint16_t> wpos;  // NE planes over elements, stride estride
+    const int64_t estride = (int64_t(E) + 63) / 64 * 64;
     std::vector<uint32_t> flags;
     std::vector<int32_t> copy_node;  // internal node id of each copy
     std::vector<int32_t> local_of(N, -1), in_chunk(N, 0);
@@ -211,11 +212,10 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
         return fail(DJ_ERR_UNSUPPORTED, "mesh needs more than 32 chunks per workgroup; use a larger variant");
     chunks.assign(nch, ChunkDesc{});
     crange.clear();
-    lcsr_slot.clear();
+    wpos.assign(size_t(NE) * estride, 0);
     flags.clear();
     copy_node.clear();
     for (auto &v : node_copies) v.clear();
-    lcsr_slot.reserve(int64_t(E) * NE + 8 * nch);
     max_copies = 0;
     for (int64_t ch = 0; ch < nch; ch++) {
         const int eb = int(ch * E / nch), ee = int((ch + 1) * E / nch);
@@ -228,21 +228,18 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
             }
         std::vector<int32_t> interior, shared;
         for (int n : touched) (in_chunk[n] == deg[n] ? interior : shared).push_back(n);
-        while (lcsr_slot.size() % 8) lcsr_slot.push_back(0);
         ChunkDesc d{};
         d.elem_begin = eb;
         d.elem_count = ee - eb;
         d.copy_begin = int32_t(copy_node.size());
         d.copy_count = int32_t(touched.size());
         d.n_interior = int32_t(interior.size());
-        d.slot_begin = int32_t(lcsr_slot.size());
-        d.n_slots = NE * (ee - eb);
         chunks[ch] = d;
         max_copies = std::max(max_copies, d.copy_count);
         std::vector<int32_t> order(interior);
         order.insert(order.end(), shared.begin(), shared.end());
         for (size_t i = 0; i < order.size(); i++) local_of[order[i]] = int32_t(i);
-        // slots of each local node, in (element, node) order
+        // incidences numbered in copy order, (element, node) order within a copy
         std::vector<int32_t> cnt(order.size(), 0);
         for (int e = eb; e < ee; e++)
             for (int a = 0; a < NE; a++) cnt[local_of[conn[int64_t(NE) * e + a]]]++;
@@ -253,12 +250,10 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
             crange.push_back(uint32_t(acc) | (uint32_t(cnt[i]) << 16));
             acc += cnt[i];
         }
-        const int64_t base = lcsr_slot.size();
-        lcsr_slot.resize(base + acc);
         for (int e = eb; e < ee; e++)
             for (int a = 0; a < NE; a++) {
                 const int li = local_of[conn[int64_t(NE) * e + a]];
-                lcsr_slot[base + pos[li]++] = uint16_t(a * c.cmax + (e - eb));
+                wpos[size_t(a) * estride + e] = uint16_t(pos[li]++);
             }
         for (size_t i = 0; i < order.size(); i++) {
             const int n = order[i];
@@ -272,7 +267,6 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
             local_of[n] = -1;
         }
     }
-    while (lcsr_slot.size() % 8) lcsr_slot.push_back(0);
     if (max_copies <= c.mcopy * c.block) break;
     if (attempt >= 12 || C <= 8)
         return fail(DJ_ERR_UNSUPPORTED, "a chunk touches " + std::to_string(max_copies) +
@@ -280,7 +274,7 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     C = std::max(8, int(double(C) * 0.9 * c.mcopy * c.block / max_copies));
     }
     const int64_t L = copy_node.size();
-    if (L >= (int64_t(1) << 31) || lcsr_slot.size() >= (size_t(1) << 31))
+    if (L >= (int64_t(1) << 31))
         return fail(DJ_ERR_UNSUPPORTED, "mesh too large for 32-bit copy indices");
     // shared nodes: copies of one node form a contiguous partial group, in ascending chunk order
     std::vector<int32_t> pidx(L, 0), cnode(L);
@@ -306,7 +300,7 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     // ---- device buffers
     const size_t ts = c.prec == DJ_FP32 ? 4 : 8;
     const int NP = n_planes(NE, c.model);
-    c.topo.estride = (int64_t(E) + 63) / 64 * 64;
+    c.topo.estride = estride;
     c.topo.n_chunks = int32_t(nch);
     c.topo.n_copies = int32_t(L);
     c.topo.n_part = n_part;
@@ -314,11 +308,11 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     ChunkDesc *d_chunks;
     int32_t *d_pidx, *d_cnode;
     uint32_t *d_crange;
-    uint16_t *d_lcsr_slot;
+    uint16_t *d_wpos;
     uint32_t *d_flags;
     DJ_HIP(upload(c, &d_chunks, chunks));
     DJ_HIP(upload(c, &d_crange, crange));
-    DJ_HIP(upload(c, &d_lcsr_slot, lcsr_slot));
+    DJ_HIP(upload(c, &d_wpos, wpos));
     DJ_HIP(upload(c, &d_flags, flags));
     DJ_HIP(upload(c, &d_pidx, pidx));
     DJ_HIP(upload(c, &d_cnode, cnode));
@@ -327,7 +321,7 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     DJ_HIP(upload(c, &c.d_node_perm, c.node_perm));
     c.topo.chunks = d_chunks;
     c.topo.crange = d_crange;
-    c.topo.lcsr_slot = d_lcsr_slot;
+    c.topo.wpos = d_wpos;
     c.topo.flags = d_flags;
     c.topo.pidx = d_pidx;
     c.topo.cnode = d_cnode;
@@ -411,7 +405,7 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     DJ_HIP(hipDeviceSynchronize());
 
     // ---- traffic model of one fused step: bytes that must cross HBM once per step
-    //   elements : NP planes + NE slot entries (uint16)
+    //   elements : NP planes + NE incidence positions (uint16)
     //   interior copies : slot range, flags, u^n, u^{n-1}, A (read), u^{n+1} (write)
     //   shared copies   : slot range, flags, partial index, u^n (element phase);
     //                     partial write; then flags, partial index, A, u^n, u^{n-1},

@@ -26,11 +26,12 @@ enum : uint32_t {
 // One chunk = a contiguous range of (reordered) elements processed by one
 // workgroup, plus its private node copies [copy_begin, copy_begin + copy_count);
 // the first n_interior copies are nodes touched by this chunk only.  The
-// chunk's node -> slot lists occupy lcsr_slot[slot_begin, slot_begin + n_slots)
-// (slot_begin is a multiple of 8 so the lists load as 16-byte vectors).
+// chunk's (element, node) incidences are numbered in node-copy order; copy l
+// owns the contiguous positions crange[l], and wpos[a][e] is the position of
+// node a of element e.
 struct ChunkDesc {
     int32_t elem_begin, elem_count, copy_begin, copy_count;
-    int32_t n_interior, slot_begin, n_slots, pad;
+    int32_t n_interior, pad0, pad1, pad2;
 };
 
 // Element-constant plane indices.  Each plane holds one scalar per element
@@ -65,9 +66,9 @@ struct DevTopo {
     int32_t n_chunks = 0;
     int32_t n_copies = 0;
     int32_t cmax = 0;           // chunk capacity (slot stride in LDS)
-    const uint32_t *crange = nullptr;    // per copy: first slot-list entry (relative to the
-                                         // chunk's slot_begin) | entry count << 16
-    const uint16_t *lcsr_slot = nullptr; // slot = a * cmax + local element
+    const uint32_t *crange = nullptr;    // per copy: first incidence position in the chunk
+                                         // | number of incidences << 16
+    const uint16_t *wpos = nullptr;      // NE planes over elements (stride estride)
     const uint32_t *flags = nullptr;
     const int32_t *pidx = nullptr;       // shared copies: start of the node's partial group
     const int32_t *cnode = nullptr;      // caller node index of each copy

@@ -40,12 +40,24 @@ namespace dj {
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
+// Cube root and reciprocal.  FP32 uses the hardware base-2 log / exp and
+// reciprocal (about 1 ulp each): they only ever multiply O(strain) terms in the
+// increment form below, so their error stays relative to the force.  FP64
+// uses the correctly rounded library cbrt and division.
 template <typename T>
 __device__ __forceinline__ T dj_cbrt(T x);
 template <>
-__device__ __forceinline__ float dj_cbrt<float>(float x) { return cbrtf(x); }
+__device__ __forceinline__ float dj_cbrt<float>(float x) {
+    return __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(x) * (1.0f / 3.0f));
+}
 template <>
 __device__ __forceinline__ double dj_cbrt<double>(double x) { return cbrt(x); }
+template <typename T>
+__device__ __forceinline__ T dj_rcp(T x);
+template <>
+__device__ __forceinline__ float dj_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <>
+__device__ __forceinline__ double dj_rcp<double>(double x) { return 1.0 / x; }
 
 // H8 natural coordinate (+1 / -1) of node a along direction i, node order
 // (---, +--, ++-, -+-, --+, +-+, +++, -++)
@@ -137,7 +149,7 @@ __device__ __forceinline__ T element_force(const T *__restrict__ cst, const T (&
     const T J = T(1) + Jm1;
     const T I1m3 = T(2) * trD + nD2;                          // I1 - 3 (Eq. 27)
     const T c = dj_cbrt(J);
-    const T Jm23 = T(1) / (c * c);                            // J^-2/3
+    const T Jm23 = dj_rcp(c * c);                             // J^-2/3
     const T muV = cst[P::MUV], kaV = cst[P::KAV];
     T c0 = -(muV * T(1.0 / 3.0)) * Jm23 * I1m3 + kaV * J * Jm1;  // (mu J^-2/3 + p) 0V
     T Q[3][3];
@@ -153,7 +165,7 @@ __device__ __forceinline__ T element_force(const T *__restrict__ cst, const T (&
         for (int k = 0; k < 3; k++) Dta[k] = D[0][k] * av[0] + D[1][k] * av[1] + D[2][k] * av[2];
         const T aDa = av[0] * Dta[0] + av[1] * Dta[1] + av[2] * Dta[2];
         const T I4m1 = T(2) * aDa + Dta[0] * Dta[0] + Dta[1] * Dta[1] + Dta[2] * Dta[2];  // I4 - 1 (Eq. 31)
-        const T Jm23m1 = -Jm1 * (c + T(1)) / (c * c * (c * c + c + T(1)));            // J^-2/3 - 1
+        const T Jm23m1 = -Jm1 * (c + T(1)) * dj_rcp(c * c * (c * c + c + T(1)));      // J^-2/3 - 1
         const T I4bm1 = Jm23 * I4m1 + Jm23m1;                                            // I4bar - 1
         const T psi4V = etaV * I4bm1;                                                    // eta (I4bar - 1) 0V
         c0 -= T(2.0 / 3.0) * psi4V * (T(1) + I4bm1);
@@ -163,7 +175,7 @@ __device__ __forceinline__ T element_force(const T *__restrict__ cst, const T (&
 #pragma unroll
             for (int k = 0; k < 3; k++) Q[i][k] += w * (av[i] + Dta[i]) * av[k];
     }
-    const T pJ = (c0 - muV * Jm23) / J;  // p 0V / J
+    const T pJ = (c0 - muV * Jm23) * dj_rcp(J);  // p 0V / J
     // adj(I + D)
     const T A00 = T(1) + D[0][0], A11 = T(1) + D[1][1], A22 = T(1) + D[2][2];
     T adj[3][3];
@@ -293,19 +305,27 @@ __device__ __forceinline__ void node_update(int l, uint32_t fl, const T (&f)[3],
 
 // ---------------------------------------------------------------------------
 // Chunk element phase.  Everything the chunk needs is requested in one round
-// (element planes, the chunk's node -> slot lists as 16-byte vectors, and the
-// per-copy data), then: slot lists to LDS; scatter u^n of the copies into the
-// element slots; element forces written back into the slots; node sums in
-// fixed list order.  Interior copies are finished at once (force output or
-// update); shared copies publish their partial sum into their node's group.
+// (element planes, each element's incidence positions, per-copy data).  In
+// LDS the chunk's (element, node) incidences are numbered in node-copy order,
+// so every copy owns a contiguous range: the scatter writes u^n of a copy over
+// its range, each element reads its nodes' u from (and writes its forces to)
+// its own positions, and each copy sums its contiguous range in fixed order.
+// Interior copies are finished at once (force output or update); shared
+// copies publish their partial sum into their node's group.
 // ---------------------------------------------------------------------------
+template <typename T, int KB>
+struct SharedRegs {  // round-A data of one shared copy per chunk of a batch
+    uint32_t fl[KB];
+    int pb[KB], li[KB];
+    bool ok[KB];
+    T uc[KB][3], up[KB][3], rv[KB][3], A[KB];
+};
+
 template <typename T, int NE, int MODEL, int BLOCK, int EPT, int MC>
 struct Chunk {
     static constexpr int CMAX = BLOCK * EPT;
     static constexpr int NP = Planes<NE, MODEL>::N;
-    static constexpr int NV = (NE * CMAX / 8 + BLOCK - 1) / BLOCK;  // 16-byte slot vectors per thread
-    static constexpr size_t LDS_VAL = size_t(3) * NE * CMAX * sizeof(T);
-    static constexpr size_t LDS = LDS_VAL + size_t(NE) * CMAX * sizeof(uint16_t);
+    static constexpr size_t LDS = size_t(3) * NE * CMAX * sizeof(T);
 
     // MODE 0: forces to the caller array; MODE 1: time-step update
     template <int MODE>
@@ -315,11 +335,11 @@ struct Chunk {
         T *lx = reinterpret_cast<T *>(smem);
         T *ly = lx + NE * CMAX;
         T *lz = lx + 2 * NE * CMAX;
-        uint16_t *ls = reinterpret_cast<uint16_t *>(smem + LDS_VAL);
         const T *__restrict__ ep = static_cast<const T *>(tp.elem);
         const int64_t es = tp.estride;
         // ---- one round of requests
         T cst[EPT][NP];
+        int wp[EPT][NE];
 #pragma unroll
         for (int j = 0; j < EPT; j++) {
             const int e = tid + j * BLOCK;
@@ -327,14 +347,10 @@ struct Chunk {
                 const T *src = ep + ch.elem_begin + e;
 #pragma unroll
                 for (int q = 0; q < NP; q++) cst[j][q] = __builtin_nontemporal_load(src + q * es);
-            }
-        }
-        const uint4 *sv_src = reinterpret_cast<const uint4 *>(tp.lcsr_slot + ch.slot_begin);
-        uint4 sv[NV];
+                const uint16_t *w = tp.wpos + ch.elem_begin + e;
 #pragma unroll
-        for (int v = 0; v < NV; v++) {
-            const int q = tid + v * BLOCK;
-            if (q * 8 < ch.n_slots) sv[v] = sv_src[q];
+                for (int a = 0; a < NE; a++) wp[j][a] = __builtin_nontemporal_load(w + a * es);
+            }
         }
         uint32_t cr[MC], fl[MC];
         int pb[MC];
@@ -357,11 +373,6 @@ struct Chunk {
                 }
             }
         }
-#pragma unroll
-        for (int v = 0; v < NV; v++) {
-            const int q = tid + v * BLOCK;
-            if (q * 8 < ch.n_slots) reinterpret_cast<uint4 *>(ls)[q] = sv[v];
-        }
         // loads (BC targets / forces) of interior copies, needed only at the update
         T rv[MC][3];
 #pragma unroll
@@ -375,23 +386,21 @@ struct Chunk {
                 for (int k = 0; k < 3; k++) rv[m][k] = sp.ru[k][l];
             }
         }
-        __syncthreads();
-        // ---- scatter u^n into the element slots
+        // ---- scatter u^n over each copy's contiguous incidence range
 #pragma unroll
         for (int m = 0; m < MC; m++) {
             const int i = tid + m * BLOCK;
             if (i < ch.copy_count) {
                 const int b = cr[m] & 0xffffu, n = cr[m] >> 16;
-                for (int s = b; s < b + n; s++) {
-                    const int slot = ls[s];
-                    lx[slot] = ux[m][0];
-                    ly[slot] = ux[m][1];
-                    lz[slot] = ux[m][2];
+                for (int q = b; q < b + n; q++) {
+                    lx[q] = ux[m][0];
+                    ly[q] = ux[m][1];
+                    lz[q] = ux[m][2];
                 }
             }
         }
         __syncthreads();
-        // ---- element forces, written back into the same slots
+        // ---- element forces, written back over the element's own positions
 #pragma unroll
         for (int j = 0; j < EPT; j++) {
             const int e = tid + j * BLOCK;
@@ -399,20 +408,19 @@ struct Chunk {
                 T u[NE][3], F[NE][3];
 #pragma unroll
                 for (int a = 0; a < NE; a++) {
-                    u[a][0] = lx[a * CMAX + e];
-                    u[a][1] = ly[a * CMAX + e];
-                    u[a][2] = lz[a * CMAX + e];
+                    u[a][0] = lx[wp[j][a]];
+                    u[a][1] = ly[wp[j][a]];
+                    u[a][2] = lz[wp[j][a]];
                 }
                 const T J = element_force<T, NE, MODEL>(cst[j], u, F);
-                bool fin = isfinite(J);
 #pragma unroll
                 for (int a = 0; a < NE; a++) {
-                    fin = fin && isfinite(F[a][0]) && isfinite(F[a][1]) && isfinite(F[a][2]);
-                    lx[a * CMAX + e] = F[a][0];
-                    ly[a * CMAX + e] = F[a][1];
-                    lz[a * CMAX + e] = F[a][2];
+                    lx[wp[j][a]] = F[a][0];
+                    ly[wp[j][a]] = F[a][1];
+                    lz[wp[j][a]] = F[a][2];
                 }
-                if (!fin) {
+                // a non-finite force also reaches the node sums, which are checked
+                if (!isfinite(J)) {
                     po.bad = DJ_ERR_NONFINITE;
                     po.bad_elem = ch.elem_begin + e;
                 } else if (!(J > T(0)) && po.bad == 0) {
@@ -422,18 +430,17 @@ struct Chunk {
             }
         }
         __syncthreads();
-        // ---- node sums in fixed (list) order; finish interior, publish shared
+        // ---- node sums over each copy's range, in fixed order
 #pragma unroll
         for (int m = 0; m < MC; m++) {
             const int i = tid + m * BLOCK;
             if (i < ch.copy_count) {
                 const int b = cr[m] & 0xffffu, n = cr[m] >> 16;
                 T f[3] = {T(0), T(0), T(0)};
-                for (int s = b; s < b + n; s++) {
-                    const int slot = ls[s];
-                    f[0] += lx[slot];
-                    f[1] += ly[slot];
-                    f[2] += lz[slot];
+                for (int q = b; q < b + n; q++) {
+                    f[0] += lx[q];
+                    f[1] += ly[q];
+                    f[2] += lz[q];
                 }
                 const int l = ch.copy_begin + i;
                 if (i >= ch.n_interior) {
@@ -441,6 +448,10 @@ struct Chunk {
                     st_dev(&sp.pp[0][q], f[0]);
                     st_dev(&sp.pp[1][q], f[1]);
                     st_dev(&sp.pp[2][q], f[2]);
+                    if (!(isfinite(f[0]) && isfinite(f[1]) && isfinite(f[2])) && po.bad == 0) {
+                        po.bad = DJ_ERR_NONFINITE;
+                        po.bad_elem = -1;
+                    }
                 } else if constexpr (MODE == 0) {
                     const int nd = tp.cnode[l];
                     sp.fout[3 * nd] = f[0];
@@ -454,56 +465,60 @@ struct Chunk {
         __syncthreads();  // LDS is reused by the next chunk
     }
 
-    // Shared copies of up to KB chunks: round A (copy data) for all, round B
-    // (the node's partial group) for all, then sum in rank order and finish.
+    // Round A for the shared copies of up to KB chunks (one per thread per
+    // chunk, pass `pass`): everything but the partial sums.  Issued before the
+    // grid barrier for the first batch, so its latency hides in the wait.
     template <int MODE, int KB>
-    __device__ static void shared_batch(const DevTopo &tp, const ChunkDesc *chs, int nb, int pass,
-                                        const StepPtrs<T> &sp, PhaseOut &po) {
-        constexpr int UNR = 4;
-        uint32_t fl[KB];
-        int pb[KB], li[KB];
-        bool ok[KB];
-        T uc[KB][3], up[KB][3], rv[KB][3], A[KB];
+    __device__ static void shared_load(const DevTopo &tp, const ChunkDesc *chs, int nb, int pass,
+                                       const StepPtrs<T> &sp, SharedRegs<T, KB> &r) {
 #pragma unroll
         for (int kb = 0; kb < KB; kb++) {
-            ok[kb] = false;
+            r.ok[kb] = false;
             if (kb < nb) {
                 const ChunkDesc &ch = chs[kb];
                 const int i = ch.n_interior + threadIdx.x + pass * BLOCK;
                 if (i < ch.copy_count) {
                     const int l = ch.copy_begin + i;
-                    li[kb] = l;
-                    ok[kb] = true;
-                    fl[kb] = sp.flags[l];
-                    pb[kb] = tp.pidx[l];
+                    r.li[kb] = l;
+                    r.ok[kb] = true;
+                    r.fl[kb] = sp.flags[l];
+                    r.pb[kb] = tp.pidx[l];
                     if (MODE == 1) {
-                        A[kb] = sp.acoef[l];
+                        r.A[kb] = sp.acoef[l];
 #pragma unroll
                         for (int k = 0; k < 3; k++) {
-                            uc[kb][k] = sp.uc[k][l];
-                            up[kb][k] = sp.up[k][l];
-                            rv[kb][k] = sp.ru[0] ? sp.ru[k][l] : T(0);
+                            r.uc[kb][k] = sp.uc[k][l];
+                            r.up[kb][k] = sp.up[k][l];
+                            r.rv[kb][k] = sp.ru[0] ? sp.ru[k][l] : T(0);
                         }
                     }
                 }
             }
         }
+    }
+
+    // Round B (the node's partial group) and finish: sum in rank order, then
+    // force output (MODE 0, canonical copy) or update (MODE 1).
+    template <int MODE, int KB>
+    __device__ static void shared_finish(const DevTopo &tp, SharedRegs<T, KB> &r, const StepPtrs<T> &sp,
+                                         PhaseOut &po) {
+        constexpr int UNR = 4;
         T px[KB][UNR][3];
 #pragma unroll
         for (int kb = 0; kb < KB; kb++) {
-            if (ok[kb]) {
-                const int cnt = (fl[kb] >> FLAG_NCOPY_SHIFT) & 255u;
+            if (r.ok[kb]) {
+                const int cnt = (r.fl[kb] >> FLAG_NCOPY_SHIFT) & 255u;
 #pragma unroll
                 for (int q = 0; q < UNR; q++)
                     if (q < cnt)
 #pragma unroll
-                        for (int k = 0; k < 3; k++) px[kb][q][k] = ld_dev(&sp.pp[k][pb[kb] + q]);
+                        for (int k = 0; k < 3; k++) px[kb][q][k] = ld_dev(&sp.pp[k][r.pb[kb] + q]);
             }
         }
 #pragma unroll
         for (int kb = 0; kb < KB; kb++) {
-            if (!ok[kb]) continue;
-            const int cnt = (fl[kb] >> FLAG_NCOPY_SHIFT) & 255u;
+            if (!r.ok[kb]) continue;
+            const int cnt = (r.fl[kb] >> FLAG_NCOPY_SHIFT) & 255u;
             T f[3] = {T(0), T(0), T(0)};
 #pragma unroll
             for (int q = 0; q < UNR; q++)
@@ -512,21 +527,35 @@ struct Chunk {
                     for (int k = 0; k < 3; k++) f[k] += px[kb][q][k];
             for (int q = UNR; q < cnt; q++)
 #pragma unroll
-                for (int k = 0; k < 3; k++) f[k] += ld_dev(&sp.pp[k][pb[kb] + q]);
-            const int l = li[kb];
+                for (int k = 0; k < 3; k++) f[k] += ld_dev(&sp.pp[k][r.pb[kb] + q]);
+            const int l = r.li[kb];
             if constexpr (MODE == 0) {
-                if (fl[kb] & FLAG_CANON) {
+                if (r.fl[kb] & FLAG_CANON) {
                     const int nd = tp.cnode[l];
                     sp.fout[3 * nd] = f[0];
                     sp.fout[3 * nd + 1] = f[1];
                     sp.fout[3 * nd + 2] = f[2];
                 }
             } else {
-                if (!(fl[kb] & FLAG_RU))
+                if (!(r.fl[kb] & FLAG_RU))
 #pragma unroll
-                    for (int k = 0; k < 3; k++) rv[kb][k] = T(0);
-                node_update<T>(l, fl[kb], f, uc[kb], up[kb], A[kb], rv[kb], sp, po);
+                    for (int k = 0; k < 3; k++) r.rv[kb][k] = T(0);
+                node_update<T>(l, r.fl[kb], f, r.uc[kb], r.up[kb], r.A[kb], r.rv[kb], sp, po);
             }
+        }
+    }
+
+    // all passes of one batch of chunks
+    template <int MODE, int KB>
+    __device__ static void shared_batch(const DevTopo &tp, const ChunkDesc *chs, int nb, int first_pass,
+                                        const StepPtrs<T> &sp, PhaseOut &po) {
+        for (int pass = first_pass;; pass++) {
+            bool more = false;
+            for (int kb = 0; kb < nb; kb++) more |= chs[kb].n_interior + pass * BLOCK < chs[kb].copy_count;
+            if (!more) break;
+            SharedRegs<T, KB> r;
+            shared_load<MODE, KB>(tp, chs, nb, pass, sp, r);
+            shared_finish<MODE, KB>(tp, r, sp, po);
         }
     }
 };
@@ -653,8 +682,7 @@ __global__ void __launch_bounds__(BLOCK) k_forces_shared(DevTopo tp, StepPtrs<T>
     using C = Chunk<T, NE, MODEL, BLOCK, EPT, MC>;
     PhaseOut po{0.0, 0.0, 0, -1};
     const ChunkDesc ch = tp.chunks[blockIdx.x];
-    for (int pass = 0; ch.n_interior + pass * BLOCK < ch.copy_count; pass++)
-        C::template shared_batch<0, 1>(tp, &ch, 1, pass, sp, po);
+    C::template shared_batch<0, 1>(tp, &ch, 1, 0, sp, po);
 }
 
 // The persistent multi-step kernel: n_steps x {element phase of every owned
@@ -707,6 +735,9 @@ __global__ void __launch_bounds__(BLOCK) k_step(DevTopo tp, StepArgs a) {
         sp.fout = nullptr;
         PhaseOut po{0.0, 0.0, 0, -1};
         for (int k = 0; k < nmine; k++) C::template element_phase<1>(tp, s_ch[k], sp, smem, po);
+        // round A of the first batch of shared copies, in flight during the barrier
+        SharedRegs<T, KB> sr;
+        C::template shared_load<1, KB>(tp, s_ch, min(KB, nmine), 0, sp, sr);
         // Errors of step s go to the error word of parity s & 1, which nobody
         // writes again before every workgroup has read it after this barrier.
         int32_t *errw = &a.status[5 + (s & 1)];
@@ -726,15 +757,9 @@ __global__ void __launch_bounds__(BLOCK) k_step(DevTopo tp, StepArgs a) {
             code = s_flag;
             break;
         }
-        for (int k0 = 0; k0 < nmine; k0 += KB) {
-            const int nb = min(KB, nmine - k0);
-            for (int pass = 0;; pass++) {
-                bool more = false;
-                for (int kb = 0; kb < nb; kb++) more |= s_ch[k0 + kb].n_interior + pass * BLOCK < s_ch[k0 + kb].copy_count;
-                if (!more) break;
-                C::template shared_batch<1, KB>(tp, s_ch + k0, nb, pass, sp, po);
-            }
-        }
+        C::template shared_finish<1, KB>(tp, sr, sp, po);
+        for (int k0 = 0; k0 < nmine; k0 += KB)
+            C::template shared_batch<1, KB>(tp, s_ch + k0, min(KB, nmine - k0), k0 == 0 ? 1 : 0, sp, po);
         if (check) {
             double x = po.num, y = po.den;
             block_sum2<BLOCK>(x, y, sred);

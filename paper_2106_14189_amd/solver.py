@@ -60,6 +60,7 @@ class Solver:
     def __init__(self, X, conn, E, nu, model=L.DJ_NH, rho=1000.0, eta_ratio=None, fibre=None, hg_kappa=0.1,
                  precision="fp32", dt=0.0, dt_factor=0.9, alpha=0.0, chunk_elems=0, variant=0, device=0,
                  allow_unstable_dt=False):
+        torch.cuda.init()
         self.X = np.ascontiguousarray(X, dtype=np.float64)
         self.conn = np.ascontiguousarray(conn, dtype=np.int32)
         self.n_nodes, self.n_elems = self.X.shape[0], self.conn.shape[0]
