@@ -192,6 +192,81 @@ int djtled_step(djtled_ctx *ctx, djtled_state *state, const djtled_loadset *load
  */
 int djtled_export_constants(djtled_ctx *ctx, double *V, double *dhdX, double *mass);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent meshes ("instances") of uneven sizes advanced
+ * together.  Each instance is a mesh + material + load case as above, with its
+ * own critical step (dt = dt_factor x its Eq. 14 bound), its own damping and
+ * its own ramp; all instances take the same number of steps per run.  The
+ * instances of each element kind ((T4 | H8) x (NH | TI)) are laid out side by
+ * side, and every run advances all of them with ONE persistent kernel (one
+ * grid barrier per step for the whole batch), replayed from a captured
+ * hipGraph.  The batch owns the state of every instance (initially u = 0 at
+ * step 0).  External forces R are not supported in batches (loads[i].R must be
+ * NULL); all instances of a kind share rho and hg_kappa.  In a batch, a
+ * negative loads[i].t_ramp means a ramp of |t_ramp| steps of the instance's
+ * own dt.
+ * ------------------------------------------------------------------------ */
+typedef struct djtled_batch djtled_batch;
+
+typedef struct {
+    int32_t autotune;          /* nonzero: choose variant, chunk size and steps per launch by timing
+                                  candidates on a sample of the instances */
+    int32_t variant;           /* batch kernel variant when not tuning (FP32: 0..3, FP64: 0); <0 -> default */
+    int32_t chunk_elems;       /* elements per workgroup tile when not tuning; 0 -> kernel capacity */
+    int32_t steps_per_launch;  /* persistent-launch length inside a run; 0 -> the whole run */
+    int32_t use_graph;         /* nonzero: each run replays a captured hipGraph */
+    int32_t tune_steps;        /* steps timed per candidate; 0 -> 20 */
+} djtled_tune;
+
+typedef struct {
+    int32_t n_inst, n_kinds, n_items, grid_blocks, block_threads, variant, chunk_elems, steps_per_launch;
+    int32_t graph;             /* 1: the last run replayed a hipGraph */
+    int32_t tune_candidates;   /* candidates timed by the autotuner (0: not tuned) */
+    int64_t n_elems, n_nodes;  /* totals over the instances */
+    double bytes_per_step;     /* algorithmic HBM bytes of one batch step */
+    double tune_ms;            /* host wall time spent autotuning */
+    int32_t error_inst;        /* instance of the last run-time error, else -1 */
+} djtled_batch_info_t;
+
+/*
+ * djtled_batch_create -- pre-computation (as djtled_precompute) of n instances
+ * and the batch's work list.  meshes/materials/loads: n entries each (host);
+ * alpha: n damping coefficients or NULL (-> params->alpha); params: precision,
+ * dt_factor (dt must be 0), allow_unstable_dt, device; tune may be NULL.
+ * Errors: DJ_ERR_ARG, DJ_ERR_BAD_MESH, DJ_ERR_UNSUPPORTED, DJ_ERR_UNSTABLE_DT, DJ_ERR_HIP.
+ */
+int djtled_batch_create(int32_t n, const djtled_mesh *meshes, const djtled_material *materials,
+                        const djtled_loads *loads, const double *alpha, const djtled_params *params,
+                        const djtled_tune *tune, djtled_batch **out);
+int djtled_batch_destroy(djtled_batch *b);
+int djtled_batch_info(const djtled_batch *b, djtled_batch_info_t *out);
+
+/* Per-instance sizes and step (n_nodes, n_elems, elem_type, model, precision, dt, dt_crit, alpha). */
+int djtled_batch_instance(const djtled_batch *b, int32_t inst, djtled_info_t *out);
+
+/*
+ * djtled_batch_run -- n_steps explicit steps of Eq. 13 for every instance
+ * (forces of Table 3 -> node sums -> central difference with damping -> BCs
+ * ramped per instance).  out->kernel_ms: device time of the run;
+ * out->error_elem: caller element (within djtled_batch_info's error_inst) of a
+ * DJ_ERR_INVERTED.  On an error every instance stops at the last completed
+ * step.  Synchronises `stream`.
+ */
+int djtled_batch_run(djtled_batch *b, int32_t n_steps, djtled_status *out, void *stream);
+
+/* Device time from the start of the last run to the end of each instance's
+   last step (instance order), from per-workgroup time stamps [ms]. */
+int djtled_batch_stats(const djtled_batch *b, double *inst_ms);
+
+/* Copy the state (u^n, u^{n-1}; device, n_nodes x 3 of the instance, caller
+   node order, batch precision) of one instance out of / into the batch.
+   u_prev may be NULL (read: skipped; write: u^{n-1} = u^n).  Asynchronous. */
+int djtled_batch_read(djtled_batch *b, int32_t inst, void *u_cur, void *u_prev, void *stream);
+int djtled_batch_write(djtled_batch *b, int32_t inst, const void *u_cur, const void *u_prev, void *stream);
+
+/* Every instance back to u = 0 at step 0. */
+int djtled_batch_reset(djtled_batch *b, void *stream);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *djtled_last_error(void);
 

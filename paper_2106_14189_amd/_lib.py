@@ -81,6 +81,33 @@ class djtled_status(ctypes.Structure):
                 ("error_elem", ctypes.c_int32), ("residual", ctypes.c_double), ("kernel_ms", ctypes.c_double)]
 
 
+class djtled_tune(ctypes.Structure):
+    _fields_ = [("autotune", ctypes.c_int32), ("variant", ctypes.c_int32), ("chunk_elems", ctypes.c_int32),
+                ("steps_per_launch", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("tune_steps", ctypes.c_int32)]
+
+
+class djtled_batch_info_t(ctypes.Structure):
+    _fields_ = [("n_inst", ctypes.c_int32), ("n_kinds", ctypes.c_int32), ("n_items", ctypes.c_int32),
+                ("grid_blocks", ctypes.c_int32), ("block_threads", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("chunk_elems", ctypes.c_int32), ("steps_per_launch", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("tune_candidates", ctypes.c_int32), ("n_elems", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
+                ("bytes_per_step", ctypes.c_double), ("tune_ms", ctypes.c_double), ("error_inst", ctypes.c_int32)]
+
+
+_fp = ctypes.POINTER(ctypes.c_float)
+_u16p = ctypes.POINTER(ctypes.c_uint16)
+
+
+class djtled_mlp(ctypes.Structure):
+    _fields_ = [("n_in", ctypes.c_int32), ("n_hidden", ctypes.c_int32), ("n_out", ctypes.c_int32),
+                ("ld_out", ctypes.c_int32), ("W1", _vp), ("b1", _vp), ("W2", _vp), ("b2", _vp), ("W3", _vp),
+                ("b3", _vp), ("W1_bf16", _vp), ("W2_bf16", _vp), ("W3_bf16", _vp)]
+
+
+class djtled_mlp_grads(ctypes.Structure):
+    _fields_ = [("W1", _vp), ("b1", _vp), ("W2", _vp), ("b2", _vp), ("W3", _vp), ("b3", _vp)]
+
+
 EXPORTS = {
     "djtled_precompute": (ctypes.c_int, [ctypes.POINTER(djtled_mesh), ctypes.POINTER(djtled_material),
                                          ctypes.POINTER(djtled_params), ctypes.POINTER(_vp)]),
@@ -93,6 +120,33 @@ EXPORTS = {
                                    ctypes.POINTER(djtled_step_opts), ctypes.POINTER(djtled_status), _vp]),
     "djtled_export_constants": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
     "djtled_last_error": (ctypes.c_char_p, []),
+    "djtled_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(djtled_mesh), ctypes.POINTER(djtled_material),
+                                           ctypes.POINTER(djtled_loads), _dp, ctypes.POINTER(djtled_params),
+                                           ctypes.POINTER(djtled_tune), ctypes.POINTER(_vp)]),
+    "djtled_batch_destroy": (ctypes.c_int, [_vp]),
+    "djtled_batch_info": (ctypes.c_int, [_vp, ctypes.POINTER(djtled_batch_info_t)]),
+    "djtled_batch_instance": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(djtled_info_t)]),
+    "djtled_batch_run": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(djtled_status), _vp]),
+    "djtled_batch_stats": (ctypes.c_int, [_vp, _dp]),
+    "djtled_batch_read": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp]),
+    "djtled_batch_write": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp]),
+    "djtled_batch_reset": (ctypes.c_int, [_vp, _vp]),
+    "djtled_mlp_workspace_size": (ctypes.c_int, [ctypes.POINTER(djtled_mlp), ctypes.c_int32,
+                                                 ctypes.POINTER(ctypes.c_size_t)]),
+    "djtled_mlp_forward": (ctypes.c_int, [ctypes.POINTER(djtled_mlp), ctypes.c_int32, _vp, _vp, _vp, ctypes.c_size_t,
+                                          _vp]),
+    "djtled_mlp_loss_grad": (ctypes.c_int, [ctypes.POINTER(djtled_mlp), ctypes.c_int32, _vp, _vp,
+                                            ctypes.POINTER(djtled_mlp_grads), ctypes.POINTER(ctypes.c_double), _vp,
+                                            ctypes.c_size_t, _vp]),
+    "djtled_mlp_adam": (ctypes.c_int, [ctypes.POINTER(djtled_mlp), ctypes.POINTER(djtled_mlp_grads),
+                                       ctypes.POINTER(djtled_mlp_grads), ctypes.POINTER(djtled_mlp_grads),
+                                       ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                       _vp]),
+    "djtled_mlp_sync_bf16": (ctypes.c_int, [ctypes.POINTER(djtled_mlp), _vp]),
+    "djtled_mlp_gemm_test": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int64,
+                                            ctypes.c_int32, _vp, ctypes.c_int64, ctypes.c_int32, _vp, ctypes.c_int64,
+                                            ctypes.c_int32, _vp]),
+    "djtled_mlp_last_error": (ctypes.c_char_p, []),
 }
 
 
@@ -113,7 +167,8 @@ lib = load()
 class DJError(RuntimeError):
     def __init__(self, code: int, where: str):
         self.code = code
-        msg = lib.djtled_last_error().decode(errors="replace")
+        err = lib.djtled_mlp_last_error if where.startswith("djtled_mlp") else lib.djtled_last_error
+        msg = err().decode(errors="replace")
         super().__init__(f"{where}: {ERROR_NAMES.get(code, code)}: {msg}")
 
 

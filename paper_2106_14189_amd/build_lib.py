@@ -8,7 +8,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdjtled.so")
-SOURCES = ["djtled_api.cpp", "djtled_kernels.hip"]
+SOURCES = ["djtled_api.cpp", "djtled_batch.cpp", "djtled_kernels.hip", "djtled_batch_kernels.hip",
+           "djtled_mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # packed-FP32 instructions are disabled for every HIP translation unit

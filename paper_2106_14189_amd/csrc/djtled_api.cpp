@@ -17,7 +17,7 @@
 
 using namespace dj;
 
-namespace {
+namespace dj {
 
 thread_local std::string g_err;
 
@@ -26,11 +26,9 @@ int fail(int code, const std::string &msg) {
     return code;
 }
 
-#define DJ_HIP(call)                                                                                   \
-    do {                                                                                               \
-        hipError_t e_ = (call);                                                                        \
-        if (e_ != hipSuccess) return fail(DJ_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
-    } while (0)
+}  // namespace dj
+
+namespace {
 
 template <typename T>
 hipError_t dalloc(Ctx &c, T **p, size_t n) {
@@ -51,6 +49,10 @@ hipError_t upload(Ctx &c, T **p, const std::vector<T> &v) {
     return e;
 }
 
+}  // namespace
+
+namespace dj {
+
 void free_all(Ctx *c) {
     if (!c) return;
     hipSetDevice(c->device);
@@ -59,6 +61,7 @@ void free_all(Ctx *c) {
         LoadSet *ls = static_cast<LoadSet *>(p);
         hipFree(ls->d_flags);
         hipFree(ls->d_ru);
+        hipFree(ls->d_rate);
         delete ls;
     }
     for (void *p : c->allocs) hipFree(p);
@@ -68,6 +71,10 @@ void free_all(Ctx *c) {
     if (c->h_res) hipHostFree(c->h_res);
     delete c;
 }
+
+}  // namespace dj
+
+namespace {
 
 // 21-bit spread for 3-D Morton codes
 uint64_t spread3(uint64_t x) {
@@ -97,8 +104,27 @@ struct TempBufs {
     }
 };
 
-int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djtled_params *prm) {
+}  // namespace
+
+namespace dj {
+
+int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djtled_params *prm,
+          const MultiInst *mi) {
     const int N = mesh->n_nodes, E = mesh->n_elems, NE = mesh->elem_type;
+    const int NI = mi ? mi->n_inst : 1;
+    c.n_inst = NI;
+    std::vector<int32_t> einst_c(E, 0), ninst_c(N, 0);  // instance of each caller element / node
+    if (mi) {
+        for (int i = 0; i < NI; i++) {
+            for (int e = mi->elem_off[i]; e < mi->elem_off[i + 1]; e++) einst_c[e] = i;
+            for (int n = mi->node_off[i]; n < mi->node_off[i + 1]; n++) ninst_c[n] = i;
+        }
+        c.inst_node_off.assign(mi->node_off, mi->node_off + NI + 1);
+        c.inst_elem_off.assign(mi->elem_off, mi->elem_off + NI + 1);
+    } else {
+        c.inst_node_off = {0, N};
+        c.inst_elem_off = {0, E};
+    }
     c.n_nodes = N;
     c.n_elems = E;
     c.ne = NE;
@@ -138,7 +164,10 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     }
     c.elem_perm.resize(E);
     std::iota(c.elem_perm.begin(), c.elem_perm.end(), 0);
-    std::stable_sort(c.elem_perm.begin(), c.elem_perm.end(), [&](int a, int b) { return code[a] < code[b]; });
+    // instances stay contiguous (a chunk then rarely spans two of them)
+    std::stable_sort(c.elem_perm.begin(), c.elem_perm.end(), [&](int a, int b) {
+        return einst_c[a] != einst_c[b] ? einst_c[a] < einst_c[b] : code[a] < code[b];
+    });
     std::vector<int32_t> node_new(N, -1);
     c.node_perm.clear();
     c.node_perm.reserve(N);
@@ -203,12 +232,13 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     std::vector<std::vector<int32_t>> node_copies(N);
     int max_copies = 0;
     for (int attempt = 0;; attempt++) {
+    const bool in_batch = mi && mi->batch;
     nch = (E + C - 1) / C;
-    if (nch > gmax) nch = (nch + gmax - 1) / gmax * gmax;  // whole rounds of the resident grid
+    if (nch > gmax && !in_batch) nch = (nch + gmax - 1) / gmax * gmax;  // whole rounds of the resident grid
     if (nch > E) nch = E;
     c.chunk_elems = int((E + nch - 1) / nch);
     c.grid = int(std::min<int64_t>(nch, gmax));
-    if ((nch + c.grid - 1) / c.grid > 32)
+    if (!in_batch && (nch + c.grid - 1) / c.grid > 32)
         return fail(DJ_ERR_UNSUPPORTED, "mesh needs more than 32 chunks per workgroup; use a larger variant");
     chunks.assign(nch, ChunkDesc{});
     crange.clear();
@@ -296,6 +326,11 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     c.n_shared_copies = n_part;
     c.h_flags = flags;
     c.h_copy_node = copy_node;
+    c.h_chunk_elem.resize(2 * size_t(nch));
+    for (int64_t ch = 0; ch < nch; ch++) {
+        c.h_chunk_elem[2 * ch] = chunks[ch].elem_begin;
+        c.h_chunk_elem[2 * ch + 1] = chunks[ch].elem_count;
+    }
 
     // ---- device buffers
     const size_t ts = c.prec == DJ_FP32 ? 4 : 8;
@@ -337,7 +372,7 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
         DJ_HIP(dalloc(c, &p, 3 * L * ts));
         c.d_ubuf[b] = p;
     }
-    DJ_HIP(dalloc(c, &p, 6 * size_t(std::max(n_part, 1)) * ts));
+    DJ_HIP(dalloc(c, &p, 6 * size_t(std::max(n_part, 1)) * ts));  // 2 parities x 3 planes
     c.d_part = p;
     DJ_HIP(dalloc(c, &c.d_bar, size_t(c.grid + 16) * 32));  // barrier flags, one 128-B line each
     DJ_HIP(dalloc(c, &c.d_status, 8));
@@ -383,22 +418,54 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
         DJ_HIP(tb.up(&dfib, fibi));
     }
     const double inf = std::numeric_limits<double>::infinity();
-    DJ_HIP(tb.up(&ddt, std::vector<double>{inf}));
+    int32_t *dei = nullptr;
+    if (NI > 1) {
+        std::vector<int32_t> ei(E);
+        for (int e = 0; e < E; e++) ei[e] = einst_c[c.elem_perm[e]];
+        DJ_HIP(tb.up(&dei, ei));
+    }
+    DJ_HIP(tb.up(&ddt, std::vector<double>(NI, inf)));
     DJ_HIP(tb.up(&dbad, std::vector<int32_t>{0}));
     DJ_HIP(tb.up(&dneoff, ne_off));
     DJ_HIP(tb.up(&dnelist, ne_list));
-    DJ_HIP(launch_precompute(c, dX, dconn, dE, dnu, deta, dfib, ddt, dbad, nullptr));
+    DJ_HIP(launch_precompute(c, dX, dconn, dE, dnu, deta, dfib, dei, ddt, dbad, nullptr));
     int32_t bad = 0;
-    double dtc = 0;
+    std::vector<double> dtc(NI);
     DJ_HIP(hipMemcpy(&bad, dbad, sizeof(int32_t), hipMemcpyDeviceToHost));
-    DJ_HIP(hipMemcpy(&dtc, ddt, sizeof(double), hipMemcpyDeviceToHost));
+    DJ_HIP(hipMemcpy(dtc.data(), ddt, NI * sizeof(double), hipMemcpyDeviceToHost));
     if (bad) return fail(DJ_ERR_BAD_MESH, std::to_string(bad) + " element(s) with det(0J) <= 0 or zero fibre");
-    c.dt_crit = dtc;
     const double fac = prm->dt_factor > 0 ? prm->dt_factor : 0.9;
-    c.dt = prm->dt > 0 ? prm->dt : fac * dtc;
-    if (c.dt > dtc && !prm->allow_unstable_dt)
-        return fail(DJ_ERR_UNSTABLE_DT, "dt " + std::to_string(c.dt) + " exceeds the critical step " + std::to_string(dtc));
-    DJ_HIP(launch_mass_acoef(c, dneoff, dnelist, nullptr));
+    c.inst_dt.resize(NI);
+    c.inst_dt_crit = dtc;
+    c.inst_alpha.assign(NI, prm->alpha);
+    for (int i = 0; i < NI; i++) {
+        if (!(dtc[i] < inf)) return fail(DJ_ERR_BAD_MESH, "instance " + std::to_string(i) + " has no elements");
+        if (mi && mi->alpha) c.inst_alpha[i] = mi->alpha[i];
+        c.inst_dt[i] = prm->dt > 0 ? prm->dt : fac * dtc[i];
+        if (c.inst_dt[i] > dtc[i] && !prm->allow_unstable_dt)
+            return fail(DJ_ERR_UNSTABLE_DT, "dt " + std::to_string(c.inst_dt[i]) + " exceeds the critical step " +
+                                                std::to_string(dtc[i]) + (NI > 1 ? " of instance " + std::to_string(i) : ""));
+    }
+    c.dt_crit = *std::min_element(dtc.begin(), dtc.end());
+    c.dt = c.inst_dt[0];
+    double *dc2 = nullptr, *dbpn = nullptr;
+    if (NI > 1 || (mi && mi->batch)) {  // the batch kernel always reads B' per copy
+        // per-node coefficients of the node's instance; B' per copy
+        std::vector<double> c2n(N), bpn(N);
+        for (int n = 0; n < N; n++) {
+            const int i = ninst_c[c.node_perm[n]];
+            const double dt = c.inst_dt[i], al = c.inst_alpha[i];
+            c2n[n] = 2.0 * dt * dt / (2.0 + al * dt);
+            bpn[n] = (2.0 - al * dt) / (2.0 + al * dt);
+        }
+        DJ_HIP(tb.up(&dc2, c2n));
+        DJ_HIP(tb.up(&dbpn, bpn));
+        unsigned char *pb;
+        DJ_HIP(dalloc(c, &pb, size_t(L) * ts));
+        c.d_bpc = pb;
+        c.topo.bpc = pb;
+    }
+    DJ_HIP(launch_mass_acoef(c, dneoff, dnelist, dc2, dbpn, nullptr));
     std::vector<double> m(N);
     DJ_HIP(hipMemcpy(m.data(), c.d_mass64, N * sizeof(double), hipMemcpyDeviceToHost));
     c.mass_total = std::accumulate(m.begin(), m.end(), 0.0);
@@ -408,8 +475,9 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     //   elements : NP planes + NE incidence positions (uint16)
     //   interior copies : slot range, flags, u^n, u^{n-1}, A (read), u^{n+1} (write)
     //   shared copies   : slot range, flags, partial index, u^n (element phase);
-    //                     partial write; then flags, partial index, A, u^n, u^{n-1},
-    //                     the node's cnt partials (read) and u^{n+1} (write)
+    //                     partial write (3 values); then flags, partial
+    //                     index, A, u^n, u^{n-1}, the node's cnt slots (read) and
+    //                     u^{n+1} (write)
     double eb = double(NP) * ts + 2.0 * NE;
     double interior = 0, shared = 0;
     for (int64_t l = 0; l < L; l++) {
@@ -425,7 +493,65 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     return DJ_OK;
 }
 
-}  // namespace
+// node_rate (batches): per caller node, the signed ramp rate of its instance
+// (see ramp_rate in the kernels); null for a single instance.
+int make_loadset(Ctx &c, const djtled_loads *ld, const double *node_rate, LoadSet **out) {
+    *out = nullptr;
+    if (ld->n_bc < 0 || (ld->n_bc > 0 && (!ld->bc_node || !ld->bc_mask || !ld->bc_target)))
+        return fail(DJ_ERR_ARG, "bad boundary-condition arrays");
+    if (ld->ramp < DJ_RAMP_NONE || ld->ramp > DJ_RAMP_SMOOTH || !(ld->t_ramp >= 0))
+        return fail(DJ_ERR_ARG, "bad ramp");
+    std::vector<int32_t> bc_of(c.n_nodes, -1);
+    for (int j = 0; j < ld->n_bc; j++) {
+        const int n = ld->bc_node[j];
+        if (n < 0 || n >= c.n_nodes) return fail(DJ_ERR_ARG, "boundary-condition node out of range");
+        if (ld->bc_mask[j] & ~7) return fail(DJ_ERR_ARG, "boundary-condition mask must be within 0..7");
+        bc_of[n] = j;
+    }
+    const int64_t L = c.topo.n_copies;
+    std::vector<uint32_t> fl(c.h_flags);
+    std::vector<double> ru(3 * L, 0.0), rate(node_rate ? L : 0, 0.0);
+    for (int64_t l = 0; l < L; l++) {
+        const int n = c.node_perm[c.h_copy_node[l]];
+        const int j = bc_of[n];
+        const uint32_t mask = j >= 0 ? uint32_t(ld->bc_mask[j]) : 0u;
+        if (mask == 0 && !ld->R) continue;
+        fl[l] |= mask | FLAG_RU;
+        if (node_rate) rate[l] = node_rate[n];
+        for (int k = 0; k < 3; k++)
+            ru[k * L + l] = ((mask >> k) & 1u) ? ld->bc_target[3 * j + k] : (ld->R ? ld->R[3 * size_t(n) + k] : 0.0);
+    }
+    LoadSet *ls = new LoadSet();
+    ls->ctx = &c;
+    ls->ramp = ld->ramp;
+    ls->t_ramp = ld->t_ramp;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&ls->d_flags), L * sizeof(uint32_t));
+    const size_t ts = c.prec == DJ_FP32 ? 4 : 8;
+    if (e == hipSuccess) e = hipMalloc(&ls->d_ru, 3 * L * ts);
+    if (e == hipSuccess) e = hipMemcpy(ls->d_flags, fl.data(), L * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && node_rate) e = hipMalloc(&ls->d_rate, L * ts);
+    auto put = [&](void *dst, const std::vector<double> &v) {
+        if (c.prec == DJ_FP32) {
+            std::vector<float> rf(v.begin(), v.end());
+            return hipMemcpy(dst, rf.data(), rf.size() * 4, hipMemcpyHostToDevice);
+        }
+        return hipMemcpy(dst, v.data(), v.size() * 8, hipMemcpyHostToDevice);
+    };
+    if (e == hipSuccess) e = put(ls->d_ru, ru);
+    if (e == hipSuccess && node_rate) e = put(ls->d_rate, rate);
+    if (e != hipSuccess) {
+        hipFree(ls->d_flags);
+        hipFree(ls->d_ru);
+        hipFree(ls->d_rate);
+        delete ls;
+        return fail(DJ_ERR_HIP, std::string("loadset upload: ") + hipGetErrorString(e));
+    }
+    c.loadsets.push_back(ls);
+    *out = ls;
+    return DJ_OK;
+}
+
+}  // namespace dj
 
 extern "C" {
 
@@ -516,54 +642,11 @@ int djtled_loadset_create(djtled_ctx *ctx, const djtled_loads *ld, djtled_loadse
     if (!ctx || !ld || !out) return fail(DJ_ERR_ARG, "null argument");
     *out = nullptr;
     Ctx &c = *reinterpret_cast<Ctx *>(ctx);
-    if (ld->n_bc < 0 || (ld->n_bc > 0 && (!ld->bc_node || !ld->bc_mask || !ld->bc_target)))
-        return fail(DJ_ERR_ARG, "bad boundary-condition arrays");
-    if (ld->ramp < DJ_RAMP_NONE || ld->ramp > DJ_RAMP_SMOOTH || !(ld->t_ramp >= 0))
-        return fail(DJ_ERR_ARG, "bad ramp");
-    std::vector<int32_t> bc_of(c.n_nodes, -1);
-    for (int j = 0; j < ld->n_bc; j++) {
-        const int n = ld->bc_node[j];
-        if (n < 0 || n >= c.n_nodes) return fail(DJ_ERR_ARG, "boundary-condition node out of range");
-        if (ld->bc_mask[j] & ~7) return fail(DJ_ERR_ARG, "boundary-condition mask must be within 0..7");
-        bc_of[n] = j;
-    }
-    const int64_t L = c.topo.n_copies;
-    std::vector<uint32_t> fl(c.h_flags);
-    std::vector<double> ru(3 * L, 0.0);
-    for (int64_t l = 0; l < L; l++) {
-        const int n = c.node_perm[c.h_copy_node[l]];
-        const int j = bc_of[n];
-        const uint32_t mask = j >= 0 ? uint32_t(ld->bc_mask[j]) : 0u;
-        if (mask == 0 && !ld->R) continue;
-        fl[l] |= mask | FLAG_RU;
-        for (int k = 0; k < 3; k++)
-            ru[k * L + l] = ((mask >> k) & 1u) ? ld->bc_target[3 * j + k] : (ld->R ? ld->R[3 * size_t(n) + k] : 0.0);
-    }
-    LoadSet *ls = new LoadSet();
-    ls->ctx = &c;
-    ls->ramp = ld->ramp;
-    ls->t_ramp = ld->t_ramp;
-    hipError_t e = hipMalloc(reinterpret_cast<void **>(&ls->d_flags), L * sizeof(uint32_t));
-    const size_t ts = c.prec == DJ_FP32 ? 4 : 8;
-    if (e == hipSuccess) e = hipMalloc(&ls->d_ru, 3 * L * ts);
-    if (e == hipSuccess) e = hipMemcpy(ls->d_flags, fl.data(), L * sizeof(uint32_t), hipMemcpyHostToDevice);
-    if (e == hipSuccess) {
-        if (c.prec == DJ_FP32) {
-            std::vector<float> rf(ru.begin(), ru.end());
-            e = hipMemcpy(ls->d_ru, rf.data(), rf.size() * 4, hipMemcpyHostToDevice);
-        } else {
-            e = hipMemcpy(ls->d_ru, ru.data(), ru.size() * 8, hipMemcpyHostToDevice);
-        }
-    }
-    if (e != hipSuccess) {
-        hipFree(ls->d_flags);
-        hipFree(ls->d_ru);
-        delete ls;
-        return fail(DJ_ERR_HIP, std::string("loadset upload: ") + hipGetErrorString(e));
-    }
-    c.loadsets.push_back(ls);
-    *out = reinterpret_cast<djtled_loadset *>(ls);
-    return DJ_OK;
+    DJ_HIP(hipSetDevice(c.device));
+    LoadSet *ls = nullptr;
+    const int rc = make_loadset(c, ld, nullptr, &ls);
+    if (rc == DJ_OK) *out = reinterpret_cast<djtled_loadset *>(ls);
+    return rc;
 }
 
 int djtled_loadset_destroy(djtled_loadset *p) {
@@ -576,6 +659,7 @@ int djtled_loadset_destroy(djtled_loadset *p) {
     hipDeviceSynchronize();
     hipFree(ls->d_flags);
     hipFree(ls->d_ru);
+    hipFree(ls->d_rate);
     delete ls;
     return DJ_OK;
 }

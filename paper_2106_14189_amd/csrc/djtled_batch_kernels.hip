@@ -1,0 +1,302 @@
+// Batched DJ-TLED: many independent meshes (instances) of up to four element
+// kinds -- (T4 | H8) x (neo-Hookean | transversely isotropic) -- advanced
+// together by ONE persistent kernel with one grid barrier per step.
+//
+// Each kind is a multi-instance context (its instances' elements and node
+// copies side by side, every instance with its own time step, damping and
+// ramp through per-copy coefficients).  The batch's work list holds every
+// chunk of every kind, sorted by kind and dealt round-robin to the resident
+// workgroups, so each workgroup sees a similar mix and its chunks of one kind
+// are consecutive.  A workgroup runs the element phase of each of its chunks
+// with the element code of the chunk's kind, then after the barrier the
+// shared-node phase in batches of chunks of one kind.
+//
+// The step index and the current state buffer live in device memory and are
+// advanced by the kernel, so a captured graph of launches can be replayed.
+#include "djtled_device.h"
+#include "djtled_batch.h"
+
+namespace dj {
+
+namespace {
+
+constexpr int KMAXB = 64;  // work items per workgroup
+
+template <typename T, int V>
+struct Kinds {
+    static constexpr Variant v4 = var_table<T, 4>()[V];
+    static constexpr Variant v8 = var_table<T, 8>()[V];
+    static_assert(v4.block == v8.block, "one block size for all element kinds");
+    static constexpr int BLOCK = v4.block;
+    template <int K>
+    using C = Chunk<T, (K >= 2 ? 8 : 4), (K & 1) ? DJ_TI : DJ_NH, BLOCK, (K >= 2 ? v8.ept : v4.ept),
+                    (K >= 2 ? v8.mcopy : v4.mcopy), true>;
+    static constexpr size_t LDS = C<0>::LDS > C<2>::LDS ? C<0>::LDS : C<2>::LDS;
+};
+
+template <typename F>
+__device__ __forceinline__ void on_kind(int kind, F &&f) {
+    switch (kind) {
+        case 0: f(std::integral_constant<int, 0>()); break;
+        case 1: f(std::integral_constant<int, 1>()); break;
+        case 2: f(std::integral_constant<int, 2>()); break;
+        default: f(std::integral_constant<int, 3>()); break;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ StepPtrs<T> kind_ptrs(const BatchKind &kd, int cur, int prv, int nxt, int s, int64_t n) {
+    StepPtrs<T> sp;
+    const int64_t L = kd.tp.n_copies;
+    const T *ru = static_cast<const T *>(kd.ru);
+    const T *u0 = static_cast<const T *>(kd.ubuf[0]), *u1 = static_cast<const T *>(kd.ubuf[1]),
+            *u2 = static_cast<const T *>(kd.ubuf[2]);
+    const T *uc = cur == 0 ? u0 : (cur == 1 ? u1 : u2);
+    const T *up = prv == 0 ? u0 : (prv == 1 ? u1 : u2);
+    T *un = const_cast<T *>(nxt == 0 ? u0 : (nxt == 1 ? u1 : u2));
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        sp.uc[k] = uc + k * L;
+        sp.up[k] = up + k * L;
+        sp.un[k] = un + k * L;
+        sp.ru[k] = ru ? ru + k * L : nullptr;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; k++) sp.pp[k] = static_cast<T *>(kd.part) + ((s & 1) * 3 + k) * int64_t(kd.tp.n_part);
+    sp.flags = kd.flags;
+    sp.acoef = static_cast<const T *>(kd.tp.acoef);
+    sp.bprime = T(0);
+    sp.sval = T(0);
+    sp.want_res = false;
+    sp.fout = nullptr;
+    sp.bpc = static_cast<const T *>(kd.tp.bpc);
+    sp.rrate = static_cast<const T *>(kd.rate);
+    sp.n1 = T(n + 1);
+    return sp;
+}
+
+template <typename T, int V>
+__global__ void __launch_bounds__((Kinds<T, V>::BLOCK)) k_batch_step(BatchDev bd) {
+    using K = Kinds<T, V>;
+    constexpr int BLOCK = K::BLOCK;
+    constexpr int KB = 4;  // chunks per shared-phase batch
+    using CS = typename K::template C<0>;  // the shared-node phase does not depend on the kind
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ ChunkDesc s_ch[KMAXB];
+    __shared__ int s_kind[KMAXB];
+    __shared__ int s_flag;
+    const uint32_t G = gridDim.x;
+    const int nmine = int(blockIdx.x) < bd.n_items ? (bd.n_items - int(blockIdx.x) + int(G) - 1) / int(G) : 0;
+    for (int k = threadIdx.x; k < nmine; k += BLOCK) {
+        const int w = bd.work[blockIdx.x + k * G];
+        const int kind = w >> 28, idx = w & 0x0fffffff;
+        const ChunkDesc *cp = kind == 0 ? bd.k[0].tp.chunks
+                            : kind == 1 ? bd.k[1].tp.chunks
+                            : kind == 2 ? bd.k[2].tp.chunks
+                                        : bd.k[3].tp.chunks;
+        s_ch[k] = cp[idx];
+        s_kind[k] = kind;
+    }
+    if (threadIdx.x == 0) s_flag = bd.status[0];
+    __syncthreads();
+    if (s_flag != 0) return;  // an earlier launch of this run stopped on an error
+    if (threadIdx.x == 0 && bd.first_launch) bd.tstamp[2 * blockIdx.x] = uint64_t(wall_clock64());
+    uint32_t epoch = 0;  // flags are cleared before every launch
+    const int64_t step0 = bd.clock[0];
+    int cur = int(bd.clock[1]);
+    int code = DJ_OK;
+    int s = 0;
+    for (s = 0; s < bd.n_steps; s++) {
+        const int nxt = (cur + 1) % 3, prv = (cur + 2) % 3;
+        const int64_t n = step0 + s;
+        PhaseOut po{0.0, 0.0, 0, -1};
+        int bad_kind = -1;
+        for (int k = 0; k < nmine; k++) {
+            const int kind = __builtin_amdgcn_readfirstlane(s_kind[k]);
+            on_kind(kind, [&](auto kc) {
+                constexpr int KC = decltype(kc)::value;
+                const StepPtrs<T> sp = kind_ptrs<T>(bd.k[KC], cur, prv, nxt, s, n);
+                K::template C<KC>::template element_phase<1>(bd.k[KC].tp, s_ch[k], sp, smem, po);
+            });
+            if (po.bad && bad_kind < 0) bad_kind = kind;
+        }
+        // shared-node batches: up to KB consecutive chunks of one kind
+        auto batch_len = [&](int k0) {
+            int nb = 1;
+            while (nb < KB && k0 + nb < nmine && s_kind[k0 + nb] == s_kind[k0]) nb++;
+            return nb;
+        };
+        SharedRegs<T, KB> sr;
+        const int nb0 = nmine > 0 ? batch_len(0) : 0;
+        const int kind0 = nmine > 0 ? __builtin_amdgcn_readfirstlane(s_kind[0]) : 0;
+        if (nmine > 0)
+            on_kind(kind0, [&](auto kc) {
+                constexpr int KC = decltype(kc)::value;
+                const StepPtrs<T> sp = kind_ptrs<T>(bd.k[KC], cur, prv, nxt, s, n);
+                CS::template shared_load<1, KB>(bd.k[KC].tp, s_ch, nb0, 0, sp, sr);
+            });
+        int32_t *errw = &bd.status[5 + (s & 1)];
+        if (po.bad) {
+            if (atomicCAS(errw, 0, po.bad) == 0) {
+                // kind << 28 | element, or kind << 28 | 1 << 27 | copy for a node-level error
+                bd.status[2] = po.bad_elem >= 0 ? ((bad_kind << 28) | po.bad_elem)
+                             : po.bad_elem <= -2 ? ((bad_kind << 28) | (1 << 27) | (-2 - po.bad_elem)) : -1;
+                bd.status[3] = s;
+            }
+        }
+        if (!grid_barrier(bd.bar, G, epoch, bd.status)) {
+            code = DJ_ERR_BARRIER;
+            break;
+        }
+        if (threadIdx.x == 0) s_flag = ld_dev(errw);
+        __syncthreads();
+        if (s_flag != 0) {
+            code = s_flag;
+            break;
+        }
+        // the first batch (its round A is in registers), then the rest
+        if (nmine > 0)
+            on_kind(kind0, [&](auto kc) {
+                constexpr int KC = decltype(kc)::value;
+                const StepPtrs<T> sp = kind_ptrs<T>(bd.k[KC], cur, prv, nxt, s, n);
+                CS::template shared_finish<1, KB>(bd.k[KC].tp, sr, sp, po);
+                CS::template shared_batch<1, KB>(bd.k[KC].tp, s_ch, nb0, 1, sp, po);
+            });
+        for (int k0 = nb0; k0 < nmine;) {
+            const int nb = batch_len(k0);
+            const int kind = __builtin_amdgcn_readfirstlane(s_kind[k0]);
+            on_kind(kind, [&](auto kc) {
+                constexpr int KC = decltype(kc)::value;
+                const StepPtrs<T> sp = kind_ptrs<T>(bd.k[KC], cur, prv, nxt, s, n);
+                CS::template shared_batch<1, KB>(bd.k[KC].tp, s_ch + k0, nb, 0, sp, po);
+            });
+            k0 += nb;
+        }
+        __syncthreads();  // shared copies written above are read by other threads next step
+        cur = nxt;
+    }
+    __syncthreads();
+    if (code == DJ_ERR_BARRIER) {  // sticky for the launches that follow in this run
+        if (threadIdx.x == 0) st_dev(&bd.status[0], int32_t(DJ_ERR_BARRIER));
+        return;
+    }
+    if (threadIdx.x == 0) bd.tstamp[2 * blockIdx.x + 1] = uint64_t(wall_clock64());
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // on an error the failing step is not completed: cur still names u^n
+        bd.status[0] = code;
+        bd.status[1] = s;
+        bd.clock[0] = step0 + s;
+        bd.clock[1] = cur;
+    }
+}
+
+__global__ void k_batch_reset(uint32_t *sync, int n_sync, int32_t *status, int clear_status) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_sync; i += gridDim.x * blockDim.x) sync[i] = 0u;
+    // a run starts with a clear status; later launches of the run keep the
+    // code, error and abort words and clear only the per-parity error words
+    if (clear_status && blockIdx.x == 0 && threadIdx.x < 8) status[threadIdx.x] = threadIdx.x == 2 ? -1 : 0;
+    if (!clear_status && blockIdx.x == 0 && (threadIdx.x == 5 || threadIdx.x == 6)) status[threadIdx.x] = 0;
+}
+
+// canonical copies -> caller-order arrays of the kind's instances
+template <typename T>
+__global__ void k_gather_canon(const uint32_t *__restrict__ flags, const int32_t *__restrict__ cnode, int n_copies,
+                               const T *__restrict__ uc, const T *__restrict__ up, T *__restrict__ oc,
+                               T *__restrict__ op) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= n_copies || !(flags[l] & FLAG_CANON)) return;
+    const int nd = cnode[l];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        oc[3 * int64_t(nd) + k] = uc[int64_t(k) * n_copies + l];
+        op[3 * int64_t(nd) + k] = up[int64_t(k) * n_copies + l];
+    }
+}
+
+template <typename T, int V>
+hipError_t occ_t(int *bpc, size_t *lds, int *block) {
+    *lds = Kinds<T, V>::LDS;
+    *block = Kinds<T, V>::BLOCK;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, k_batch_step<T, V>, Kinds<T, V>::BLOCK,
+                                                        Kinds<T, V>::LDS);
+}
+
+template <typename T, int V>
+hipError_t launch_t(const BatchDev &bd, int grid, hipStream_t s) {
+    const void *fn = reinterpret_cast<const void *>(&k_batch_step<T, V>);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, int(Kinds<T, V>::LDS));
+    if (e != hipSuccess) return e;
+    BatchDev b = bd;
+    void *args[] = {&b};
+    return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(Kinds<T, V>::BLOCK), args, Kinds<T, V>::LDS, s);
+}
+
+template <typename F>
+hipError_t batch_dispatch(int prec, int v, F &&f) {
+    if (prec == DJ_FP32) {
+        switch (v) {
+            case 0: return f(std::integral_constant<int, 0>(), float());
+            case 1: return f(std::integral_constant<int, 1>(), float());
+            case 2: return f(std::integral_constant<int, 2>(), float());
+            case 3: return f(std::integral_constant<int, 3>(), float());
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (v == 0) return f(std::integral_constant<int, 0>(), double());
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool batch_variant_ok(int prec, int v) { return prec == DJ_FP32 ? (v >= 0 && v < 4) : v == 0; }
+
+hipError_t batch_occupancy(int prec, int v, int *bpc, size_t *lds, int *block) {
+    return batch_dispatch(prec, v, [&](auto vc, auto t) {
+        using T = decltype(t);
+        return occ_t<T, decltype(vc)::value>(bpc, lds, block);
+    });
+}
+
+hipError_t launch_batch_step(const BatchDev &bd, int prec, int v, int grid, hipStream_t s) {
+    return batch_dispatch(prec, v, [&](auto vc, auto t) {
+        using T = decltype(t);
+        return launch_t<T, decltype(vc)::value>(bd, grid, s);
+    });
+}
+
+hipError_t launch_batch_reset(uint32_t *bar, int n_sync, int32_t *status, bool clear_status, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_reset, dim3((n_sync + 255) / 256), dim3(256), 0, s, bar, n_sync, status,
+                       clear_status ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_canon(const BatchKind &kd, int prec, int cur, void *oc, void *op, hipStream_t s) {
+    const int L = kd.tp.n_copies, B = 256;
+    const int prv = (cur + 2) % 3;
+    if (prec == DJ_FP32)
+        hipLaunchKernelGGL(k_gather_canon<float>, dim3((L + B - 1) / B), dim3(B), 0, s, kd.flags, kd.tp.cnode, L,
+                           static_cast<const float *>(kd.ubuf[cur]), static_cast<const float *>(kd.ubuf[prv]),
+                           static_cast<float *>(oc), static_cast<float *>(op));
+    else
+        hipLaunchKernelGGL(k_gather_canon<double>, dim3((L + B - 1) / B), dim3(B), 0, s, kd.flags, kd.tp.cnode, L,
+                           static_cast<const double *>(kd.ubuf[cur]), static_cast<const double *>(kd.ubuf[prv]),
+                           static_cast<double *>(oc), static_cast<double *>(op));
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_state(const BatchKind &kd, int prec, int cur, const void *ic, const void *ip,
+                                hipStream_t s) {
+    const int L = kd.tp.n_copies, B = 256;
+    const int prv = (cur + 2) % 3;
+    if (prec == DJ_FP32)
+        hipLaunchKernelGGL(k_scatter_in<float>, dim3((L + B - 1) / B), dim3(B), 0, s, kd.tp.cnode, L,
+                           static_cast<const float *>(ic), static_cast<const float *>(ip),
+                           static_cast<float *>(kd.ubuf[cur]), static_cast<float *>(kd.ubuf[prv]));
+    else
+        hipLaunchKernelGGL(k_scatter_in<double>, dim3((L + B - 1) / B), dim3(B), 0, s, kd.tp.cnode, L,
+                           static_cast<const double *>(ic), static_cast<const double *>(ip),
+                           static_cast<double *>(kd.ubuf[cur]), static_cast<double *>(kd.ubuf[prv]));
+    return hipGetLastError();
+}
+
+}  // namespace dj

@@ -1,0 +1,735 @@
+// Device code shared by the DJ-TLED kernel translation units: element force,
+// chunk phases, node update, grid barrier.
+//
+// HIP kernels of the DJ-TLED time step for gfx950 (MI355X).
+//
+// Data layout (all structure-of-arrays, coalesced):
+//   element planes  : one scalar per element per plane, chunk-contiguous
+//   node copies     : every chunk (workgroup tile of <= cmax elements) owns a
+//                     private copy of each node its elements touch; the copy
+//                     state (u^n, u^{n-1}, u^{n+1} in three rotating buffers)
+//                     is stored as 3 planes over copies
+//   LDS             : 3 planes x (nodes per element) x cmax slots; slot
+//                     a * cmax + e holds node a of local element e, first its
+//                     displacement (scattered in from the copies through the
+//                     local node -> slot CSR), then its element force
+//   partials        : shared nodes (copies in several chunks) exchange their
+//                     per-chunk force sums through a double-buffered array,
+//                     read back in ascending chunk order after the step's
+//                     single grid barrier, so every copy forms the same sum.
+//
+// Element force: Table 3 (neo-Hookean and transversely isotropic rows) in an
+// increment form that is equal in exact arithmetic but has no O(1)
+// cancellation in single precision:
+//   tJ = 0J + dJ, dJ = H_xi Ue (Eq. 11),  D = 0J^-1 dJ,  tJ^-1 = (I + D)^-1 0J^-1
+//   J - 1 = tr D + (tr^2 D - tr D^2) / 2 + det D      (Eq. 12)
+//   I1 - 3 = g_hat^T m1 - 3 = 2 tr D + |D|^2           (Eq. 27; m1 from I1m = 2 0V 0J^-T 0J^-1)
+//   I4 - 1 = g_hat^T m4 - 1 = 2 a.D a + |D^T a|^2      (Eq. 31; m4 from I4m, Eq. 45)
+//   F = 0V [ c0 I + mu J^-2/3 D^T + 2 J^-2/3 psi4 (a + D^T a) a^T
+//            - (p / J) D adj(I + D) ] 0J^-1 H_xi
+// with p the volumetric coefficient of Table 3, c0 = mu J^-2/3 + p, and
+// psi4 = eta_a (I4bar - 1).  The first three terms are J^-2/3 tJ^T (mu/2 I1m +
+// psi4 I4m) with their O(1) part moved into c0; the last is p 0V tJ^-1 less
+// that same O(1) part.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "djtled_internal.h"
+
+namespace dj {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+// Cube root and reciprocal.  FP32 uses the hardware base-2 log / exp and
+// reciprocal (about 1 ulp each): they only ever multiply O(strain) terms in the
+// increment form below, so their error stays relative to the force.  FP64
+// uses the correctly rounded library cbrt and division.
+template <typename T>
+__device__ __forceinline__ T dj_cbrt(T x);
+template <>
+__device__ __forceinline__ float dj_cbrt<float>(float x) {
+    return __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(x) * (1.0f / 3.0f));
+}
+template <>
+__device__ __forceinline__ double dj_cbrt<double>(double x) { return cbrt(x); }
+template <typename T>
+__device__ __forceinline__ T dj_rcp(T x);
+template <>
+__device__ __forceinline__ float dj_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <>
+__device__ __forceinline__ double dj_rcp<double>(double x) { return 1.0 / x; }
+
+// H8 natural coordinate (+1 / -1) of node a along direction i, node order
+// (---, +--, ++-, -+-, --+, +-+, +++, -++)
+__host__ __device__ constexpr int h8s(int a, int i) {
+    return (i == 0) ? ((((a + 1) >> 1) & 1) ? 1 : -1) : (i == 1) ? (((a >> 1) & 1) ? 1 : -1) : (((a >> 2) & 1) ? 1 : -1);
+}
+// Flanagan-Belytschko hourglass base vectors Gamma_alpha[a]
+__host__ __device__ constexpr int hgG(int al, int a) {
+    return al == 0 ? h8s(a, 0) * h8s(a, 1)
+         : al == 1 ? h8s(a, 1) * h8s(a, 2)
+         : al == 2 ? h8s(a, 2) * h8s(a, 0)
+                   : h8s(a, 0) * h8s(a, 1) * h8s(a, 2);
+}
+static_assert(h8s(0, 0) == -1 && h8s(1, 0) == 1 && h8s(2, 0) == 1 && h8s(3, 0) == -1, "H8 order");
+static_assert(h8s(2, 1) == 1 && h8s(3, 1) == 1 && h8s(4, 1) == -1 && h8s(7, 2) == 1, "H8 order");
+
+__device__ __forceinline__ double ramp_value(int ramp, double t, double t_ramp) {
+    if (ramp == DJ_RAMP_NONE || t_ramp <= 0.0) return 1.0;
+    double tau = t / t_ramp;
+    if (tau >= 1.0) return 1.0;
+    if (tau <= 0.0) return 0.0;
+    if (ramp == DJ_RAMP_LINEAR) return tau;
+    return tau * tau * tau * (10.0 - 15.0 * tau + 6.0 * tau * tau);
+}
+
+// Device-scope relaxed store / load: write through to, and read from, the
+// coherence point shared by all XCDs (used for every value one workgroup
+// publishes to another).
+template <typename T>
+__device__ __forceinline__ void st_dev(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T ld_dev(const T *p) {
+    return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Partial node forces: three planes (x, y, z) over the partial entries of
+// one step parity; each component is published and read with a device-scope
+// access.  Entries of neighbouring nodes are adjacent in each plane, so a
+// wave's stores of one component fall on few cache lines.
+template <typename T>
+__device__ __forceinline__ void put_partial(T *const (&pp)[3], int q, const T (&f)[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; k++) st_dev(&pp[k][q], f[k]);
+}
+template <typename T>
+__device__ __forceinline__ void get_partial(T *const (&pp)[3], int q, T (&f)[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; k++) f[k] = ld_dev(&pp[k][q]);
+}
+
+// ---------------------------------------------------------------------------
+// element force (register-resident).  cst: the element's planes.  u: nodal
+// displacements.  F: nodal forces.  Returns J.
+// ---------------------------------------------------------------------------
+template <typename T, int NE, int MODEL>
+__device__ __forceinline__ T element_force(const T *__restrict__ cst, const T (&u)[NE][3], T (&F)[NE][3]) {
+    using P = Planes<NE, MODEL>;
+    // relative displacements: differences of nearby values; the base node drops
+    // out because every row of H_xi sums to zero
+    T du[NE][3];
+#pragma unroll
+    for (int a = 1; a < NE; a++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) du[a][k] = u[a][k] - u[0][k];
+    // dJ = H_xi Ue (the increment of Eq. 11), rows = natural directions
+    T dJ[3][3];
+    if constexpr (NE == 4) {
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) dJ[i][k] = du[i + 1][k];
+    } else {
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                T s = 0;
+#pragma unroll
+                for (int a = 1; a < 8; a++) s += (h8s(a, i) > 0) ? du[a][k] : -du[a][k];
+                dJ[i][k] = s * T(0.125);
+            }
+    }
+    const T *Ji = cst + P::JINV;
+    // D = 0J^-1 dJ  (the transposed displacement gradient)
+    T D[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) D[i][k] = Ji[3 * i] * dJ[0][k] + Ji[3 * i + 1] * dJ[1][k] + Ji[3 * i + 2] * dJ[2][k];
+    const T trD = D[0][0] + D[1][1] + D[2][2];
+    T trD2 = 0, nD2 = 0;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            trD2 += D[i][j] * D[j][i];
+            nD2 += D[i][j] * D[i][j];
+        }
+    const T detD = D[0][0] * (D[1][1] * D[2][2] - D[1][2] * D[2][1]) - D[0][1] * (D[1][0] * D[2][2] - D[1][2] * D[2][0]) +
+                   D[0][2] * (D[1][0] * D[2][1] - D[1][1] * D[2][0]);
+    const T Jm1 = trD + T(0.5) * (trD * trD - trD2) + detD;  // J - 1  (Eq. 12)
+    const T J = T(1) + Jm1;
+    const T I1m3 = T(2) * trD + nD2;                          // I1 - 3 (Eq. 27)
+    const T c = dj_cbrt(J);
+    const T Jm23 = dj_rcp(c * c);                             // J^-2/3
+    const T muV = cst[P::MUV], kaV = cst[P::KAV];
+    T c0 = -(muV * T(1.0 / 3.0)) * Jm23 * I1m3 + kaV * J * Jm1;  // (mu J^-2/3 + p) 0V
+    T Q[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) Q[i][k] = muV * Jm23 * D[k][i];
+    if constexpr (MODEL == DJ_TI) {
+        const T av[3] = {cst[P::FIB], cst[P::FIB + 1], cst[P::FIB + 2]};
+        const T etaV = cst[P::ETAV];
+        T Dta[3];
+#pragma unroll
+        for (int k = 0; k < 3; k++) Dta[k] = D[0][k] * av[0] + D[1][k] * av[1] + D[2][k] * av[2];
+        const T aDa = av[0] * Dta[0] + av[1] * Dta[1] + av[2] * Dta[2];
+        const T I4m1 = T(2) * aDa + Dta[0] * Dta[0] + Dta[1] * Dta[1] + Dta[2] * Dta[2];  // I4 - 1 (Eq. 31)
+        const T Jm23m1 = -Jm1 * (c + T(1)) * dj_rcp(c * c * (c * c + c + T(1)));      // J^-2/3 - 1
+        const T I4bm1 = Jm23 * I4m1 + Jm23m1;                                            // I4bar - 1
+        const T psi4V = etaV * I4bm1;                                                    // eta (I4bar - 1) 0V
+        c0 -= T(2.0 / 3.0) * psi4V * (T(1) + I4bm1);
+        const T w = T(2) * Jm23 * psi4V;
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) Q[i][k] += w * (av[i] + Dta[i]) * av[k];
+    }
+    const T pJ = (c0 - muV * Jm23) * dj_rcp(J);  // p 0V / J
+    // adj(I + D)
+    const T A00 = T(1) + D[0][0], A11 = T(1) + D[1][1], A22 = T(1) + D[2][2];
+    T adj[3][3];
+    adj[0][0] = A11 * A22 - D[1][2] * D[2][1];
+    adj[0][1] = D[0][2] * D[2][1] - D[0][1] * A22;
+    adj[0][2] = D[0][1] * D[1][2] - D[0][2] * A11;
+    adj[1][0] = D[1][2] * D[2][0] - D[1][0] * A22;
+    adj[1][1] = A00 * A22 - D[0][2] * D[2][0];
+    adj[1][2] = D[0][2] * D[1][0] - A00 * D[1][2];
+    adj[2][0] = D[1][0] * D[2][1] - A11 * D[2][0];
+    adj[2][1] = D[0][1] * D[2][0] - A00 * D[2][1];
+    adj[2][2] = A00 * A11 - D[0][1] * D[1][0];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        Q[i][i] += c0;
+#pragma unroll
+        for (int k = 0; k < 3; k++) Q[i][k] -= pJ * (D[i][0] * adj[0][k] + D[i][1] * adj[1][k] + D[i][2] * adj[2][k]);
+    }
+    // M = Q 0J^-1  (rows: force component, columns: natural direction)
+    T M[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) M[i][j] = Q[i][0] * Ji[j] + Q[i][1] * Ji[3 + j] + Q[i][2] * Ji[6 + j];
+    if constexpr (NE == 4) {
+        // F = M H_xi with H_xi = [-1 1 0 0; -1 0 1 0; -1 0 0 1]: node 1 takes minus the sum
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            F[1][k] = M[k][0];
+            F[2][k] = M[k][1];
+            F[3][k] = M[k][2];
+            F[0][k] = -(M[k][0] + M[k][1] + M[k][2]);
+        }
+    } else {
+        // hourglass control: q_alpha = gamma_alpha^T Ue, gamma_alpha = Gamma_alpha - (dh/dX)^T g_alpha
+        const T kh = cst[P::KHG];
+        T q[4][3];
+#pragma unroll
+        for (int al = 0; al < 4; al++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                T s = 0;
+#pragma unroll
+                for (int a = 1; a < 8; a++) s += (hgG(al, a) > 0) ? du[a][k] : -du[a][k];
+                const T *g = cst + P::HG + 3 * al;
+                q[al][k] = s - (g[0] * D[0][k] + g[1] * D[1][k] + g[2] * D[2][k]);
+            }
+        // f_a = kh sum_alpha gamma_alpha[a] q_alpha: the dh/dX part joins M as - kh Qh^T 0J^-1
+        T Qh[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                T s = 0;
+#pragma unroll
+                for (int al = 0; al < 4; al++) s += cst[P::HG + 3 * al + i] * q[al][k];
+                Qh[i][k] = kh * s;
+            }
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) M[k][j] -= Qh[0][k] * Ji[j] + Qh[1][k] * Ji[3 + j] + Qh[2][k] * Ji[6 + j];
+#pragma unroll
+        for (int a = 0; a < 8; a++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const T s = M[k][0] * T(h8s(a, 0)) + M[k][1] * T(h8s(a, 1)) + M[k][2] * T(h8s(a, 2));
+                const T h = T(hgG(0, a)) * q[0][k] + T(hgG(1, a)) * q[1][k] + T(hgG(2, a)) * q[2][k] +
+                            T(hgG(3, a)) * q[3][k];
+                F[a][k] = s * T(0.125) + kh * h;
+            }
+    }
+    return J;
+}
+
+// ---------------------------------------------------------------------------
+// Per-step pointers and node update
+// ---------------------------------------------------------------------------
+template <typename T>
+struct StepPtrs {
+    const T *uc[3];   // u^n planes (over copies)
+    const T *up[3];   // u^{n-1}
+    T *un[3];         // u^{n+1}
+    T *pp[3];         // partial-force planes of this step's parity (over partial entries)
+    const uint32_t *flags;
+    const T *ru[3];   // load planes (null if no loads)
+    const T *acoef;
+    T bprime;
+    T sval;           // ramp value s(t_{n+1})
+    bool want_res;
+    T *fout;          // forces entry point: caller-order output
+    // batches (per-copy coefficients): B' per copy, ramp rate per loaded copy
+    const T *bpc;
+    const T *rrate;
+    T n1;             // n + 1
+};
+
+struct PhaseOut {
+    double num, den;  // residual partial sums over canonical copies
+    int bad;          // 0, DJ_ERR_INVERTED or DJ_ERR_NONFINITE
+    int bad_elem;     // internal element index; -2 - copy for a node-level error
+};
+
+// Ramp value of a batch instance at step n + 1 from its rate q = dt / t_ramp
+// stored with the ramp kind in the sign (+ smooth, - linear; 0: no ramp).
+// Same polynomial as ramp_value.
+template <typename T>
+__device__ __forceinline__ T ramp_rate(T q, T n1) {
+    if (q == T(0)) return T(1);
+    const T tau = (q < T(0) ? -q : q) * n1;
+    if (tau >= T(1)) return T(1);
+    if (q < T(0)) return tau;
+    return tau * tau * tau * (T(10) - T(15) * tau + T(6) * tau * tau);
+}
+
+// u^{n+1} = u^n + B'(u^n - u^{n-1}) + A (R - F); prescribed components = s(t) target
+template <typename T>
+__device__ __forceinline__ void node_update(int l, uint32_t fl, const T (&f)[3], const T (&uc)[3], const T (&up)[3],
+                                            T A, T bp, T sv, const T (&rv)[3], const StepPtrs<T> &sp,
+                                            PhaseOut &po) {
+    bool fin = true;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const bool pres = (fl >> k) & 1u;
+        T un;
+        if (pres) {
+            un = sv * rv[k];
+            if (sp.want_res && (fl & FLAG_CANON)) po.den += double(f[k]) * double(f[k]);
+        } else {
+            un = uc[k] + bp * (uc[k] - up[k]) + A * (rv[k] - f[k]);
+            if (sp.want_res && (fl & FLAG_CANON)) {
+                const double d = double(f[k]) - double(rv[k]);
+                po.num += d * d;
+            }
+        }
+        fin = fin && isfinite(un);
+        sp.un[k][l] = un;
+    }
+    if (!fin && po.bad == 0) {
+        po.bad = DJ_ERR_NONFINITE;
+        po.bad_elem = -2 - l;  // node-level error: the copy
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Chunk element phase.  Everything the chunk needs is requested in one round
+// (element planes, each element's incidence positions, per-copy data).  In
+// LDS the chunk's (element, node) incidences are numbered in node-copy order,
+// so every copy owns a contiguous range: the scatter writes u^n of a copy over
+// its range, each element reads its nodes' u from (and writes its forces to)
+// its own positions, and each copy sums its contiguous range in fixed order.
+// Interior copies are finished at once (force output or update); shared
+// copies publish their partial sum into their node's group.
+// ---------------------------------------------------------------------------
+template <typename T, int KB>
+struct SharedRegs {  // round-A data of one shared copy per chunk of a batch
+    uint32_t fl[KB];
+    int pb[KB], li[KB];
+    bool ok[KB];
+    T uc[KB][3], up[KB][3], rv[KB][3], A[KB], bp[KB], rr[KB];
+};
+
+// PC: per-copy B' and ramp rates (batches of instances with their own steps)
+template <typename T, int NE, int MODEL, int BLOCK, int EPT, int MC, bool PC = false>
+struct Chunk {
+    static constexpr int CMAX = BLOCK * EPT;
+    static constexpr int NP = Planes<NE, MODEL>::N;
+    static constexpr size_t LDS = size_t(3) * NE * CMAX * sizeof(T);
+
+    // MODE 0: forces to the caller array; MODE 1: time-step update
+    template <int MODE>
+    __device__ static void element_phase(const DevTopo &tp, const ChunkDesc &ch, const StepPtrs<T> &sp,
+                                         unsigned char *smem, PhaseOut &po) {
+        const int tid = threadIdx.x;
+        T *lx = reinterpret_cast<T *>(smem);
+        T *ly = lx + NE * CMAX;
+        T *lz = lx + 2 * NE * CMAX;
+        const T *__restrict__ ep = static_cast<const T *>(tp.elem);
+        const int64_t es = tp.estride;
+        // ---- one round of requests
+        T cst[EPT][NP];
+        int wp[EPT][NE];
+#pragma unroll
+        for (int j = 0; j < EPT; j++) {
+            const int e = tid + j * BLOCK;
+            if (e < ch.elem_count) {
+                const T *src = ep + ch.elem_begin + e;
+#pragma unroll
+                for (int q = 0; q < NP; q++) cst[j][q] = __builtin_nontemporal_load(src + q * es);
+                const uint16_t *w = tp.wpos + ch.elem_begin + e;
+#pragma unroll
+                for (int a = 0; a < NE; a++) wp[j][a] = __builtin_nontemporal_load(w + a * es);
+            }
+        }
+        uint32_t cr[MC], fl[MC];
+        int pb[MC];
+        T ux[MC][3], upv[MC][3], A[MC], Bp[MC], rr[MC];
+#pragma unroll
+        for (int m = 0; m < MC; m++) {
+            const int i = tid + m * BLOCK;
+            if (i < ch.copy_count) {
+                const int l = ch.copy_begin + i;
+                cr[m] = tp.crange[l];
+                fl[m] = sp.flags[l];
+#pragma unroll
+                for (int k = 0; k < 3; k++) ux[m][k] = sp.uc[k][l];
+                if (i >= ch.n_interior) {
+                    pb[m] = tp.pidx[l];
+                } else if (MODE == 1) {
+#pragma unroll
+                    for (int k = 0; k < 3; k++) upv[m][k] = sp.up[k][l];
+                    A[m] = sp.acoef[l];
+                    if constexpr (PC) Bp[m] = sp.bpc[l];
+                }
+            }
+        }
+        // loads (BC targets / forces) of interior copies, needed only at the update
+        T rv[MC][3];
+#pragma unroll
+        for (int m = 0; m < MC; m++) {
+            const int i = tid + m * BLOCK;
+#pragma unroll
+            for (int k = 0; k < 3; k++) rv[m][k] = T(0);
+            if constexpr (PC) rr[m] = T(0);
+            if (MODE == 1 && i < ch.n_interior && (fl[m] & FLAG_RU)) {
+                const int l = ch.copy_begin + i;
+#pragma unroll
+                for (int k = 0; k < 3; k++) rv[m][k] = sp.ru[k][l];
+                if constexpr (PC) rr[m] = sp.rrate[l];
+            }
+        }
+        // ---- scatter u^n over each copy's contiguous incidence range
+#pragma unroll
+        for (int m = 0; m < MC; m++) {
+            const int i = tid + m * BLOCK;
+            if (i < ch.copy_count) {
+                const int b = cr[m] & 0xffffu, n = cr[m] >> 16;
+                for (int q = b; q < b + n; q++) {
+                    lx[q] = ux[m][0];
+                    ly[q] = ux[m][1];
+                    lz[q] = ux[m][2];
+                }
+            }
+        }
+        __syncthreads();
+        // ---- element forces, written back over the element's own positions
+#pragma unroll
+        for (int j = 0; j < EPT; j++) {
+            const int e = tid + j * BLOCK;
+            if (e < ch.elem_count) {
+                T u[NE][3], F[NE][3];
+#pragma unroll
+                for (int a = 0; a < NE; a++) {
+                    u[a][0] = lx[wp[j][a]];
+                    u[a][1] = ly[wp[j][a]];
+                    u[a][2] = lz[wp[j][a]];
+                }
+                const T J = element_force<T, NE, MODEL>(cst[j], u, F);
+                // an inverted (or non-finite) element stops the run; its force is
+                // left out so that the error is reported at the element itself
+                const bool ok = J > T(0);
+#pragma unroll
+                for (int a = 0; a < NE; a++) {
+                    lx[wp[j][a]] = ok ? F[a][0] : T(0);
+                    ly[wp[j][a]] = ok ? F[a][1] : T(0);
+                    lz[wp[j][a]] = ok ? F[a][2] : T(0);
+                }
+                if (!isfinite(J)) {
+                    po.bad = DJ_ERR_NONFINITE;
+                    po.bad_elem = ch.elem_begin + e;
+                } else if (!(J > T(0)) && po.bad == 0) {
+                    po.bad = DJ_ERR_INVERTED;
+                    po.bad_elem = ch.elem_begin + e;
+                }
+            }
+        }
+        __syncthreads();
+        // ---- node sums over each copy's range, in fixed order
+#pragma unroll
+        for (int m = 0; m < MC; m++) {
+            const int i = tid + m * BLOCK;
+            if (i < ch.copy_count) {
+                const int b = cr[m] & 0xffffu, n = cr[m] >> 16;
+                T f[3] = {T(0), T(0), T(0)};
+                for (int q = b; q < b + n; q++) {
+                    f[0] += lx[q];
+                    f[1] += ly[q];
+                    f[2] += lz[q];
+                }
+                const int l = ch.copy_begin + i;
+                if (i >= ch.n_interior) {
+                    const int q = pb[m] + int((fl[m] >> FLAG_RANK_SHIFT) & 255u);
+                    put_partial(sp.pp, q, f);
+                    if (!(isfinite(f[0]) && isfinite(f[1]) && isfinite(f[2])) && po.bad == 0) {
+                        po.bad = DJ_ERR_NONFINITE;
+                        po.bad_elem = -2 - l;
+                    }
+                } else if constexpr (MODE == 0) {
+                    const int nd = tp.cnode[l];
+                    sp.fout[3 * nd] = f[0];
+                    sp.fout[3 * nd + 1] = f[1];
+                    sp.fout[3 * nd + 2] = f[2];
+                } else if constexpr (PC) {
+                    node_update<T>(l, fl[m], f, ux[m], upv[m], A[m], Bp[m], ramp_rate(rr[m], sp.n1), rv[m], sp, po);
+                } else {
+                    node_update<T>(l, fl[m], f, ux[m], upv[m], A[m], sp.bprime, sp.sval, rv[m], sp, po);
+                }
+            }
+        }
+        __syncthreads();  // LDS is reused by the next chunk
+    }
+
+    // Round A for the shared copies of up to KB chunks (one per thread per
+    // chunk, pass `pass`): everything but the partial sums.  Issued before the
+    // grid barrier for the first batch, so its latency hides in the wait.
+    template <int MODE, int KB>
+    __device__ static void shared_load(const DevTopo &tp, const ChunkDesc *chs, int nb, int pass,
+                                       const StepPtrs<T> &sp, SharedRegs<T, KB> &r) {
+#pragma unroll
+        for (int kb = 0; kb < KB; kb++) {
+            r.ok[kb] = false;
+            if (kb < nb) {
+                const ChunkDesc &ch = chs[kb];
+                const int i = ch.n_interior + threadIdx.x + pass * BLOCK;
+                if (i < ch.copy_count) {
+                    const int l = ch.copy_begin + i;
+                    r.li[kb] = l;
+                    r.ok[kb] = true;
+                    r.fl[kb] = sp.flags[l];
+                    r.pb[kb] = tp.pidx[l];
+                    if (MODE == 1) {
+                        r.A[kb] = sp.acoef[l];
+#pragma unroll
+                        for (int k = 0; k < 3; k++) {
+                            r.uc[kb][k] = sp.uc[k][l];
+                            r.up[kb][k] = sp.up[k][l];
+                            r.rv[kb][k] = sp.ru[0] ? sp.ru[k][l] : T(0);
+                        }
+                        if constexpr (PC) {
+                            r.bp[kb] = sp.bpc[l];
+                            r.rr[kb] = sp.rrate ? sp.rrate[l] : T(0);
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    // Round B (the node's partial group) and finish: sum in rank order, then
+    // force output (MODE 0, canonical copy) or update (MODE 1).
+    template <int MODE, int KB>
+    __device__ static void shared_finish(const DevTopo &tp, SharedRegs<T, KB> &r, const StepPtrs<T> &sp,
+                                         PhaseOut &po) {
+        constexpr int UNR = 4;
+        T px[KB][UNR][3];
+#pragma unroll
+        for (int kb = 0; kb < KB; kb++) {
+            if (r.ok[kb]) {
+                const int cnt = (r.fl[kb] >> FLAG_NCOPY_SHIFT) & 255u;
+#pragma unroll
+                for (int q = 0; q < UNR; q++)
+                    if (q < cnt) get_partial(sp.pp, r.pb[kb] + q, px[kb][q]);
+            }
+        }
+#pragma unroll
+        for (int kb = 0; kb < KB; kb++) {
+            if (!r.ok[kb]) continue;
+            const int cnt = (r.fl[kb] >> FLAG_NCOPY_SHIFT) & 255u;
+            T f[3] = {T(0), T(0), T(0)};
+#pragma unroll
+            for (int q = 0; q < UNR; q++)
+                if (q < cnt)
+#pragma unroll
+                    for (int k = 0; k < 3; k++) f[k] += px[kb][q][k];
+            for (int q = UNR; q < cnt; q++) {
+                T g[3];
+                get_partial(sp.pp, r.pb[kb] + q, g);
+#pragma unroll
+                for (int k = 0; k < 3; k++) f[k] += g[k];
+            }
+            const int l = r.li[kb];
+            if constexpr (MODE == 0) {
+                if (r.fl[kb] & FLAG_CANON) {
+                    const int nd = tp.cnode[l];
+                    sp.fout[3 * nd] = f[0];
+                    sp.fout[3 * nd + 1] = f[1];
+                    sp.fout[3 * nd + 2] = f[2];
+                }
+            } else {
+                if (!(r.fl[kb] & FLAG_RU))
+#pragma unroll
+                    for (int k = 0; k < 3; k++) r.rv[kb][k] = T(0);
+                if constexpr (PC)
+                    node_update<T>(l, r.fl[kb], f, r.uc[kb], r.up[kb], r.A[kb], r.bp[kb],
+                                   ramp_rate((r.fl[kb] & FLAG_RU) ? r.rr[kb] : T(0), sp.n1), r.rv[kb], sp, po);
+                else
+                    node_update<T>(l, r.fl[kb], f, r.uc[kb], r.up[kb], r.A[kb], sp.bprime, sp.sval, r.rv[kb], sp,
+                                   po);
+            }
+        }
+    }
+
+    // all passes of one batch of chunks
+    template <int MODE, int KB>
+    __device__ static void shared_batch(const DevTopo &tp, const ChunkDesc *chs, int nb, int first_pass,
+                                        const StepPtrs<T> &sp, PhaseOut &po) {
+        for (int pass = first_pass;; pass++) {
+            bool more = false;
+            for (int kb = 0; kb < nb; kb++) more |= chs[kb].n_interior + pass * BLOCK < chs[kb].copy_count;
+            if (!more) break;
+            SharedRegs<T, KB> r;
+            shared_load<MODE, KB>(tp, chs, nb, pass, sp, r);
+            shared_finish<MODE, KB>(tp, r, sp, po);
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// block-wide sum of two doubles in a fixed order (result valid in thread 0)
+// ---------------------------------------------------------------------------
+template <int BLOCK>
+__device__ __forceinline__ void block_sum2(double &x, double &y, double *sred) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        x += __shfl_xor(x, o, 64);
+        y += __shfl_xor(y, o, 64);
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) {
+        sred[2 * w] = x;
+        sred[2 * w + 1] = y;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0, b = 0;
+        for (int i = 0; i < BLOCK / 64; i++) {
+            a += sred[2 * i];
+            b += sred[2 * i + 1];
+        }
+        x = a;
+        y = b;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Cross-workgroup communication.  On gfx950 the L2 of each XCD is not coherent
+// with the others, and agent-scope fences write back / invalidate whole L2s
+// (tens of microseconds with hundreds of workgroups).  So every value one
+// workgroup publishes to another (partial node forces, residual partials,
+// flags) is stored and loaded with device-scope relaxed atomics, which write
+// through to and read from the coherence point; a thread waits for its own
+// stores to be acknowledged before its workgroup signals arrival.
+// ---------------------------------------------------------------------------
+
+constexpr unsigned SPIN_LIMIT = 1u << 24;
+constexpr int N_RELEASE = 16;   // release-flag copies, one cache line apart
+constexpr int FLAG_STRIDE = 32; // uint32 per flag slot (128 B)
+
+// Grid barrier for the persistent kernel (all workgroups co-resident through
+// a cooperative launch).  Arrival: one flag per workgroup; workgroup 0 polls
+// them all and then raises N_RELEASE release flags.  Bounded spins: a broken
+// co-residency ends in DJ_ERR_BARRIER instead of a hang.
+//   sync[0 .. G*FLAG_STRIDE)        arrival flags
+//   sync[G*FLAG_STRIDE ...)         release flags
+//   status[4]                       abort flag
+__device__ __forceinline__ bool grid_barrier(uint32_t *sync, uint32_t nblocks, uint32_t &epoch, int32_t *status) {
+    __shared__ int s_ok;
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's published stores are complete
+    __syncthreads();
+    const uint32_t target = epoch + 1u;
+    uint32_t *rel = sync + size_t(nblocks) * FLAG_STRIDE;
+    if (threadIdx.x == 0) {
+        s_ok = 1;
+        st_dev(&sync[size_t(blockIdx.x) * FLAG_STRIDE], target);
+    }
+    if (blockIdx.x == 0) {
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < nblocks; i += blockDim.x) {
+            unsigned spins = 0;
+            while (ld_dev(&sync[size_t(i) * FLAG_STRIDE]) != target) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > SPIN_LIMIT || ld_dev(&status[4]) != 0) {
+                    st_dev(&status[4], 1);
+                    s_ok = 0;
+                    break;
+                }
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < N_RELEASE && s_ok) st_dev(&rel[threadIdx.x * FLAG_STRIDE], target);
+    } else if (threadIdx.x == 0) {
+        const uint32_t *r = &rel[(blockIdx.x % N_RELEASE) * FLAG_STRIDE];
+        unsigned spins = 0;
+        while (ld_dev(r) != target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > SPIN_LIMIT || ld_dev(&status[4]) != 0) {
+                st_dev(&status[4], 1);
+                s_ok = 0;
+                break;
+            }
+        }
+    }
+    __syncthreads();
+    epoch = target;
+    return s_ok != 0;
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+// copies <- caller arrays (both state vectors at once when src1 != null)
+template <typename T>
+__global__ void k_scatter_in(const int32_t *__restrict__ cnode, int n_copies, const T *__restrict__ src0,
+                             const T *__restrict__ src1, T *__restrict__ d0, T *__restrict__ d1) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= n_copies) return;
+    const int n = cnode[l];
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        d0[int64_t(k) * n_copies + l] = src0[3 * n + k];
+        if (src1) d1[int64_t(k) * n_copies + l] = src1[3 * n + k];
+    }
+}
+
+// Kernel variants per (precision, element type): {threads, elements per thread, copies per thread}
+constexpr Variant VAR_T4F[4] = {{256, 4, 2}, {256, 2, 2}, {512, 2, 2}, {128, 4, 2}};
+constexpr Variant VAR_H8F[4] = {{256, 2, 4}, {256, 1, 4}, {512, 1, 3}, {128, 2, 4}};
+constexpr Variant VAR_T4D[4] = {{256, 2, 2}, {256, 1, 2}, {512, 1, 2}, {128, 2, 2}};
+constexpr Variant VAR_H8D[4] = {{256, 1, 4}, {128, 1, 4}, {512, 1, 3}, {128, 2, 4}};
+
+template <typename T, int NE>
+constexpr const Variant *var_table() {
+    return sizeof(T) == 4 ? (NE == 4 ? VAR_T4F : VAR_H8F) : (NE == 4 ? VAR_T4D : VAR_H8D);
+}
+
+}  // namespace dj

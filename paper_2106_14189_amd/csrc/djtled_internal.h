@@ -31,8 +31,12 @@ enum : uint32_t {
 // node a of element e.
 struct ChunkDesc {
     int32_t elem_begin, elem_count, copy_begin, copy_count;
-    int32_t n_interior, pad0, pad1, pad2;
+    int32_t n_interior, tag, pad1, pad2;  // tag: element kind (batches)
 };
+
+// Element kinds of a batch: slot t holds the group of (T4|H8) x (NH|TI)
+// instances, t = 2 * (element is H8) + (model is TI).
+inline int kind_of(int ne, int model) { return (ne == 8 ? 2 : 0) + (model == DJ_TI ? 1 : 0); }
 
 // Element-constant plane indices.  Each plane holds one scalar per element
 // (structure of arrays, element stride `estride`).
@@ -76,6 +80,7 @@ struct DevTopo {
     const void *elem = nullptr;          // element planes (context precision)
     int64_t estride = 0;
     const void *acoef = nullptr;         // per copy A_i = 2 dt^2 / ((2 + alpha dt) m_i)
+    const void *bpc = nullptr;           // batches: per copy B' = (2 - alpha dt) / (2 + alpha dt)
 };
 
 struct StepArgs {
@@ -93,7 +98,7 @@ struct StepArgs {
     int32_t check_every = 1;
     int32_t cur0 = 0;           // buffer index of u^n at entry (prev = cur0 + 2 mod 3)
     void *ubuf[3] = {nullptr, nullptr, nullptr};  // each: 3 planes over copies
-    void *part = nullptr;       // partial forces: 2 parities x 3 planes x n_part
+    void *part = nullptr;       // partial forces: 2 parities x 3 planes over n_part entries
     void *u_out_cur = nullptr;  // caller arrays written at the end
     void *u_out_prev = nullptr;
     uint32_t *bar = nullptr;    // barrier flags: (grid + 16) x 32 uint32
@@ -128,7 +133,24 @@ struct Ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;  // brackets the persistent kernel
     std::vector<uint32_t> h_flags;   // topology flags per copy
     std::vector<int32_t> h_copy_node;  // internal node of each copy
+    std::vector<int32_t> h_chunk_elem; // per chunk: first element, element count
     std::vector<void *> loadsets;
+    // several instances in one context (batches): per-instance step, damping
+    int n_inst = 1;
+    std::vector<double> inst_dt, inst_dt_crit, inst_alpha;
+    std::vector<int32_t> inst_node_off, inst_elem_off;  // caller numbering, n_inst + 1 entries
+    void *d_bpc = nullptr;
+};
+
+// Extra inputs of a multi-instance context: caller nodes and elements are
+// numbered instance by instance (offsets below); every instance has its own
+// damping and time step.
+struct MultiInst {
+    int n_inst = 1;
+    const int32_t *node_off = nullptr;  // n_inst + 1
+    const int32_t *elem_off = nullptr;  // n_inst + 1
+    const double *alpha = nullptr;      // per instance
+    int batch = 0;                      // chunks feed a batch work list (no per-context grid rounds)
 };
 
 struct LoadSet {
@@ -137,14 +159,32 @@ struct LoadSet {
     void *d_ru = nullptr;
     int ramp = DJ_RAMP_NONE;
     double t_ramp = 0.0;
+    void *d_rate = nullptr;          // batches: per copy ramp rate (see ramp_rate)
 };
+
+// ---- host side (djtled_api.cpp) ----
+extern thread_local std::string g_err;  // djtled_last_error()
+int fail(int code, const std::string &msg);
+void free_all(Ctx *c);
+int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djtled_params *prm,
+          const MultiInst *mi = nullptr);
+int make_loadset(Ctx &c, const djtled_loads *ld, const double *node_rate, LoadSet **out);
+
+#define DJ_HIP(call)                                                                                         \
+    do {                                                                                                     \
+        hipError_t e_ = (call);                                                                              \
+        if (e_ != hipSuccess) return ::dj::fail(DJ_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
 
 // ---- kernel launchers (djtled_kernels.hip) ----
 hipError_t occupancy(int ne, int model, int prec, int variant, int *blocks_per_cu, size_t *lds_bytes);
 hipError_t launch_precompute(Ctx &c, const double *dX, const int32_t *dconn, const double *dE, const double *dnu,
-                             const double *deta, const double *dfib, double *d_dtmin, int32_t *d_bad,
-                             hipStream_t s);
-hipError_t launch_mass_acoef(Ctx &c, const int32_t *d_ne_off, const int32_t *d_ne_list, hipStream_t s);
+                             const double *deta, const double *dfib, const int32_t *d_einst, double *d_dtmin,
+                             int32_t *d_bad, hipStream_t s);
+// c2: per internal node 2 dt^2 / (2 + alpha dt) of its instance; bp: per node
+// B' (written per copy to c.d_bpc when that is allocated)
+hipError_t launch_mass_acoef(Ctx &c, const int32_t *d_ne_off, const int32_t *d_ne_list, const double *d_c2,
+                             const double *d_bp, hipStream_t s);
 hipError_t launch_forces(Ctx &c, const void *u, void *f, hipStream_t s);
 hipError_t launch_step(Ctx &c, const StepArgs &a, const void *u_cur_in, const void *u_prev_in, hipStream_t s,
                        hipEvent_t ev0, hipEvent_t ev1);

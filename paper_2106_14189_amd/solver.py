@@ -174,3 +174,139 @@ def from_workload(wl, **kw) -> Solver:
         args.update(eta_ratio=mat.eta_ratio, fibre=mat.fibre)
     args.update(kw)
     return Solver(wl.mesh.X, wl.mesh.conn, mat.E, mat.nu, **args)
+
+
+@dataclass
+class Instance:
+    """One mesh + material + load case of a batch (host arrays)."""
+    X: np.ndarray
+    conn: np.ndarray
+    E: object
+    nu: object
+    model: int = L.DJ_NH
+    rho: float = 1000.0
+    eta_ratio: object = None
+    fibre: object = None
+    hg_kappa: float = 0.1
+    bc_node: object = None
+    bc_mask: object = None
+    bc_target: object = None
+    ramp: int = L.DJ_RAMP_NONE
+    t_ramp: float = 0.0          # seconds; < 0: |t_ramp| steps of the instance's own dt
+    alpha: float | None = None
+
+
+class Batch:
+    """Many independent instances advanced by one persistent kernel per run
+    (``djtled_batch_*``).  The batch owns every instance's state."""
+
+    def __init__(self, instances, precision="fp32", dt_factor=0.9, alpha=0.0, autotune=False, variant=-1,
+                 chunk_elems=0, steps_per_launch=0, use_graph=True, tune_steps=0, device=0,
+                 allow_unstable_dt=False):
+        torch.cuda.init()
+        n = len(instances)
+        meshes = (L.djtled_mesh * n)()
+        mats = (L.djtled_material * n)()
+        loads = (L.djtled_loads * n)()
+        keep = []
+        self.sizes = []
+        al = np.zeros(n)
+        for i, ins in enumerate(instances):
+            X = np.ascontiguousarray(ins.X, dtype=np.float64)
+            conn = np.ascontiguousarray(ins.conn, dtype=np.int32)
+            ne_ = conn.shape[1]
+            E = np.ascontiguousarray(np.broadcast_to(np.asarray(ins.E, np.float64), (conn.shape[0],)))
+            nu = np.ascontiguousarray(np.broadcast_to(np.asarray(ins.nu, np.float64), (conn.shape[0],)))
+            keep += [X, conn, E, nu]
+            meshes[i] = L.djtled_mesh(X.shape[0], conn.shape[0], ne_, _dptr(X), _iptr(conn))
+            m = L.djtled_material()
+            m.model, m.E, m.nu, m.rho, m.hg_kappa = ins.model, _dptr(E), _dptr(nu), float(ins.rho), float(ins.hg_kappa)
+            if ins.model == L.DJ_TI:
+                er = np.ascontiguousarray(np.broadcast_to(np.asarray(ins.eta_ratio, np.float64), (conn.shape[0],)))
+                fb = np.ascontiguousarray(np.broadcast_to(np.asarray(ins.fibre, np.float64), (conn.shape[0], 3)))
+                keep += [er, fb]
+                m.eta_ratio, m.fibre = _dptr(er), _dptr(fb)
+            mats[i] = m
+            bn = np.ascontiguousarray(ins.bc_node if ins.bc_node is not None else np.zeros(0), dtype=np.int32)
+            bm = np.ascontiguousarray(ins.bc_mask if ins.bc_mask is not None else np.zeros(0), dtype=np.int32)
+            bt = np.ascontiguousarray(ins.bc_target if ins.bc_target is not None else np.zeros((0, 3)),
+                                      dtype=np.float64).reshape(-1, 3)
+            keep += [bn, bm, bt]
+            loads[i] = L.djtled_loads(len(bn), _iptr(bn), _iptr(bm), _dptr(bt), int(ins.ramp), float(ins.t_ramp), None)
+            al[i] = alpha if ins.alpha is None else ins.alpha
+            self.sizes.append((X.shape[0], conn.shape[0]))
+        self.precision = L.DJ_FP64 if precision in ("fp64", L.DJ_FP64) else L.DJ_FP32
+        self.dtype = torch.float64 if self.precision == L.DJ_FP64 else torch.float32
+        self.device = torch.device("cuda", device)
+        prm = L.djtled_params(self.precision, 0.0, float(dt_factor), float(alpha), int(allow_unstable_dt), 0, 0,
+                              int(device))
+        tn = L.djtled_tune(int(autotune), int(variant), int(chunk_elems), int(steps_per_launch), int(use_graph),
+                           int(tune_steps))
+        h = ctypes.c_void_p()
+        L.check(L.lib.djtled_batch_create(n, meshes, mats, loads, _dptr(al), ctypes.byref(prm), ctypes.byref(tn),
+                                          ctypes.byref(h)), "djtled_batch_create")
+        self.handle = h
+        self.n = n
+        self.step_index = 0
+        del keep
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.lib.djtled_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        inf = L.djtled_batch_info_t()
+        L.check(L.lib.djtled_batch_info(self.handle, ctypes.byref(inf)), "djtled_batch_info")
+        return {k: getattr(inf, k) for k, _ in L.djtled_batch_info_t._fields_}
+
+    def instance(self, i: int) -> dict:
+        inf = L.djtled_info_t()
+        L.check(L.lib.djtled_batch_instance(self.handle, int(i), ctypes.byref(inf)), "djtled_batch_instance")
+        return {k: getattr(inf, k) for k, _ in L.djtled_info_t._fields_}
+
+    def run(self, n_steps: int, stream=None, raise_on_error: bool = True) -> Status:
+        out = L.djtled_status()
+        s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else ctypes.c_void_p(None)
+        code = L.lib.djtled_batch_run(self.handle, int(n_steps), ctypes.byref(out), s)
+        st = Status(out.code, out.steps_done, out.error_step, out.error_elem, out.residual, out.kernel_ms)
+        self.step_index += st.steps_done
+        if code < 0 and raise_on_error:
+            raise L.DJError(code, "djtled_batch_run")
+        return st
+
+    def stats(self) -> np.ndarray:
+        ms = np.zeros(self.n)
+        L.check(L.lib.djtled_batch_stats(self.handle, _dptr(ms)), "djtled_batch_stats")
+        return ms
+
+    def read(self, i: int, with_prev: bool = False):
+        nn = self.sizes[i][0]
+        u = torch.empty((nn, 3), dtype=self.dtype, device=self.device)
+        up = torch.empty_like(u) if with_prev else None
+        L.check(L.lib.djtled_batch_read(self.handle, int(i), ctypes.c_void_p(u.data_ptr()),
+                                        ctypes.c_void_p(up.data_ptr()) if up is not None else None,
+                                        _stream(None)), "djtled_batch_read")
+        torch.cuda.current_stream().synchronize()
+        return (u, up) if with_prev else u
+
+    def write(self, i: int, u: torch.Tensor, u_prev: torch.Tensor | None = None):
+        nn = self.sizes[i][0]
+        for t in (u, u_prev):
+            if t is not None and (t.dtype != self.dtype or tuple(t.shape) != (nn, 3) or not t.is_contiguous()
+                                  or t.device != self.device):
+                raise ValueError(f"state must be a contiguous {self.dtype} tensor of shape ({nn}, 3) on {self.device}")
+        L.check(L.lib.djtled_batch_write(self.handle, int(i), ctypes.c_void_p(u.data_ptr()),
+                                         ctypes.c_void_p(u_prev.data_ptr()) if u_prev is not None else None,
+                                         _stream(None)), "djtled_batch_write")
+        torch.cuda.current_stream().synchronize()
+
+    def reset(self):
+        L.check(L.lib.djtled_batch_reset(self.handle, _stream(None)), "djtled_batch_reset")
+        self.step_index = 0

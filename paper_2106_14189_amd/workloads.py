@@ -292,3 +292,114 @@ def config1(elem: int = T4, n: int = 64, n_steps: int = 1000, seed_offset: int =
     loads = compression_loads(mesh, -0.2, RAMP_SMOOTH)
     name = f"cube{n}_{'t4' if elem == T4 else 'h8'}_nh_fp32"
     return Workload(name, mesh, mat, loads, 0.9, alpha=37.0, n_steps=n_steps, fp64=False, seed=seed)
+
+
+def patch_loads(mesh: Mesh, rng, frac: float = 0.05, amp: float = 0.010, n_rbf: int = 4,
+                ramp=RAMP_SMOOTH, t_ramp=0.0, fix_bottom: bool = True) -> Loads:
+    """Bottom cap fixed; about `frac` of the surface nodes, in one seeded patch
+    around a random upper-surface node, prescribed with a smooth field: a sum of
+    `n_rbf` Gaussian radial basis functions with random vector weights, times
+    the window (1 - (r / R)^2)^2 that vanishes at the patch rim (r: distance
+    from the patch centre, R: patch radius), scaled to a maximum magnitude of
+    `amp`."""
+    surf = mesh.surface
+    Xs = mesh.X[surf]
+    upper = surf[Xs[:, 2] > 0.0]
+    centre = mesh.X[rng.choice(upper)]
+    d = np.linalg.norm(mesh.X[surf] - centre, axis=1)
+    k = max(4, int(round(frac * len(surf))))
+    patch = surf[np.argsort(d)[:k]]
+    P = mesh.X[patch]
+    radius = np.linalg.norm(P - centre, axis=1).max() + 1e-12
+    centres = P[rng.choice(len(patch), n_rbf, replace=False)]
+    weights = rng.normal(size=(n_rbf, 3))
+    field = np.zeros((len(patch), 3))
+    for c, w in zip(centres, weights):
+        field += np.exp(-np.sum((P - c) ** 2, axis=1) / (0.5 * radius) ** 2)[:, None] * w[None, :]
+    r = np.linalg.norm(P - centre, axis=1) / radius
+    field *= ((1.0 - r * r) ** 2)[:, None]
+    field *= amp / np.linalg.norm(field, axis=1).max()
+    fixed = np.setdiff1d(mesh.bottom, patch) if fix_bottom else np.zeros(0, np.int32)
+    bc_node = np.concatenate([fixed, patch]).astype(np.int32)
+    bc_mask = np.full(len(bc_node), 7, np.int32)
+    tgt = np.concatenate([np.zeros((len(fixed), 3)), field])
+    return Loads(bc_node=bc_node, bc_mask=bc_mask, bc_target=tgt, ramp=ramp, t_ramp=t_ramp)
+
+
+def config2(target_elems: int = 1_200_000, seed_offset: int = 0) -> Workload:
+    """Transversely isotropic neo-Hookean ellipsoid (semi-axes 0.05, 0.04,
+    0.03 m) voxelised into ~1.2M Kuhn tetrahedra, interior nodes jittered
+    +-15 %, nodes and elements permuted; E = 3 kPa, nu = 0.45, rho = 1000;
+    per-element unit fibre uniform on the sphere, eta_a / mu ~ U[2, 10];
+    bottom cap (z < -0.8 c) fixed; ~5 % of the surface nodes prescribed with a
+    smooth windowed random field of maximum 10 mm, ramped smoothly over 0.4 s;
+    dynamic relaxation to 1e-6."""
+    seed = seed_for(2) + seed_offset
+    rng = np.random.default_rng(seed)
+    mesh = ellipsoid_mesh(target_elems=target_elems, jitter=0.15, seed=seed, permute=True)
+    mat = uniform_material(mesh.n_elems, 3000.0, 0.45, 1000.0, model=TI, rng=rng)
+    loads = patch_loads(mesh, rng)
+    wl = Workload(f"ellipsoid{mesh.n_elems // 1000}k_t4_ti_fp32_relax", mesh, mat, loads, 0.9, alpha=60.0,
+                  n_steps=200000, fp64=False, seed=seed)
+    wl.extra.update(t_ramp=0.4, tol=1e-6, check_every=100)
+    return wl
+
+
+def box_mesh(nx: int, ny: int, nz: int, h: float, elem: int = T4, jitter: float = 0.05, seed: int = 0) -> Mesh:
+    """nx x ny x nz voxels of side h, jittered like cube_mesh (boundary nodes
+    move only tangentially, so the faces stay planar)."""
+    rng = np.random.default_rng(seed)
+    kk, jj, ii = np.meshgrid(np.arange(nz + 1), np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
+    idx = np.stack([ii.ravel(), jj.ravel(), kk.ravel()], axis=1)  # node id = i + (nx+1)(j + (ny+1)k)
+    X = idx.astype(np.float64) * h
+    if jitter > 0:
+        d = rng.uniform(-jitter * h, jitter * h, size=X.shape)
+        d[(idx == 0) | (idx == np.array([nx, ny, nz]))] = 0.0
+        X = X + d
+    conn = _grid_conn(nx, ny, nz, elem)
+    bottom = np.nonzero(idx[:, 2] == 0)[0].astype(np.int32)
+    top = np.nonzero(idx[:, 2] == nz)[0].astype(np.int32)
+    return Mesh(X=X, conn=conn, bottom=bottom, top=top, height=nz * h)
+
+
+def box_instance(E_target: int, elem: int, model: int, rng, size: float = 0.1, jitter: float = 0.05,
+                 permute: bool = True):
+    """A jittered, permuted box grid with about E_target elements (6 Kuhn
+    tetrahedra or one hexahedron per voxel), n x n x nz voxels of side
+    size / n, with E ~ U[2, 6] kPa per element, nu = 0.45, and for TI a unit
+    fibre uniform on the sphere and eta_a / mu ~ U[2, 10]."""
+    vox = E_target / (6.0 if elem == T4 else 1.0)
+    n = max(2, int(round(vox ** (1.0 / 3.0))))
+    nz = max(2, int(round(vox / (n * n))))
+    m = box_mesh(n, n, nz, size / n, elem, jitter=jitter, seed=int(rng.integers(2 ** 31)))
+    if permute:
+        m = permute_mesh(m, rng)
+    mat = uniform_material(m.n_elems, rng.uniform(2000.0, 6000.0, m.n_elems), 0.45, 1000.0, model=model, rng=rng)
+    return m, mat
+
+
+def config3(n_inst: int = 256, n_steps: int = 500, seed_offset: int = 0, e_min: float = 5e3, e_max: float = 2e5):
+    """Batch of independent box instances: element counts log-uniform in
+    [5k, 200k], element kind (T4 / H8) and model (NH / TI) each a fair coin;
+    bottom face fixed, top face moved by a displacement of magnitude U[5 %,
+    20 %] of the height in a seeded direction (downward z component), smooth
+    ramp over the run's steps.  Returns a list of (Mesh, Material, Loads,
+    alpha) with t_ramp given in steps (negative)."""
+    out = []
+    for k in range(n_inst):
+        rng = np.random.default_rng(seed_for(3, k) + seed_offset)
+        Ek = int(round(np.exp(rng.uniform(np.log(e_min), np.log(e_max)))))
+        elem = T4 if rng.random() < 0.5 else H8
+        model = NH if rng.random() < 0.5 else TI
+        mesh, mat = box_instance(Ek, elem, model, rng)
+        d = rng.normal(size=3)
+        d[2] = -abs(d[2]) - 0.5
+        d /= np.linalg.norm(d)
+        amp = rng.uniform(0.05, 0.20) * mesh.height
+        nb, nt = len(mesh.bottom), len(mesh.top)
+        loads = Loads(bc_node=np.concatenate([mesh.bottom, mesh.top]).astype(np.int32),
+                      bc_mask=np.full(nb + nt, 7, np.int32),
+                      bc_target=np.concatenate([np.zeros((nb, 3)), np.tile(amp * d, (nt, 1))]),
+                      ramp=RAMP_SMOOTH, t_ramp=-float(n_steps))
+        out.append((mesh, mat, loads, 37.0))
+    return out

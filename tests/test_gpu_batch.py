@@ -1,0 +1,176 @@
+"""Batches (djtled_batch_*): several independent instances of mixed element
+kinds advanced by one persistent kernel per run, against the FP64 oracle run
+instance by instance with the instance's own step, damping and ramp.
+
+Tolerances: after the run, FP32 max|u_gpu - u_ora| / max|u_ora| <= 1e-4 per
+instance; FP64 <= 1e-10.  Splitting a run (several runs, several launches
+per run, graph or not) is bitwise neutral.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2106_14189_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def S():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2106_14189_amd import solver
+    return solver
+
+
+def _mixed(n_steps, seed=7):
+    """Six small instances: every element kind, uneven sizes, own loads and damping."""
+    spec = [(300, W.T4, W.NH), (900, W.T4, W.TI), (120, W.H8, W.NH), (250, W.H8, W.TI), (2000, W.T4, W.NH),
+            (60, W.H8, W.NH)]
+    out = []
+    for k, (ne, elem, model) in enumerate(spec):
+        rng = np.random.default_rng(seed + 11 * k)
+        mesh, mat = W.box_instance(ne, elem, model, rng)
+        d = rng.normal(size=3)
+        d[2] = -abs(d[2]) - 0.5
+        d /= np.linalg.norm(d)
+        amp = rng.uniform(0.05, 0.15) * mesh.height
+        nb, nt = len(mesh.bottom), len(mesh.top)
+        ramp = W.RAMP_SMOOTH if k % 3 else W.RAMP_LINEAR
+        loads = W.Loads(bc_node=np.concatenate([mesh.bottom, mesh.top]).astype(np.int32),
+                        bc_mask=np.concatenate([np.full(nb, 7), np.full(nt, 7 if k % 2 else 4)]).astype(np.int32),
+                        bc_target=np.concatenate([np.zeros((nb, 3)), np.tile(amp * d, (nt, 1))]), ramp=ramp,
+                        t_ramp=-float(n_steps // 2 + 10 * k))
+        out.append((mesh, mat, loads, 20.0 + 5.0 * k))
+    return out
+
+
+def _instances(S, spec):
+    ins = []
+    for mesh, mat, ld, alpha in spec:
+        ins.append(S.Instance(mesh.X, mesh.conn, mat.E, mat.nu, model=mat.model, rho=mat.rho, eta_ratio=mat.eta_ratio,
+                              fibre=mat.fibre, hg_kappa=mat.hg_kappa, bc_node=ld.bc_node, bc_mask=ld.bc_mask,
+                              bc_target=ld.bc_target, ramp=ld.ramp, t_ramp=ld.t_ramp, alpha=alpha))
+    return ins
+
+
+def _oracle_run(mesh, mat, ld, alpha, dt, n_steps):
+    ora = oracle.Oracle(mesh.X, mesh.conn, mat.E, mat.nu, model=mat.model, rho=mat.rho, eta_ratio=mat.eta_ratio,
+                        fibre=mat.fibre, hg_kappa=mat.hg_kappa)
+    np.testing.assert_allclose(dt, 0.9 * ora.dt_crit, rtol=1e-12)
+    u, up = np.zeros((mesh.n_nodes, 3)), np.zeros((mesh.n_nodes, 3))
+    t_ramp = ld.t_ramp if ld.t_ramp >= 0 else -ld.t_ramp * dt
+    rc, done, _ = ora.run(u, up, n_steps, dt, alpha, ld.bc_node, ld.bc_mask, ld.bc_target, ramp=ld.ramp,
+                          t_ramp=t_ramp)
+    assert rc == 0 and done == n_steps
+    return u
+
+
+@pytest.mark.parametrize("prec,variant", [("fp32", 1), ("fp32", 0), ("fp32", 2), ("fp32", 3), ("fp64", 0)])
+def test_batch_matches_oracle_per_instance(S, prec, variant):
+    n_steps = 160
+    spec = _mixed(n_steps)
+    b = S.Batch(_instances(S, spec), precision=prec, variant=variant)
+    inf = b.info()
+    say(f"{prec} v{variant}: {inf['n_inst']} instances, {inf['n_kinds']} kinds, {inf['n_items']} chunks, "
+        f"grid {inf['grid_blocks']}x{inf['block_threads']}")
+    st = b.run(n_steps)
+    assert st.code == 0 and st.steps_done == n_steps
+    say(f"  graph={b.info()['graph']} kernel {st.kernel_ms:.2f} ms")
+    tol = 1e-4 if prec == "fp32" else 1e-10
+    for i, (mesh, mat, ld, alpha) in enumerate(spec):
+        d = b.instance(i)
+        assert d["n_nodes"] == mesh.n_nodes and d["n_elems"] == mesh.n_elems and d["alpha"] == alpha
+        uo = _oracle_run(mesh, mat, ld, alpha, d["dt"], n_steps)
+        ug = b.read(i).double().cpu().numpy()
+        err = np.abs(ug - uo).max() / np.abs(uo).max()
+        say(f"  instance {i} ({mesh.ne}-node, model {mat.model}, {mesh.n_elems} el): rel error {err:.2e}")
+        assert err <= tol
+    b.close()
+
+
+def test_batch_run_splitting_and_graph_are_bitwise_neutral(S):
+    spec = _mixed(120, seed=3)
+    ins = _instances(S, spec)
+    a = S.Batch(ins, use_graph=True)
+    assert a.run(120).code == 0
+    assert a.info()["graph"] == 1, "the run should replay a captured graph"
+    ua = [a.read(i, with_prev=True) for i in range(len(spec))]
+    b = S.Batch(ins, use_graph=False, steps_per_launch=16)
+    for n in (50, 30, 40):
+        assert b.run(n).code == 0
+    for i in range(len(spec)):
+        ub, upb = b.read(i, with_prev=True)
+        assert torch.equal(ua[i][0], ub) and torch.equal(ua[i][1], upb)
+    # graph replay of a second run continues from the state
+    a.reset()
+    assert a.run(120).code == 0 and a.info()["graph"] == 1
+    assert torch.equal(a.read(0), ua[0][0])
+    a.close()
+    b.close()
+
+
+def test_batch_write_read_and_single_instance_equivalence(S):
+    spec = _mixed(100, seed=5)[:2]
+    b = S.Batch(_instances(S, spec), precision="fp64", variant=0)
+    mesh = spec[1][0]
+    g = torch.Generator().manual_seed(0)
+    u = (1e-4 * torch.randn((mesh.n_nodes, 3), generator=g, dtype=torch.float64)).cuda()
+    up = (1e-4 * torch.randn((mesh.n_nodes, 3), generator=g, dtype=torch.float64)).cuda()
+    b.write(1, u, up)
+    r, rp = b.read(1, with_prev=True)
+    assert torch.equal(r, u) and torch.equal(rp, up)
+    assert torch.count_nonzero(b.read(0)) == 0
+    # the batch instance and a single-mesh context advance the same state alike
+    m, mat, ld, alpha = spec[1]
+    sv = S.Solver(m.X, m.conn, mat.E, mat.nu, model=mat.model, eta_ratio=mat.eta_ratio, fibre=mat.fibre,
+                  precision="fp64", alpha=alpha)
+    assert sv.info()["dt"] == b.instance(1)["dt"]
+    ls = sv.loadset(ld.bc_node, ld.bc_mask, ld.bc_target, ld.ramp, -ld.t_ramp * sv.info()["dt"])
+    su, sup = u.clone(), up.clone()
+    assert b.run(60).code == 0
+    st, _ = sv.step(su, sup, 60, ls)
+    assert st.code == 0
+    err = (b.read(1) - su).abs().max().item() / su.abs().max().item()
+    say(f"batch vs single context (FP64): {err:.2e}")
+    assert err <= 1e-12
+    b.close()
+
+
+def test_batch_reports_the_inverted_instance(S):
+    spec = _mixed(40, seed=9)[:3]
+    mesh, mat, ld, alpha = spec[2]
+    ld.bc_target = ld.bc_target.copy()
+    ld.bc_target[len(mesh.bottom):] = [0.0, 0.0, -3.0 * mesh.height]  # crush instance 2 through itself
+    ld.ramp, ld.t_ramp = W.RAMP_LINEAR, -20.0
+    b = S.Batch(_instances(S, spec))
+    st = b.run(400, raise_on_error=False)
+    say(f"code {st.code} at step {st.error_step}, instance {b.info()['error_inst']}, element {st.error_elem}")
+    assert st.code in (-3, -4)
+    assert b.info()["error_inst"] == 2
+    assert 0 < st.steps_done < 400
+    assert torch.isfinite(b.read(0)).all()
+    b.close()
+
+
+def test_batch_autotune_picks_a_candidate(S):
+    spec = _mixed(80, seed=13)
+    b = S.Batch(_instances(S, spec), autotune=True, tune_steps=10)
+    inf = b.info()
+    say(f"autotune: {inf['tune_candidates']} candidates in {inf['tune_ms']:.0f} ms -> variant {inf['variant']}, "
+        f"chunk {inf['chunk_elems']}, steps/launch {inf['steps_per_launch']}")
+    assert inf["tune_candidates"] >= 2
+    assert b.run(80).code == 0
+    for i in (0, 3):
+        mesh, mat, ld, alpha = spec[i]
+        uo = _oracle_run(mesh, mat, ld, alpha, b.instance(i)["dt"], 80)
+        err = np.abs(b.read(i).double().cpu().numpy() - uo).max() / np.abs(uo).max()
+        assert err <= 1e-4
+    b.close()

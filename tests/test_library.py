@@ -8,12 +8,13 @@ import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "djtled.h")
+HEADERS = [os.path.join(ROOT, "include", f) for f in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if f.endswith(".h")]
 
 
 def _declared():
-    txt = open(HEADER).read()
-    return sorted(set(re.findall(r"\b(djtled_[a-z_]+)\s*\(", txt)))
+    txt = "".join(open(h).read() for h in HEADERS)
+    return sorted(set(re.findall(r"\b(djtled_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_header_declares_the_entry_points():
