@@ -20,8 +20,6 @@ using namespace dj;
 
 namespace {
 
-constexpr int KMAXB = 64;  // work items per workgroup (the kernel's LDS list)
-
 struct Batch {
     int device = 0, prec = DJ_FP32, n_inst = 0;
     int variant = 1, chunk_elems = 0, spl = 0, use_graph = 1;
@@ -251,7 +249,8 @@ int build_batch(Batch &b, const std::vector<int> &sel, const djtled_mesh *meshes
     b.block = blk;
     b.grid = std::min(bpc * prop.multiProcessorCount, b.n_items);
     if ((b.n_items + b.grid - 1) / b.grid > KMAXB)
-        return fail(DJ_ERR_UNSUPPORTED, "batch needs more than 64 chunks per workgroup; use larger chunks");
+        return fail(DJ_ERR_UNSUPPORTED, "batch needs more than " + std::to_string(KMAXB) +
+                                            " chunks per workgroup; use larger chunks");
     // workgroups holding each instance's chunks (for per-instance completion times)
     b.inst_wgs.assign(b.n_inst, {});
     for (int j = 0; j < b.n_items; j++) {
@@ -486,16 +485,17 @@ int djtled_batch_create(int32_t n, const djtled_mesh *meshes, const djtled_mater
     for (int i = 0; i < n; i++) all[i] = i;
     int chunk = tn.chunk_elems;
     int n_cand = 0;
+    std::vector<std::pair<int, int>> cands;  // (variant, chunk) in order of preference
     double t_tune = 0;
     const int tsteps = tn.tune_steps > 0 ? tn.tune_steps : 20;
     if (tn.autotune) {
-        // candidates timed on every m-th instance (at least 16 instances when there are that many)
+        // candidates timed on every m-th instance (m <= 8, at least 16 instances when there are that many)
         const double t0 = now_ms();
-        const int m = std::max(1, n / 16 >= 4 ? 4 : 1);
+        const int m = std::max(1, std::min(8, n / 16));
         std::vector<int> sub;
         for (int i = 0; i < n; i += m) sub.push_back(i);
         std::vector<int> vs = prec == DJ_FP32 ? std::vector<int>{1, 2, 0, 3} : std::vector<int>{0};
-        double best = std::numeric_limits<double>::infinity();
+        std::vector<std::pair<double, std::pair<int, int>>> ranked;  // time per element-step, (variant, chunk)
         for (int v : vs)
             for (int cf : {0, 2}) {
                 Batch *t = new Batch();
@@ -518,12 +518,7 @@ int djtled_batch_create(int32_t n, const djtled_mesh *meshes, const djtled_mater
                     if (rc == DJ_OK) rc = run_batch(*t, tsteps, &st, nullptr);
                     if (rc == DJ_OK && st.kernel_ms > 0) {
                         n_cand++;
-                        const double per = st.kernel_ms / (double(t->n_elems) * tsteps);
-                        if (per < best) {
-                            best = per;
-                            variant = v;
-                            chunk = t->chunk_elems;
-                        }
+                        ranked.push_back({st.kernel_ms / (double(t->n_elems) * tsteps), {v, t->chunk_elems}});
                     }
                 }
                 destroy_batch(t);
@@ -531,19 +526,28 @@ int djtled_batch_create(int32_t n, const djtled_mesh *meshes, const djtled_mater
             }
         t_tune = now_ms() - t0;
         if (n_cand == 0) return fail(DJ_ERR_UNSUPPORTED, "autotuner: no batch kernel candidate ran");
+        std::sort(ranked.begin(), ranked.end());
+        for (auto &r : ranked) cands.push_back(r.second);
+    } else {
+        cands.push_back({variant, chunk});
     }
-    Batch *b = new Batch();
-    b->device = dev;
-    b->prec = prec;
-    b->spl = tn.steps_per_launch;
-    b->use_graph = tn.use_graph ? 1 : 0;
-    int rc = build_batch(*b, all, meshes, materials, loads, alpha, params, variant, chunk);
-    if (rc != DJ_OK) {
+    // the best candidate that can hold the whole batch
+    Batch *b = nullptr;
+    int rc = DJ_OK;
+    for (auto &c : cands) {
+        b = new Batch();
+        b->device = dev;
+        b->prec = prec;
+        b->spl = tn.steps_per_launch;
+        b->use_graph = tn.use_graph ? 1 : 0;
+        rc = build_batch(*b, all, meshes, materials, loads, alpha, params, c.first, c.second);
+        if (rc == DJ_OK) break;
         std::string msg = g_err;
         destroy_batch(b);
+        b = nullptr;
         g_err = msg;
-        return rc;
     }
+    if (!b) return rc;
     if (tn.autotune && tn.steps_per_launch == 0) {
         // steps per launch: one launch per run against launches of 32 steps
         const double t0 = now_ms();

@@ -6,6 +6,8 @@
 
 namespace dj {
 
+constexpr int KMAXB = 128;  // work items (chunks) per workgroup: the kernel's LDS list
+
 // Device view of one element kind of a batch (a multi-instance context plus
 // the load set of its instances).
 struct BatchKind {

@@ -20,8 +20,6 @@ namespace dj {
 
 namespace {
 
-constexpr int KMAXB = 64;  // work items per workgroup
-
 template <typename T, int V>
 struct Kinds {
     static constexpr Variant v4 = var_table<T, 4>()[V];

@@ -204,7 +204,7 @@ __global__ void k_to_bf16(const float *__restrict__ x, int M, int K, uint16_t *_
     y[i] = k < K ? f2bf(x[int64_t(m) * K + k]) : uint16_t(0);
 }
 
-__global__ void k_sum_parts(const double *__restrict__ p, int n, double *__restrict__ out) {
+__global__ void k_sum_parts(const double *__restrict__ p, int n, double scale, double *__restrict__ out) {
     __shared__ double s[256];
     double a = 0.0;
     for (int i = threadIdx.x; i < n; i += 256) a += p[i];
@@ -214,7 +214,7 @@ __global__ void k_sum_parts(const double *__restrict__ p, int n, double *__restr
         if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = s[0];
+    if (threadIdx.x == 0) *out = s[0] * scale;
 }
 
 // Adam on one tensor; refreshes the BF16 copy when given
@@ -396,7 +396,7 @@ int djtled_mlp_loss_grad(const djtled_mlp *m, int32_t batch, const float *P, con
     g.loss_part = w.loss_part;
     MLP_HIP((gemm<true, true, EPI_LOSS>(g, 1, s)));
     const int tiles = ((O + BN - 1) / BN) * ((B + BM - 1) / BM);
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, w.loss_part, tiles, w.loss);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, w.loss_part, tiles, 1.0 / (double(B) * m->n_out), w.loss);
     MLP_HIP(hipGetLastError());
     // dW3 [O x H] = dY^T H2  (A = dY: M contiguous; B = H2: N contiguous)
     g = ga(O, H, B, w.dY, O, w.H2, H);

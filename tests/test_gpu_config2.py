@@ -7,10 +7,10 @@ Tolerances:
     compared with the oracle's (<= 1e-4, the full-run displacement bar); FP32
     relaxation itself stalls near r ~ 1e-5 (rounding of the FP32 forces and
     displacements), so it is asked for r <= 3e-5.
-  * full size (about 1.2M tets / 213k nodes): FP32 relaxation to r <= 5e-5,
-    continued in FP64 to r <= 1e-6.  The oracle then recomputes r from the
-    final state (<= 1.1e-6) and the FP32 force at that state (<= 1e-5
-    relative).
+  * full size (about 1.2M tets / 213k nodes): FP32 relaxation to r <= 1e-3
+    (its rounding floor here is near 4e-4), continued in FP64 to r <= 1e-6.
+    The oracle then recomputes r from the final state (<= 1.1e-6) and the
+    FP32 force at that state (<= 1e-5 relative).
 """
 import sys
 import time
@@ -92,7 +92,7 @@ def test_config2_full_size_mixed_precision_relaxation(S):
     s32 = S.from_workload(wl, precision="fp32")
     u, up = s32.zeros(), s32.zeros()
     t0 = time.perf_counter()
-    st, step = _relax(s32, wl, u, up, 5e-5)
+    st, step = _relax(s32, wl, u, up, 1e-3)
     torch.cuda.synchronize()
     t32 = time.perf_counter() - t0
     say(f"  fp32: {st.steps_done} steps, r={st.residual:.2e}, {t32:.2f} s, "

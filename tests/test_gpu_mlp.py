@@ -136,7 +136,9 @@ def test_adam_step_matches_oracle(M):
         omlp.adam(ref, gr, m, v, t, 1e-3)
     for k in ref:
         got = net.w[k][: ref[k].shape[0]].double().cpu().numpy()
-        assert np.abs((got - w0[k]) - (ref[k] - w0[k])).max() <= 1e-5 * np.abs(ref[k] - w0[k]).max() + 1e-9, k
+        # FP32 weights: the step is exact to a few units in the last place of w
+        tol = 1e-5 * np.abs(ref[k] - w0[k]).max() + 4 * 2.0 ** -24 * np.abs(w0[k]).max()
+        assert np.abs(got - ref[k]).max() <= tol, k
     wb = net.wb["W2"].float().cpu().numpy()
     np.testing.assert_array_equal(wb, omlp.bf16(net.w["W2"].cpu().numpy()).astype(np.float32))
 
