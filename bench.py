@@ -39,13 +39,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2106_14189_amd", "csrc", "djtled_kernels.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_2106_14189_amd", "csrc", f) for f in ("djtled_kernels.hip", "djtled_device.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "djtled_step_cube64_t4_traffic.json")
 METRIC = "DJ-TLED element-steps/sec + HBM GB/s; warm-start vs plain time-to-1e-3"
 
 
 def _src_sha() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    """sha256 of the step kernel's sources (the kernel file and its device header)."""
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def _traffic(bytes_scale_steps: int):

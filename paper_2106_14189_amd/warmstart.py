@@ -132,6 +132,38 @@ def steady_states(mesh, mat, fam: PatchFamily, P: np.ndarray, n_steps: int, t_ra
     return U, dev_ms / 1e3
 
 
+def steady_states_single(sv: S.Solver, fam: PatchFamily, P: np.ndarray, tol: float, t_ramp: float,
+                         check_every: int = 100, max_steps: int = 400000, sv64: S.Solver | None = None,
+                         tol64: float = 1e-6, log=None) -> tuple[torch.Tensor, float]:
+    """Relaxed states for every load in P on one context (meshes too large to
+    batch): relaxation to r <= tol, optionally continued on an FP64 context to
+    r <= tol64.  Returns (U [n x 3N] float32 on the GPU, device seconds)."""
+    n, N = len(P), sv.n_nodes
+    U = torch.empty((n, 3 * N), dtype=torch.float32, device="cuda")
+    dev_ms = 0.0
+    for i, p in enumerate(P):
+        ls = sv.loadset(fam.bc_node, fam.bc_mask, fam.targets(p), L.DJ_RAMP_SMOOTH, t_ramp)
+        u, up = sv.zeros(), sv.zeros()
+        st, step = sv.step(u, up, max_steps, ls, relax=True, tol=tol, check_every=check_every)
+        ls.close()
+        if st.code != 1:
+            raise RuntimeError(f"relaxation of load {i} did not converge: {st}")
+        dev_ms += st.kernel_ms
+        if sv64 is not None:
+            ls = sv64.loadset(fam.bc_node, fam.bc_mask, fam.targets(p), L.DJ_RAMP_SMOOTH, t_ramp)
+            u64, up64 = u.double(), up.double()
+            st, _ = sv64.step(u64, up64, max_steps, ls, step0=step, relax=True, tol=tol64, check_every=check_every)
+            ls.close()
+            if st.code != 1:
+                raise RuntimeError(f"FP64 relaxation of load {i} did not converge: {st}")
+            dev_ms += st.kernel_ms
+            u = u64.float()
+        U[i] = u.reshape(-1)
+        if log and (i % max(1, n // 8) == 0 or i == n - 1):
+            log(f"  relaxed {i + 1}/{n}: {st.steps_done} steps, r = {st.residual:.2e}")
+    return U, dev_ms / 1e3
+
+
 def residual_of(sv: S.Solver, fam: PatchFamily, p: np.ndarray, u: torch.Tensor, check_every: int = 1) -> float:
     """The relaxation residual of state u under load p (one RELAX check, no step)."""
     ls = sv.loadset(fam.bc_node, fam.bc_mask, fam.targets(p), L.DJ_RAMP_NONE, 0.0)
@@ -182,20 +214,31 @@ def solve_to_error(sv: S.Solver, fam: PatchFamily, p: np.ndarray, u_ref: torch.T
 
 def experiment(mesh, mat, alpha: float, n_train: int, n_test: int, seed: int, relax_steps: int, t_ramp: float,
                hidden: int = 512, epochs: int = 200, batch: int = 64, lr: float = 1e-3, per_batch: int = 64,
-               chunk: int = 50, log=print) -> dict:
-    """Train on n_train steady states, compare warm and cold starts on n_test loads."""
+               chunk: int = 50, single: bool = False, tol_train: float = 1e-3, log=print) -> dict:
+    """Train on n_train steady states, compare warm and cold starts on n_test loads.
+    single=False: steady states from batches of instances (relax_steps fixed
+    steps); single=True (large meshes): one context, FP32 relaxation to
+    tol_train for training data, and an FP64 finish to 1e-6 for the held-out
+    references."""
     rng = np.random.default_rng(seed)
     fam = PatchFamily(mesh, seed=seed)
     P_tr, P_te = fam.sample(rng, n_train), fam.sample(rng, n_test)
     log(f"mesh {mesh.n_elems} elements / {mesh.n_nodes} nodes; {len(fam.bc_node)} prescribed nodes; "
         f"{n_train} training and {n_test} held-out loads")
-    t0 = time.perf_counter()
-    U_tr, gen_s = steady_states(mesh, mat, fam, P_tr, relax_steps, t_ramp, alpha, per_batch, log)
-    U_te, gen_te_s = steady_states(mesh, mat, fam, P_te, relax_steps, t_ramp, alpha, per_batch, log)
-    gen_wall = time.perf_counter() - t0
-    # the reference states must be converged: residual of a few of them
     sv = S.Solver(mesh.X, mesh.conn, mat.E, mat.nu, model=mat.model, rho=mat.rho, eta_ratio=mat.eta_ratio,
                   fibre=mat.fibre, hg_kappa=mat.hg_kappa, alpha=alpha)
+    t0 = time.perf_counter()
+    if single:
+        sv64 = S.Solver(mesh.X, mesh.conn, mat.E, mat.nu, model=mat.model, rho=mat.rho, eta_ratio=mat.eta_ratio,
+                        fibre=mat.fibre, hg_kappa=mat.hg_kappa, alpha=alpha, precision="fp64")
+        U_tr, gen_s = steady_states_single(sv, fam, P_tr, tol_train, t_ramp, log=log)
+        U_te, gen_te_s = steady_states_single(sv, fam, P_te, tol_train, t_ramp, sv64=sv64, log=log)
+        sv64.close()
+    else:
+        U_tr, gen_s = steady_states(mesh, mat, fam, P_tr, relax_steps, t_ramp, alpha, per_batch, log)
+        U_te, gen_te_s = steady_states(mesh, mat, fam, P_te, relax_steps, t_ramp, alpha, per_batch, log)
+    gen_wall = time.perf_counter() - t0
+    # the reference states must be converged: residual of a few of them
     res = [residual_of(sv, fam, P_te[i], U_te[i].reshape(-1, 3)) for i in range(min(4, n_test))]
     log(f"  data: {gen_s + gen_te_s:.1f} s device, {gen_wall:.1f} s wall; held-out residuals {max(res):.2e}")
     # network: inputs are the encoded load vectors, outputs u / AMP_MAX
