@@ -222,6 +222,19 @@ def bench_warm_start(log) -> dict:
     return r
 
 
+def bench_warm_start_full(log) -> dict:
+    """The warm-start pipeline on the full ~1.2M-tet ellipsoid (single-context
+    relaxations; FP64-finished references for the held-out loads)."""
+    from paper_2106_14189_amd import warmstart
+    from paper_2106_14189_amd import workloads as W
+    wl = W.config2()
+    r = warmstart.experiment(wl.mesh, wl.material, wl.alpha, n_train=256, n_test=8, seed=4, relax_steps=0,
+                             t_ramp=0.4, hidden=512, epochs=100, batch=64, lr=1e-3, single=True, tol_train=1e-3,
+                             chunk=200, log=log)
+    r["workload"] = "ellipsoid1200k_t4_ti_fp32_patch_loads"
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,6 +249,8 @@ def main():
     ap.add_argument("--no-relax", action="store_true", help="skip the ellipsoid relaxation measurement")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start measurement")
     ap.add_argument("--no-mlp", action="store_true", help="skip the full-size network timing")
+    ap.add_argument("--warm-full", action="store_true",
+                    help="also run the warm-start pipeline on the full ellipsoid (several GPU-minutes)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -335,7 +350,8 @@ def main():
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
     extra = {}
     for name, skip, fn in (("batch", args.no_batch, bench_batch), ("relaxation", args.no_relax, bench_relaxation),
-                           ("mlp", args.no_mlp, bench_mlp), ("warm_start", args.no_warm, bench_warm_start)):
+                           ("mlp", args.no_mlp, bench_mlp), ("warm_start", args.no_warm, bench_warm_start),
+                           ("warm_start_full", not args.warm_full, bench_warm_start_full)):
         if skip:
             continue
         try:

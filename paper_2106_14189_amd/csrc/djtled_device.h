@@ -722,10 +722,15 @@ __global__ void k_scatter_in(const int32_t *__restrict__ cnode, int n_copies, co
 }
 
 // Kernel variants per (precision, element type): {threads, elements per thread, copies per thread}
-constexpr Variant VAR_T4F[4] = {{256, 4, 2}, {256, 2, 2}, {512, 2, 2}, {128, 4, 2}};
-constexpr Variant VAR_H8F[4] = {{256, 2, 4}, {256, 1, 4}, {512, 1, 3}, {128, 2, 4}};
-constexpr Variant VAR_T4D[4] = {{256, 2, 2}, {256, 1, 2}, {512, 1, 2}, {128, 2, 2}};
-constexpr Variant VAR_H8D[4] = {{256, 1, 4}, {128, 1, 4}, {512, 1, 3}, {128, 2, 4}};
+// Variants 4 and 5 trade register spills for a third wave per SIMD.
+constexpr Variant VAR_T4F[N_VARIANTS] = {{256, 4, 2, 1}, {256, 2, 2, 1}, {512, 2, 2, 1},
+                                         {128, 4, 2, 1}, {256, 4, 2, 3}, {256, 2, 2, 3}};
+constexpr Variant VAR_H8F[N_VARIANTS] = {{256, 2, 4, 1}, {256, 1, 4, 1}, {512, 1, 3, 1},
+                                         {128, 2, 4, 1}, {256, 1, 4, 3}, {512, 1, 3, 3}};
+constexpr Variant VAR_T4D[N_VARIANTS] = {{256, 2, 2, 1}, {256, 1, 2, 1}, {512, 1, 2, 1},
+                                         {128, 2, 2, 1}, {256, 2, 2, 1}, {256, 2, 2, 1}};
+constexpr Variant VAR_H8D[N_VARIANTS] = {{256, 1, 4, 1}, {128, 1, 4, 1}, {512, 1, 3, 1},
+                                         {128, 2, 4, 1}, {256, 1, 4, 1}, {256, 1, 4, 1}};
 
 template <typename T, int NE>
 constexpr const Variant *var_table() {

@@ -61,7 +61,9 @@ inline int n_planes(int ne, int model) {
 // capacity is block * ept elements.
 struct Variant {
     int block, ept, mcopy;  // mcopy: node copies per thread a chunk may hold
+    int wpe;                // minimum waves per SIMD the step kernel is compiled for (register budget)
 };
+constexpr int N_VARIANTS = 6;
 const std::vector<Variant> &variants(int ne, int prec);
 
 // Everything the kernels need, as device pointers.

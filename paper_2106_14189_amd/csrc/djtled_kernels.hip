@@ -28,8 +28,8 @@ __global__ void __launch_bounds__(BLOCK) k_forces_shared(DevTopo tp, StepPtrs<T>
 // published before a common barrier, so they leave the loop together.
 constexpr int KMAX = 32;  // chunks per workgroup
 
-template <typename T, int NE, int MODEL, int BLOCK, int EPT, int MC>
-__global__ void __launch_bounds__(BLOCK) k_step(DevTopo tp, StepArgs a) {
+template <typename T, int NE, int MODEL, int BLOCK, int EPT, int MC, int WPE>
+__global__ void __launch_bounds__(BLOCK, WPE) k_step(DevTopo tp, StepArgs a) {
     using C = Chunk<T, NE, MODEL, BLOCK, EPT, MC>;
     constexpr int KB = 4;  // chunks per shared-phase batch
     extern __shared__ __align__(16) unsigned char smem[];
@@ -337,12 +337,12 @@ __global__ void k_reset_sync(uint32_t *sync, int n_sync, int32_t *status) {
 // Dispatch over (precision, element type, model, variant)
 // ---------------------------------------------------------------------------
 
-template <typename T, int NE, int MODEL, int BLOCK, int EPT, int MC>
+template <typename T, int NE, int MODEL, int BLOCK, int EPT, int MC, int WPE>
 struct Inst {
     using C = Chunk<T, NE, MODEL, BLOCK, EPT, MC>;
     static hipError_t occ(int *bpc, size_t *lds) {
         *lds = C::LDS;
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, k_step<T, NE, MODEL, BLOCK, EPT, MC>, BLOCK, C::LDS);
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, k_step<T, NE, MODEL, BLOCK, EPT, MC, WPE>, BLOCK, C::LDS);
     }
     static hipError_t forces(Ctx &c, const void *u, void *f, hipStream_t s) {
         const int L = c.topo.n_copies, B = 256;
@@ -393,11 +393,11 @@ struct Inst {
         DevTopo tp = c.topo;
         StepArgs aa = a;
         void *args[] = {&tp, &aa};
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_step<T, NE, MODEL, BLOCK, EPT, MC>),
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_step<T, NE, MODEL, BLOCK, EPT, MC, WPE>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(C::LDS));
         if (e != hipSuccess) return e;
         if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
-        e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_step<T, NE, MODEL, BLOCK, EPT, MC>),
+        e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_step<T, NE, MODEL, BLOCK, EPT, MC, WPE>),
                                        dim3(c.grid), dim3(BLOCK), args, C::LDS, s);
         if (e != hipSuccess) return e;
         if (ev1) e = hipEventRecord(ev1, s);
@@ -406,7 +406,8 @@ struct Inst {
 };
 
 template <typename T, int NE, int MODEL, int V>
-using InstV = Inst<T, NE, MODEL, var_table<T, NE>()[V].block, var_table<T, NE>()[V].ept, var_table<T, NE>()[V].mcopy>;
+using InstV = Inst<T, NE, MODEL, var_table<T, NE>()[V].block, var_table<T, NE>()[V].ept, var_table<T, NE>()[V].mcopy,
+                  var_table<T, NE>()[V].wpe>;
 
 template <typename T, int NE, int MODEL, typename F>
 static hipError_t with_variant(int v, F &&f) {
@@ -415,6 +416,8 @@ static hipError_t with_variant(int v, F &&f) {
         case 1: return f(InstV<T, NE, MODEL, 1>());
         case 2: return f(InstV<T, NE, MODEL, 2>());
         case 3: return f(InstV<T, NE, MODEL, 3>());
+        case 4: return f(InstV<T, NE, MODEL, 4>());
+        case 5: return f(InstV<T, NE, MODEL, 5>());
         default: return hipErrorInvalidValue;
     }
 }
@@ -430,8 +433,8 @@ static hipError_t dispatch(int prec, int ne, int model, int v, F &&f) {
 }
 
 const std::vector<Variant> &variants(int ne, int prec) {
-    static const std::vector<Variant> t4f(VAR_T4F, VAR_T4F + 4), h8f(VAR_H8F, VAR_H8F + 4);
-    static const std::vector<Variant> t4d(VAR_T4D, VAR_T4D + 4), h8d(VAR_H8D, VAR_H8D + 4);
+    static const std::vector<Variant> t4f(VAR_T4F, VAR_T4F + N_VARIANTS), h8f(VAR_H8F, VAR_H8F + N_VARIANTS);
+    static const std::vector<Variant> t4d(VAR_T4D, VAR_T4D + N_VARIANTS), h8d(VAR_H8D, VAR_H8D + N_VARIANTS);
     if (prec == DJ_FP32) return ne == 4 ? t4f : h8f;
     return ne == 4 ? t4d : h8d;
 }

@@ -64,47 +64,63 @@ struct GemmArgs {
     int k_per_split;       // multiple of BKT
 };
 
-template <bool AK>
-__device__ __forceinline__ void load_tile(const uint16_t *__restrict__ G, int64_t ld, int r0, int k0, int R, int K,
-                                          uint16_t (*S)[LDK], int kend) {
-    // 128 rows x 32 k = 512 vectors of 8 elements, two per thread
+// One 128 x 32 tile per operand: 512 vectors of 8 elements, two per thread.
+// fetch: global -> registers (zero outside the matrix or beyond kend);
+// stash: registers -> the K-contiguous LDS tile.
+struct TileRegs {
+    uint4 v[2];
+};
+
+template <bool KC>
+__device__ __forceinline__ void fetch_tile(const uint16_t *__restrict__ G, int64_t ld, int r0, int k0, int R, int kend,
+                                           TileRegs &t) {
 #pragma unroll
     for (int h = 0; h < 2; h++) {
         const int v = threadIdx.x + h * 256;
-        if (AK) {
-            const int r = v >> 2, kq = (v & 3) * 8;
-            const int gr = r0 + r, gk = k0 + kq;
-            uint16_t t[8];
+        uint16_t e[8];
+        if (KC) {
+            const int gr = r0 + (v >> 2), gk = k0 + (v & 3) * 8;
             if (gr < R && gk + 8 <= kend) {
-                const uint4 q = *reinterpret_cast<const uint4 *>(G + int64_t(gr) * ld + gk);
-                *reinterpret_cast<uint4 *>(t) = q;
-            } else {
-#pragma unroll
-                for (int i = 0; i < 8; i++) t[i] = (gr < R && gk + i < kend) ? G[int64_t(gr) * ld + gk + i] : 0;
+                t.v[h] = *reinterpret_cast<const uint4 *>(G + int64_t(gr) * ld + gk);
+                continue;
             }
-            *reinterpret_cast<uint4 *>(&S[r][kq]) = *reinterpret_cast<uint4 *>(t);
+#pragma unroll
+            for (int i = 0; i < 8; i++) e[i] = (gr < R && gk + i < kend) ? G[int64_t(gr) * ld + gk + i] : 0;
+        } else {
+            const int gk = k0 + (v >> 4), gr = r0 + (v & 15) * 8;
+            if (gk < kend && gr + 8 <= R) {
+                t.v[h] = *reinterpret_cast<const uint4 *>(G + int64_t(gk) * ld + gr);
+                continue;
+            }
+#pragma unroll
+            for (int i = 0; i < 8; i++) e[i] = (gk < kend && gr + i < R) ? G[int64_t(gk) * ld + gr + i] : 0;
+        }
+        t.v[h] = *reinterpret_cast<const uint4 *>(e);
+    }
+}
+
+template <bool KC>
+__device__ __forceinline__ void stash_tile(const TileRegs &t, uint16_t (*S)[LDK]) {
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const int v = threadIdx.x + h * 256;
+        if (KC) {
+            *reinterpret_cast<uint4 *>(&S[v >> 2][(v & 3) * 8]) = t.v[h];
         } else {
             const int k = v >> 4, rq = (v & 15) * 8;
-            const int gk = k0 + k, gr = r0 + rq;
-            uint16_t t[8];
-            if (gk < kend && gr + 8 <= R) {
-                const uint4 q = *reinterpret_cast<const uint4 *>(G + int64_t(gk) * ld + gr);
-                *reinterpret_cast<uint4 *>(t) = q;
-            } else {
+            const uint16_t *e = reinterpret_cast<const uint16_t *>(&t.v[h]);
 #pragma unroll
-                for (int i = 0; i < 8; i++) t[i] = (gk < kend && gr + i < R) ? G[int64_t(gk) * ld + gr + i] : 0;
-            }
-#pragma unroll
-            for (int i = 0; i < 8; i++) S[rq + i][k] = t[i];
+            for (int i = 0; i < 8; i++) S[rq + i][k] = e[i];
         }
     }
-    (void)K;
 }
 
 template <bool AK, bool BK, int EPI>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
-    __shared__ __align__(16) uint16_t As[BM][LDK];
-    __shared__ __align__(16) uint16_t Bs[BN][LDK];
+    // two LDS stages: the tiles of step k + 1 are fetched into registers while
+    // step k multiplies, then stored into the other stage; one barrier per step
+    __shared__ __align__(16) uint16_t As[2][BM][LDK];
+    __shared__ __align__(16) uint16_t Bs[2][BN][LDK];
     __shared__ double s_loss[4];
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int kbeg = blockIdx.z * g.k_per_split;
@@ -118,24 +134,33 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
         for (int j = 0; j < 2; j++)
 #pragma unroll
             for (int r = 0; r < 16; r++) acc[i][j][r] = 0.0f;
-    for (int k0 = kbeg; k0 < kend; k0 += BKT) {
-        load_tile<AK>(g.A, g.lda, m0, k0, g.M, g.K, As, kend);
-        load_tile<BK>(g.B, g.ldb, n0, k0, g.N, g.K, Bs, kend);
+    TileRegs ra, rb;
+    if (kbeg < kend) {
+        fetch_tile<AK>(g.A, g.lda, m0, kbeg, g.M, kend, ra);
+        fetch_tile<BK>(g.B, g.ldb, n0, kbeg, g.N, kend, rb);
+    }
+    int st = 0;
+    for (int k0 = kbeg; k0 < kend; k0 += BKT, st ^= 1) {
+        stash_tile<AK>(ra, As[st]);
+        stash_tile<BK>(rb, Bs[st]);
         __syncthreads();
+        if (k0 + BKT < kend) {
+            fetch_tile<AK>(g.A, g.lda, m0, k0 + BKT, g.M, kend, ra);
+            fetch_tile<BK>(g.B, g.ldb, n0, k0 + BKT, g.N, kend, rb);
+        }
 #pragma unroll
         for (int kk = 0; kk < BKT; kk += 16) {
             const int kq = kk + 8 * (lane >> 5);
             bf16x8 a[2], b[2];
 #pragma unroll
-            for (int i = 0; i < 2; i++) a[i] = *reinterpret_cast<const bf16x8 *>(&As[wm + 32 * i + (lane & 31)][kq]);
+            for (int i = 0; i < 2; i++) a[i] = *reinterpret_cast<const bf16x8 *>(&As[st][wm + 32 * i + (lane & 31)][kq]);
 #pragma unroll
-            for (int j = 0; j < 2; j++) b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[wn + 32 * j + (lane & 31)][kq]);
+            for (int j = 0; j < 2; j++) b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[st][wn + 32 * j + (lane & 31)][kq]);
 #pragma unroll
             for (int i = 0; i < 2; i++)
 #pragma unroll
                 for (int j = 0; j < 2; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         }
-        __syncthreads();
     }
     // epilogue: acc[i][j][r] -> row wm + 32 i + 8 (r / 4) + 4 (lane / 32) + r % 4, col wn + 32 j + lane % 32
     double lsum = 0.0;

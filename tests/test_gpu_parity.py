@@ -61,7 +61,7 @@ def _oracle(mesh, E, nu, model, kw):
 @pytest.mark.parametrize("elem", [W.T4, W.H8])
 @pytest.mark.parametrize("model", [W.NH, W.TI])
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-@pytest.mark.parametrize("variant,chunk", [(0, 0), (0, 37), (1, 0), (2, 0), (3, 0)])
+@pytest.mark.parametrize("variant,chunk", [(0, 0), (0, 37), (1, 0), (2, 0), (3, 0), (4, 0), (5, 37)])
 def test_forces_parity(S, elem, model, prec, variant, chunk):
     say(f"forces elem={elem} model={model} prec={prec} variant={variant} chunk={chunk}")
     mesh, E, nu, kw, rng = _case(elem, model, n=7, seed=3 + variant)
@@ -142,7 +142,8 @@ def test_full_run_config0_fp64(S):
 
 @pytest.mark.parametrize("elem", [W.T4, W.H8])
 @pytest.mark.parametrize("model", [W.NH, W.TI])
-def test_full_run_fp32_small(S, elem, model):
+@pytest.mark.parametrize("variant", [0, 4, 5])
+def test_full_run_fp32_small(S, elem, model, variant):
     """FP32 run on a 10^3 cube (permuted, per-element E): <= 1e-4 after 600 steps."""
     mesh, E, nu, kw, rng = _case(elem, model, n=10, seed=21)
     n_steps = 600
@@ -152,8 +153,8 @@ def test_full_run_fp32_small(S, elem, model):
     wl = W.Workload("small", mesh, W.Material(model, E, np.full(mesh.n_elems, nu)), loads, 0.9, alpha=37.0)
     say(f"fp32 full run elem={elem} model={model}: oracle")
     uo, _ = _run_oracle(ora, wl, n_steps, dt, wl.alpha)
-    sv = _solver(S, mesh, E, nu, model, kw, "fp32", alpha=wl.alpha)
-    say("  gpu")
+    sv = _solver(S, mesh, E, nu, model, kw, "fp32", alpha=wl.alpha, variant=variant)
+    say(f"  gpu variant {variant}")
     ug, _ = _run_gpu(sv, wl, n_steps)
     err = np.abs(ug.double().cpu().numpy() - uo).max() / np.abs(uo).max()
     say(f"  rel max displacement error {err:.3e}")
