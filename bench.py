@@ -93,8 +93,8 @@ def _pct(x, q):
     return float(np.percentile(np.asarray(x), q))
 
 
-def bench_batch(log) -> dict:
-    """Config-3 batch: 256 instances, 500 steps, autotuned, graph replay."""
+def bench_batch(log, variant: int = -1) -> dict:
+    """Config-3 batch: 256 instances, 500 steps, autotuned (or a given kernel variant), graph replay."""
     from paper_2106_14189_amd import solver as S
     from paper_2106_14189_amd import workloads as W
     t0 = time.perf_counter()
@@ -104,7 +104,7 @@ def bench_batch(log) -> dict:
                       bc_target=ld.bc_target, ramp=ld.ramp, t_ramp=ld.t_ramp, alpha=al) for m, mat, ld, al in spec]
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
-    b = S.Batch(ins, autotune=True)
+    b = S.Batch(ins, autotune=variant < 0, variant=variant)
     t_build = time.perf_counter() - t0
     info = b.info()
     log(f"batch: {info['n_inst']} instances, {info['n_elems']} elements, variant {info['variant']}, "
@@ -246,6 +246,7 @@ def main():
     ap.add_argument("--copy-calib", action="store_true",
                     help="after the run, copy a 256 MiB buffer 4 times (calibrates rocprofv3 byte counters)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-instance batch measurement")
+    ap.add_argument("--batch-variant", type=int, default=-1, help="batch kernel variant (-1: autotune)")
     ap.add_argument("--no-relax", action="store_true", help="skip the ellipsoid relaxation measurement")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start measurement")
     ap.add_argument("--no-mlp", action="store_true", help="skip the full-size network timing")
@@ -349,7 +350,8 @@ def main():
     del runs
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
     extra = {}
-    for name, skip, fn in (("batch", args.no_batch, bench_batch), ("relaxation", args.no_relax, bench_relaxation),
+    for name, skip, fn in (("batch", args.no_batch, lambda lg: bench_batch(lg, args.batch_variant)),
+                           ("relaxation", args.no_relax, bench_relaxation),
                            ("mlp", args.no_mlp, bench_mlp), ("warm_start", args.no_warm, bench_warm_start),
                            ("warm_start_full", not args.warm_full, bench_warm_start_full)):
         if skip:

@@ -194,7 +194,7 @@ int build_batch(Batch &b, const std::vector<int> &sel, const djtled_mesh *meshes
             umat.fibre = fib.data();
         }
         djtled_params kp = *prm;
-        kp.variant = variant;
+        kp.variant = variant & 3;  // the chunk geometry of the batch kernel's variant (4..7: 0..3 + prefetch)
         kp.chunk_elems = chunk_elems;
         kp.dt = 0.0;
         MultiInst mi;
@@ -494,7 +494,7 @@ int djtled_batch_create(int32_t n, const djtled_mesh *meshes, const djtled_mater
         const int m = std::max(1, std::min(8, n / 16));
         std::vector<int> sub;
         for (int i = 0; i < n; i += m) sub.push_back(i);
-        std::vector<int> vs = prec == DJ_FP32 ? std::vector<int>{1, 2, 0, 3} : std::vector<int>{0};
+        std::vector<int> vs = prec == DJ_FP32 ? std::vector<int>{1, 2, 5, 6, 0, 3, 4, 7} : std::vector<int>{0};
         std::vector<std::pair<double, std::pair<int, int>>> ranked;  // time per element-step, (variant, chunk)
         for (int v : vs)
             for (int cf : {0, 2}) {

@@ -20,16 +20,21 @@ namespace dj {
 
 namespace {
 
+// Batch variant V: 0..3 use the step-kernel tables' variants 0..3 for every
+// kind; V + 4 is the same with the element data staged in LDS by prefetch.
 template <typename T, int V>
 struct Kinds {
-    static constexpr Variant v4 = var_table<T, 4>()[V];
-    static constexpr Variant v8 = var_table<T, 8>()[V];
+    static constexpr int VB = V & 3;
+    static constexpr bool PF = V >= 4;
+    static constexpr Variant v4 = var_table<T, 4>()[VB];
+    static constexpr Variant v8 = var_table<T, 8>()[VB];
     static_assert(v4.block == v8.block, "one block size for all element kinds");
     static constexpr int BLOCK = v4.block;
     template <int K>
     using C = Chunk<T, (K >= 2 ? 8 : 4), (K & 1) ? DJ_TI : DJ_NH, BLOCK, (K >= 2 ? v8.ept : v4.ept),
-                    (K >= 2 ? v8.mcopy : v4.mcopy), true>;
-    static constexpr size_t LDS = C<0>::LDS > C<2>::LDS ? C<0>::LDS : C<2>::LDS;
+                    (K >= 2 ? v8.mcopy : v4.mcopy), true, PF>;
+    static constexpr size_t mx(size_t a, size_t b) { return a > b ? a : b; }
+    static constexpr size_t LDS = mx(mx(C<0>::LDS, C<1>::LDS), mx(C<2>::LDS, C<3>::LDS));
 };
 
 template <typename F>
@@ -99,6 +104,17 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK)) k_batch_step(BatchDev bd
     __syncthreads();
     if (s_flag != 0) return;  // an earlier launch of this run stopped on an error
     if (threadIdx.x == 0 && bd.first_launch) bd.tstamp[2 * blockIdx.x] = uint64_t(wall_clock64());
+    // staged element data of chunk k + 1 is requested while chunk k is summed
+    auto prefetch = [&](int k) {
+        if constexpr (K::PF) {
+            const int kind = __builtin_amdgcn_readfirstlane(s_kind[k]);
+            on_kind(kind, [&](auto kc) {
+                constexpr int KC = decltype(kc)::value;
+                K::template C<KC>::prefetch(bd.k[KC].tp, s_ch[k], smem);
+            });
+        }
+    };
+    if (nmine > 0) prefetch(0);
     uint32_t epoch = 0;  // flags are cleared before every launch
     const int64_t step0 = bd.clock[0];
     int cur = int(bd.clock[1]);
@@ -111,10 +127,12 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK)) k_batch_step(BatchDev bd
         int bad_kind = -1;
         for (int k = 0; k < nmine; k++) {
             const int kind = __builtin_amdgcn_readfirstlane(s_kind[k]);
+            const int kn = k + 1 < nmine ? k + 1 : 0;
             on_kind(kind, [&](auto kc) {
                 constexpr int KC = decltype(kc)::value;
                 const StepPtrs<T> sp = kind_ptrs<T>(bd.k[KC], cur, prv, nxt, s, n);
-                K::template C<KC>::template element_phase<1>(bd.k[KC].tp, s_ch[k], sp, smem, po);
+                K::template C<KC>::template element_phase<1>(bd.k[KC].tp, s_ch[k], sp, smem, po,
+                                                              [&]() { prefetch(kn); });
             });
             if (po.bad && bad_kind < 0) bad_kind = kind;
         }
@@ -173,6 +191,7 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK)) k_batch_step(BatchDev bd
         __syncthreads();  // shared copies written above are read by other threads next step
         cur = nxt;
     }
+    __builtin_amdgcn_s_waitcnt(0);  // no staged load outlives the workgroup
     __syncthreads();
     if (code == DJ_ERR_BARRIER) {  // sticky for the launches that follow in this run
         if (threadIdx.x == 0) st_dev(&bd.status[0], int32_t(DJ_ERR_BARRIER));
@@ -237,6 +256,10 @@ hipError_t batch_dispatch(int prec, int v, F &&f) {
             case 1: return f(std::integral_constant<int, 1>(), float());
             case 2: return f(std::integral_constant<int, 2>(), float());
             case 3: return f(std::integral_constant<int, 3>(), float());
+            case 4: return f(std::integral_constant<int, 4>(), float());
+            case 5: return f(std::integral_constant<int, 5>(), float());
+            case 6: return f(std::integral_constant<int, 6>(), float());
+            case 7: return f(std::integral_constant<int, 7>(), float());
             default: return hipErrorInvalidValue;
         }
     }
@@ -246,7 +269,7 @@ hipError_t batch_dispatch(int prec, int v, F &&f) {
 
 }  // namespace
 
-bool batch_variant_ok(int prec, int v) { return prec == DJ_FP32 ? (v >= 0 && v < 4) : v == 0; }
+bool batch_variant_ok(int prec, int v) { return prec == DJ_FP32 ? (v >= 0 && v < 8) : v == 0; }
 
 hipError_t batch_occupancy(int prec, int v, int *bpc, size_t *lds, int *block) {
     return batch_dispatch(prec, v, [&](auto vc, auto t) {

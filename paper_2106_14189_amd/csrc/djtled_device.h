@@ -358,36 +358,88 @@ struct SharedRegs {  // round-A data of one shared copy per chunk of a batch
     T uc[KB][3], up[KB][3], rv[KB][3], A[KB], bp[KB], rr[KB];
 };
 
-// PC: per-copy B' and ramp rates (batches of instances with their own steps)
-template <typename T, int NE, int MODEL, int BLOCK, int EPT, int MC, bool PC = false>
+struct NoOp {
+    __device__ void operator()() const {}
+};
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+
+// PC: per-copy B' and ramp rates (batches of instances with their own steps).
+// PF: the chunk's element planes and slot positions are staged in LDS by
+// direct global -> LDS loads issued while the previous chunk is summed
+// (prefetch), instead of being loaded into registers at the chunk's start.
+template <typename T, int NE, int MODEL, int BLOCK, int EPT, int MC, bool PC = false, bool PF = false>
 struct Chunk {
     static constexpr int CMAX = BLOCK * EPT;
     static constexpr int NP = Planes<NE, MODEL>::N;
-    static constexpr size_t LDS = size_t(3) * NE * CMAX * sizeof(T);
+    static constexpr size_t SLOTS = size_t(3) * NE * CMAX * sizeof(T);
+    static constexpr int PDW = CMAX * int(sizeof(T)) / 4;  // dwords of one staged plane
+    static constexpr int WDW = CMAX / 2 + 2;               // dwords of one staged slot-position plane
+    static constexpr size_t STAGE = PF ? size_t(4) * (size_t(NP) * PDW + size_t(NE) * WDW) : 0;
+    static constexpr size_t LDS = SLOTS + STAGE;
 
-    // MODE 0: forces to the caller array; MODE 1: time-step update
-    template <int MODE>
+    // LDS-DMA loads of one chunk's element planes and slot positions into the
+    // staging area (dword granularity; each wave takes 64-dword pieces).
+    // Completion: s_waitcnt vmcnt + a workgroup barrier before the reads.
+    __device__ static void prefetch(const DevTopo &tp, const ChunkDesc &ch, unsigned char *smem) {
+        if constexpr (PF) {
+            constexpr int NW = BLOCK / 64;
+            const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+            uint32_t *stage = reinterpret_cast<uint32_t *>(smem + SLOTS);
+            uint32_t *wstage = stage + NP * PDW;
+            const int64_t es = tp.estride;
+            const int ndw = ch.elem_count * int(sizeof(T)) / 4;
+            const uint32_t *src = reinterpret_cast<const uint32_t *>(static_cast<const T *>(tp.elem) + ch.elem_begin);
+            const int64_t pstride = es * int64_t(sizeof(T)) / 4;  // dwords between planes
+#pragma unroll 1
+            for (int q = 0; q < NP; q++, src += pstride) {
+#pragma unroll 1
+                for (int i = w * 64; i < ndw; i += NW * 64)
+                    if (i + lane < ndw)
+                        __builtin_amdgcn_global_load_lds((glb_void_t *)(src + i + lane), (lds_void_t *)(stage + q * PDW + i),
+                                                         4, 0, 0);
+            }
+            const int e0 = ch.elem_begin & ~1;
+            const int nw = (ch.elem_begin + ch.elem_count - e0 + 1) / 2;
+            const uint32_t *wsrc = reinterpret_cast<const uint32_t *>(tp.wpos + e0);
+#pragma unroll 1
+            for (int a = 0; a < NE; a++, wsrc += es / 2) {
+#pragma unroll 1
+                for (int i = w * 64; i < nw; i += NW * 64)
+                    if (i + lane < nw)
+                        __builtin_amdgcn_global_load_lds((glb_void_t *)(wsrc + i + lane), (lds_void_t *)(wstage + a * WDW + i),
+                                                         4, 0, 0);
+            }
+        }
+    }
+
+    // MODE 0: forces to the caller array; MODE 1: time-step update.  `after`
+    // runs once the element forces are in LDS (PF: issues the next prefetch).
+    template <int MODE, typename After = NoOp>
     __device__ static void element_phase(const DevTopo &tp, const ChunkDesc &ch, const StepPtrs<T> &sp,
-                                         unsigned char *smem, PhaseOut &po) {
+                                         unsigned char *smem, PhaseOut &po, After after = After()) {
         const int tid = threadIdx.x;
         T *lx = reinterpret_cast<T *>(smem);
         T *ly = lx + NE * CMAX;
         T *lz = lx + 2 * NE * CMAX;
         const T *__restrict__ ep = static_cast<const T *>(tp.elem);
         const int64_t es = tp.estride;
-        // ---- one round of requests
+        // ---- one round of requests (element data from registers, or staged in LDS)
         T cst[EPT][NP];
         int wp[EPT][NE];
+        if constexpr (!PF) {
 #pragma unroll
-        for (int j = 0; j < EPT; j++) {
-            const int e = tid + j * BLOCK;
-            if (e < ch.elem_count) {
-                const T *src = ep + ch.elem_begin + e;
+            for (int j = 0; j < EPT; j++) {
+                const int e = tid + j * BLOCK;
+                if (e < ch.elem_count) {
+                    const T *src = ep + ch.elem_begin + e;
 #pragma unroll
-                for (int q = 0; q < NP; q++) cst[j][q] = __builtin_nontemporal_load(src + q * es);
-                const uint16_t *w = tp.wpos + ch.elem_begin + e;
+                    for (int q = 0; q < NP; q++) cst[j][q] = __builtin_nontemporal_load(src + q * es);
+                    const uint16_t *w = tp.wpos + ch.elem_begin + e;
 #pragma unroll
-                for (int a = 0; a < NE; a++) wp[j][a] = __builtin_nontemporal_load(w + a * es);
+                    for (int a = 0; a < NE; a++) wp[j][a] = __builtin_nontemporal_load(w + a * es);
+                }
             }
         }
         uint32_t cr[MC], fl[MC];
@@ -440,7 +492,22 @@ struct Chunk {
                 }
             }
         }
+        if constexpr (PF) __builtin_amdgcn_s_waitcnt(0);  // this thread's staged loads have landed
         __syncthreads();
+        if constexpr (PF) {
+            const T *stage = reinterpret_cast<const T *>(smem + SLOTS);
+            const uint16_t *wstage = reinterpret_cast<const uint16_t *>(smem + SLOTS) + 2 * NP * PDW + (ch.elem_begin & 1);
+#pragma unroll
+            for (int j = 0; j < EPT; j++) {
+                const int e = tid + j * BLOCK;
+                if (e < ch.elem_count) {
+#pragma unroll
+                    for (int q = 0; q < NP; q++) cst[j][q] = stage[q * CMAX + e];
+#pragma unroll
+                    for (int a = 0; a < NE; a++) wp[j][a] = wstage[a * 2 * WDW + e];
+                }
+            }
+        }
         // ---- element forces, written back over the element's own positions
 #pragma unroll
         for (int j = 0; j < EPT; j++) {
@@ -473,6 +540,7 @@ struct Chunk {
             }
         }
         __syncthreads();
+        after();
         // ---- node sums over each copy's range, in fixed order
 #pragma unroll
         for (int m = 0; m < MC; m++) {

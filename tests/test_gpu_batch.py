@@ -73,7 +73,8 @@ def _oracle_run(mesh, mat, ld, alpha, dt, n_steps):
     return u
 
 
-@pytest.mark.parametrize("prec,variant", [("fp32", 1), ("fp32", 0), ("fp32", 2), ("fp32", 3), ("fp64", 0)])
+@pytest.mark.parametrize("prec,variant", [("fp32", 1), ("fp32", 0), ("fp32", 2), ("fp32", 3), ("fp32", 4), ("fp32", 5),
+                                          ("fp32", 6), ("fp32", 7), ("fp64", 0)])
 def test_batch_matches_oracle_per_instance(S, prec, variant):
     n_steps = 160
     spec = _mixed(n_steps)
@@ -172,5 +173,30 @@ def test_batch_autotune_picks_a_candidate(S):
         mesh, mat, ld, alpha = spec[i]
         uo = _oracle_run(mesh, mat, ld, alpha, b.instance(i)["dt"], 80)
         err = np.abs(b.read(i).double().cpu().numpy() - uo).max() / np.abs(uo).max()
+        assert err <= 1e-4
+    b.close()
+
+
+def test_full_size_config3_sampled_against_oracle(S):
+    """Config 3 at full size (256 instances, ~14.2M elements, 500 steps) in
+    the launch configuration the benchmark times (autotuned, graph replay):
+    every instance finite, and the three smallest instances against the
+    oracle (<= 1e-4)."""
+    spec = W.config3()
+    say(f"config3: {len(spec)} instances, {sum(m.n_elems for m, _, _, _ in spec)} elements")
+    b = S.Batch(_instances(S, spec), autotune=True)
+    inf = b.info()
+    say(f"  variant {inf['variant']}, chunk {inf['chunk_elems']}, steps/launch {inf['steps_per_launch']}")
+    st = b.run(500)
+    assert st.code == 0 and st.steps_done == 500, st
+    assert b.info()["graph"] == 1
+    for i in range(len(spec)):
+        assert torch.isfinite(b.read(i)).all(), i
+    order = np.argsort([m.n_elems for m, _, _, _ in spec])[:3]
+    for i in order:
+        mesh, mat, ld, alpha = spec[i]
+        uo = _oracle_run(mesh, mat, ld, alpha, b.instance(int(i))["dt"], 500)
+        err = np.abs(b.read(int(i)).double().cpu().numpy() - uo).max() / np.abs(uo).max()
+        say(f"  instance {i} ({mesh.ne}-node, model {mat.model}, {mesh.n_elems} el): rel error {err:.2e}")
         assert err <= 1e-4
     b.close()
