@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "djtled_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-NH, TI = 0, 1
+NH, TI, OT, MR = 0, 1, 2, 3
 RAMP_NONE, RAMP_LINEAR, RAMP_SMOOTH = 0, 1, 2
 OK, CONVERGED, ERR_INVERTED, ERR_NONFINITE = 0, 1, -3, -4
 
@@ -51,7 +51,7 @@ def _load():
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
         lib.ora_create.restype = P
-        lib.ora_create.argtypes = [I, I, I, dp, ip, I, dp, dp, dp, dp, D, D, ip]
+        lib.ora_create.argtypes = [I, I, I, dp, ip, I, dp, dp, dp, dp, dp, dp, dp, D, D, ip]
         lib.ora_destroy.argtypes = [P]
         lib.ora_dt_crit.restype = D
         lib.ora_dt_crit.argtypes = [P]
@@ -107,7 +107,8 @@ def jacobian_invariants(J0, tJ, a):
 class Oracle:
     """One mesh + material with Algorithm 1's pre-computation done in FP64."""
 
-    def __init__(self, X, conn, E, nu, model=NH, eta_ratio=None, fibre=None, rho=1000.0, hg_kappa=0.1):
+    def __init__(self, X, conn, E, nu, model=NH, eta_ratio=None, fibre=None, rho=1000.0, hg_kappa=0.1,
+                 eta_b_ratio=None, fibre_b=None, c01=None):
         lib = _load()
         self.X = _f64(X)
         self.conn = np.ascontiguousarray(conn, dtype=np.int32)
@@ -119,16 +120,21 @@ class Oracle:
         self._E = _f64(E)
         self._nu = _f64(nu)
         self.model = model
-        if model == TI:
-            self._eta = _f64(np.broadcast_to(np.asarray(eta_ratio, dtype=np.float64), (self.n_elems,)))
-            self._fib = _f64(np.broadcast_to(np.asarray(fibre, dtype=np.float64), (self.n_elems, 3)))
+        per = lambda v, shape: _f64(np.broadcast_to(np.asarray(v, dtype=np.float64), shape))  # noqa: E731
+        etap = fibp = etabp = fibbp = c01p = None
+        if model in (TI, OT):
+            self._eta, self._fib = per(eta_ratio, (self.n_elems,)), per(fibre, (self.n_elems, 3))
             etap, fibp = _dp(self._eta), _dp(self._fib)
-        else:
-            etap = fibp = None
+        if model == OT:
+            self._etab, self._fibb = per(eta_b_ratio, (self.n_elems,)), per(fibre_b, (self.n_elems, 3))
+            etabp, fibbp = _dp(self._etab), _dp(self._fibb)
+        if model == MR:
+            self._c01 = per(c01, (self.n_elems,))
+            c01p = _dp(self._c01)
         err = ctypes.c_int(0)
         self._ctx = lib.ora_create(self.ne, self.n_nodes, self.n_elems, _dp(self.X), _ip(self.conn), model,
-                                   _dp(self._E), _dp(self._nu), etap, fibp, float(rho), float(hg_kappa),
-                                   ctypes.byref(err))
+                                   _dp(self._E), _dp(self._nu), etap, fibp, etabp, fibbp, c01p, float(rho),
+                                   float(hg_kappa), ctypes.byref(err))
         if not self._ctx:
             raise ValueError(f"oracle rejected the mesh/material (code {err.value})")
         self.rho = rho

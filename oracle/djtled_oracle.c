@@ -33,8 +33,12 @@
  *    lumped mass-proportional damping D = alpha M (Eq. 13), textbook form.
  *  - Eq. 14: L_e = 3V / A_max (T4, the smallest altitude) or, for the
  *    one-point H8, L_e = 1 / sqrt(2 sum |dh/dX|^2) (the Flanagan-Belytschko
- *    eigenvalue bound; h / sqrt(3) for a cube); c = sqrt((kappa + 4 mu / 3 +
- *    4 eta) / rho) (eta = 0 for the isotropic model).
+ *    eigenvalue bound; h / sqrt(3) for a cube); c = sqrt((kappa + 4 mu_0 / 3 +
+ *    4 (eta_a + eta_b)) / rho), with mu_0 the initial shear modulus (mu, or
+ *    2 (C10 + C01) for Mooney-Rivlin) and the fibre moduli of the model (0
+ *    for the isotropic models).
+ *  - Mooney-Rivlin: C10 = mu / 2 from E and nu (as Sec. 5.1 does), C01 given
+ *    per element; kappa from E and nu.  Orthotropic: eta_b = ratio_b * mu.
  *  - Displacement boundary conditions overwrite the constrained components
  *    after each update with s(t) * target; s is 1, linear or the quintic
  *    smoothstep tau^3 (10 - 15 tau + 6 tau^2).
@@ -47,6 +51,8 @@
 
 #define ORA_NH 0
 #define ORA_TI 1
+#define ORA_OT 2
+#define ORA_MR 3
 
 /* ------------------------------------------------------------------ */
 /* 3x3 matrix helpers (row-major)                                       */
@@ -131,12 +137,16 @@ typedef struct {
     double *X;                /* n_nodes x 3 */
     int *conn;                /* n_elems x ne */
     double *mu, *kappa, *eta; /* per element */
-    double *fibre;            /* per element unit fibre direction (TI) */
+    double *fibre;            /* per element unit fibre direction a (TI, OT) */
+    double *eta_b, *fibre_b;  /* OT: second fibre modulus and unit direction b */
+    double *c01;              /* MR: C01 (C10 = mu / 2) */
     /* Algorithm 1, pre-computation, per element */
     double *J0, *detJ0, *V;   /* step 1 */
     double *G;                /* step 2: six 3x3 matrices, Appendix B */
-    double *m1, *m4;          /* step 3: Appendix C, Eqs. C.1, C.2 */
-    double *I1m, *I4m;        /* step 4: Eqs. 37, 45 */
+    double *m1, *m4, *m6;     /* step 3: Appendix C, Eqs. C.1, C.2, C.3 */
+    double *M2;               /* step 3: Eq. C.5 (6 x 6) */
+    double *I1m, *I4m, *I6m;  /* step 4: Eqs. 37, 45, 46 */
+    double *I2m;              /* step 4: Eqs. 40-41, six 3x3 matrices */
     double *dhdX;             /* Eq. 6 (TLED route, hourglass) : 3 x ne */
     double *gam, *khg;        /* hourglass shape vectors (4 x 8) and stiffness */
     double *mass;             /* lumped nodal mass */
@@ -146,6 +156,7 @@ typedef struct {
 void ora_destroy(ora_ctx *c) {
     if (!c) return;
     free(c->X); free(c->conn); free(c->mu); free(c->kappa); free(c->eta); free(c->fibre);
+    free(c->eta_b); free(c->fibre_b); free(c->c01); free(c->m6); free(c->M2); free(c->I6m); free(c->I2m);
     free(c->J0); free(c->detJ0); free(c->V); free(c->G); free(c->m1); free(c->m4);
     free(c->I1m); free(c->I4m); free(c->dhdX); free(c->gam); free(c->khg); free(c->mass);
     free(c);
@@ -218,18 +229,23 @@ static double char_length(const ora_ctx *c, int e) {
  *   ne      4 (T4) or 8 (H8)
  *   X       n_nodes x 3 reference coordinates
  *   conn    n_elems x ne node indices
- *   model   ORA_NH or ORA_TI
+ *   model   ORA_NH, ORA_TI, ORA_OT or ORA_MR (Table 3 rows)
  *   E, nu   per-element Young's modulus and Poisson's ratio
- *   eta_ratio, fibre   TI only: eta_a = eta_ratio * mu, unit fibre a (n_elems x 3)
+ *   eta_ratio, fibre   TI, OT: eta_a = eta_ratio * mu, fibre a (n_elems x 3)
+ *   eta_b_ratio, fibre_b   OT: eta_b = eta_b_ratio * mu, fibre b (n_elems x 3)
+ *   c01     MR: C01 per element (C10 = mu / 2)
  * On failure returns NULL and sets *err: -1 argument, -2 bad mesh (index out
  * of range or det(0J) <= 0).
  */
 ora_ctx *ora_create(int ne, int n_nodes, int n_elems, const double *X, const int *conn, int model,
                     const double *E, const double *nu, const double *eta_ratio, const double *fibre,
+                    const double *eta_b_ratio, const double *fibre_b, const double *c01,
                     double rho, double hg_kappa, int *err) {
     *err = 0;
-    if ((ne != 4 && ne != 8) || n_nodes <= 0 || n_elems <= 0 || (model != ORA_NH && model != ORA_TI) ||
-        (model == ORA_TI && (!eta_ratio || !fibre)) || rho <= 0.0) {
+    const int fib_a = (model == ORA_TI || model == ORA_OT), fib_b = (model == ORA_OT);
+    if ((ne != 4 && ne != 8) || n_nodes <= 0 || n_elems <= 0 || model < ORA_NH || model > ORA_MR ||
+        (fib_a && (!eta_ratio || !fibre)) || (fib_b && (!eta_b_ratio || !fibre_b)) ||
+        (model == ORA_MR && !c01) || rho <= 0.0) {
         *err = -1;
         return NULL;
     }
@@ -246,6 +262,13 @@ ora_ctx *ora_create(int ne, int n_nodes, int n_elems, const double *X, const int
     c->kappa = (double *)malloc(sizeof(double) * E_);
     c->eta = (double *)calloc(E_, sizeof(double));
     c->fibre = (double *)calloc(3 * E_, sizeof(double));
+    c->eta_b = (double *)calloc(E_, sizeof(double));
+    c->fibre_b = (double *)calloc(3 * E_, sizeof(double));
+    c->c01 = (double *)calloc(E_, sizeof(double));
+    c->m6 = (double *)calloc(6 * E_, sizeof(double));
+    c->M2 = (double *)calloc(36 * E_, sizeof(double));
+    c->I6m = (double *)calloc(9 * E_, sizeof(double));
+    c->I2m = (double *)calloc(54 * E_, sizeof(double));
     c->J0 = (double *)malloc(sizeof(double) * 9 * E_);
     c->detJ0 = (double *)malloc(sizeof(double) * E_);
     c->V = (double *)malloc(sizeof(double) * E_);
@@ -268,13 +291,21 @@ ora_ctx *ora_create(int ne, int n_nodes, int n_elems, const double *X, const int
     for (size_t e = 0; e < E_; e++) {
         const int *cn = conn + e * ne;
         ora_lame(E[e], nu[e], &c->mu[e], &c->kappa[e]);
-        if (model == ORA_TI) {
+        if (fib_a) {
             c->eta[e] = eta_ratio[e] * c->mu[e];
             double n = sqrt(fibre[3 * e] * fibre[3 * e] + fibre[3 * e + 1] * fibre[3 * e + 1] +
                             fibre[3 * e + 2] * fibre[3 * e + 2]);
             if (!(n > 0.0)) { *err = -1; ora_destroy(c); return NULL; }
             for (int k = 0; k < 3; k++) c->fibre[3 * e + k] = fibre[3 * e + k] / n;
         }
+        if (fib_b) {
+            c->eta_b[e] = eta_b_ratio[e] * c->mu[e];
+            double n = sqrt(fibre_b[3 * e] * fibre_b[3 * e] + fibre_b[3 * e + 1] * fibre_b[3 * e + 1] +
+                            fibre_b[3 * e + 2] * fibre_b[3 * e + 2]);
+            if (!(n > 0.0)) { *err = -1; ora_destroy(c); return NULL; }
+            for (int k = 0; k < 3; k++) c->fibre_b[3 * e + k] = fibre_b[3 * e + k] / n;
+        }
+        if (model == ORA_MR) c->c01[e] = c01[e];
         /* Step 1: 0J = H_xi X_e (Eq. 3), det(0J), 0V, A = a a^T */
         double *J0 = c->J0 + 9 * e;
         for (int i = 0; i < 3; i++)
@@ -290,31 +321,64 @@ ora_ctx *ora_create(int ne, int n_nodes, int n_elems, const double *X, const int
         double J0inv[9], J0invT[9];
         inv3(J0, J0inv);
         tr3(J0inv, J0invT);
-        double A[9];
-        const double *av = c->fibre + 3 * e;
+        double A[9], Bm[9];
+        const double *av = c->fibre + 3 * e, *bv = c->fibre_b + 3 * e;
         for (int i = 0; i < 3; i++)
-            for (int j = 0; j < 3; j++) A[3 * i + j] = av[i] * av[j];
+            for (int j = 0; j < 3; j++) {
+                A[3 * i + j] = av[i] * av[j];
+                Bm[3 * i + j] = bv[i] * bv[j];
+            }
         /* Step 2: G matrices (Appendix B) */
         double (*G)[9] = (double (*)[9])(c->G + 54 * e);
         g_matrices(J0inv, G);
-        /* Step 3: m1 = [tr G_k] (C.1), m4 = [tr(A G_k)] (C.2) */
+        /* Step 3: m1 = [tr G_k] (C.1), m4 = [tr(A G_k)] (C.2), m6 = [tr(B G_k)] (C.3),
+           W = [tr(G_k^T G_l)] (C.4) and M2 = (m1 m1^T - W) / 2 (C.5) */
         for (int k = 0; k < 6; k++) {
             c->m1[6 * e + k] = trace3(G[k]);
-            if (model == ORA_TI) {
+            if (fib_a) {
                 double AG[9];
                 mul3(A, G[k], AG);
                 c->m4[6 * e + k] = trace3(AG);
             }
+            if (fib_b) {
+                double BG[9];
+                mul3(Bm, G[k], BG);
+                c->m6[6 * e + k] = trace3(BG);
+            }
         }
-        /* Step 4: I1m = 2 0V 0J^{-T} 0J^{-1} (Eq. 37), I4m = 2 0V 0J^{-T} A 0J^{-1} (Eq. 45) */
+        if (model == ORA_MR)
+            for (int k = 0; k < 6; k++)
+                for (int l = 0; l < 6; l++) {
+                    double GT[9], P[9];
+                    tr3(G[k], GT);
+                    mul3(GT, G[l], P);
+                    c->M2[36 * e + 6 * k + l] = 0.5 * (c->m1[6 * e + k] * c->m1[6 * e + l] - trace3(P));
+                }
+        /* Step 4: I1m = 2 0V 0J^{-T} 0J^{-1} (Eq. 37), I4m = 2 0V 0J^{-T} A 0J^{-1} (Eq. 45),
+           I6m = 2 0V 0J^{-T} B 0J^{-1} (Eq. 46), I2,k = 2 0V 0J^{-T} (tr(G_k) I - G_k) 0J^{-1} (Eq. 41) */
         double t[9], t2[9];
         mul3(J0invT, J0inv, t);
         for (int i = 0; i < 9; i++) c->I1m[9 * e + i] = 2.0 * c->V[e] * t[i];
-        if (model == ORA_TI) {
+        if (fib_a) {
             mul3(J0invT, A, t);
             mul3(t, J0inv, t2);
             for (int i = 0; i < 9; i++) c->I4m[9 * e + i] = 2.0 * c->V[e] * t2[i];
         }
+        if (fib_b) {
+            mul3(J0invT, Bm, t);
+            mul3(t, J0inv, t2);
+            for (int i = 0; i < 9; i++) c->I6m[9 * e + i] = 2.0 * c->V[e] * t2[i];
+        }
+        if (model == ORA_MR)
+            for (int k = 0; k < 6; k++) {
+                double Q[9];
+                const double tg = trace3(G[k]);
+                for (int i = 0; i < 9; i++) Q[i] = -G[k][i];
+                Q[0] += tg; Q[4] += tg; Q[8] += tg;
+                mul3(J0invT, Q, t);
+                mul3(t, J0inv, t2);
+                for (int i = 0; i < 9; i++) c->I2m[54 * e + 9 * k + i] = 2.0 * c->V[e] * t2[i];
+            }
         /* Eq. 6: 0B = dh/dX = 0J^{-1} H_xi */
         double *B = c->dhdX + (size_t)3 * ne * e;
         for (int i = 0; i < 3; i++)
@@ -327,7 +391,7 @@ ora_ctx *ora_create(int ne, int n_nodes, int n_elems, const double *X, const int
         if (ne == 8) {
             double sb = 0.0;
             for (int i = 0; i < 3 * ne; i++) sb += B[i] * B[i];
-            c->khg[e] = hg_kappa * (c->kappa[e] + 4.0 * c->mu[e] / 3.0) * c->V[e] * sb / 8.0;
+            c->khg[e] = hg_kappa * (c->kappa[e] + 4.0 * (c->mu[e] + 2.0 * c->c01[e]) / 3.0) * c->V[e] * sb / 8.0;
             for (int al = 0; al < 4; al++) {
                 double gx[3] = {0, 0, 0};
                 for (int b = 0; b < 8; b++)
@@ -344,7 +408,8 @@ ora_ctx *ora_create(int ne, int n_nodes, int n_elems, const double *X, const int
     }
     /* Eq. 14: critical time step */
     for (size_t e = 0; e < E_; e++) {
-        double cw = sqrt((c->kappa[e] + 4.0 * c->mu[e] / 3.0 + 4.0 * c->eta[e]) / c->rho);
+        double cw = sqrt((c->kappa[e] + 4.0 * (c->mu[e] + 2.0 * c->c01[e]) / 3.0 + 4.0 * (c->eta[e] + c->eta_b[e])) /
+                         c->rho);
         double L = char_length(c, (int)e);
         if (L / cw < dtc) dtc = L / cw;
     }
@@ -397,7 +462,7 @@ static void hourglass_force(const ora_ctx *c, int e, const double Ue[8][3], doub
 }
 
 /*
- * DJ-TLED element force, Algorithm 1 run-time steps 1-4, Table 3 (NH and TI rows).
+ * DJ-TLED element force, Algorithm 1 run-time steps 1-4, Table 3 (NH, TI, OT and MR rows).
  * Fe[a][k] is component k of the force at local node a (column a of the 3 x n_e F).
  * Returns J (the volume ratio of Eq. 12).
  */
@@ -418,20 +483,29 @@ static double force_djtled(const ora_ctx *c, int e, const double Ue[8][3], doubl
     /* step 2: ghat (Eq. 18) */
     double g[6];
     ghat_of(tJ, g);
-    /* step 3: I1 = ghat^T m1 (Eq. 27), I4 = ghat^T m4 (Eq. 31) */
-    double I1 = 0.0, I4 = 0.0;
+    /* step 3: I1 = ghat^T m1 (Eq. 27), I2 = ghat^T M2 ghat (Eq. 28), I4 = ghat^T m4 (Eq. 31),
+       I6 = ghat^T m6 (Eq. 32) */
+    double I1 = 0.0, I2 = 0.0, I4 = 0.0, I6 = 0.0;
     for (int k = 0; k < 6; k++) {
         I1 += g[k] * c->m1[6 * e + k];
         I4 += g[k] * c->m4[6 * e + k];
+        I6 += g[k] * c->m6[6 * e + k];
+        for (int l = 0; l < 6; l++) I2 += g[k] * c->M2[36 * e + 6 * k + l] * g[l];
     }
     double Jm23 = pow(J, -2.0 / 3.0);
-    double I1b = Jm23 * I1, I4b = Jm23 * I4;
-    /* step 4: Table 3.  dPsi/dI1b = mu/2, dPsi/dI4b = eta (I4b - 1), J dPsi/dJ = kappa J (J - 1) */
-    double mu = c->mu[e], kap = c->kappa[e], eta = (c->model == ORA_TI) ? c->eta[e] : 0.0;
-    double d1 = 0.5 * mu, d4 = eta * (I4b - 1.0);
+    double I1b = Jm23 * I1, I2b = Jm23 * Jm23 * I2, I4b = Jm23 * I4, I6b = Jm23 * I6;
+    /* step 4: Table 3.  dPsi/dI1b = mu/2 (C10 for MR), dPsi/dI2b = C01 (MR), dPsi/dI4b = eta_a (I4b - 1),
+       dPsi/dI6b = eta_b (I6b - 1), J dPsi/dJ = kappa J (J - 1) */
+    double mu = c->mu[e], kap = c->kappa[e];
+    double d1 = 0.5 * mu, d2 = (c->model == ORA_MR) ? c->c01[e] : 0.0;
+    double d4 = c->eta[e] * (I4b - 1.0), d6 = c->eta_b[e] * (I6b - 1.0);
     double Imix[9];
-    for (int i = 0; i < 9; i++) Imix[i] = d1 * c->I1m[9 * e + i] + d4 * c->I4m[9 * e + i];
-    double vol = -2.0 / 3.0 * (d1 * I1b + d4 * I4b) + kap * J * (J - 1.0);
+    for (int i = 0; i < 9; i++) {
+        double gI2 = 0.0;  /* ghat^T . I2m (Eq. 42) */
+        for (int k = 0; k < 6; k++) gI2 += g[k] * c->I2m[54 * e + 9 * k + i];
+        Imix[i] = d1 * c->I1m[9 * e + i] + Jm23 * d2 * gI2 + d4 * c->I4m[9 * e + i] + d6 * c->I6m[9 * e + i];
+    }
+    double vol = -2.0 / 3.0 * (d1 * I1b + 2.0 * d2 * I2b + d4 * I4b + d6 * I6b) + kap * J * (J - 1.0);
     double M[9], t[9];
     mul3(tJT, Imix, t);
     for (int i = 0; i < 9; i++) M[i] = Jm23 * t[i] + vol * c->V[e] * tJinv[i];
@@ -448,10 +522,11 @@ static double force_djtled(const ora_ctx *c, int e, const double Ue[8][3], doubl
 
 /*
  * Classical TLED element force (Eq. 4): F = X S 0B 0V with X = I + u 0B^T
- * (Table 8, TLED column), C = X^T X, and S of Eq. 54 plus the fibre term
- * obtained from Eq. 7 for Psi = mu/2 (I1b - 3) + eta/2 (I4b - 1)^2 + kappa/2 (J - 1)^2:
- *   S = J^{-2/3} (mu I + 2 eta (I4b - 1) A)
- *       + (-(mu/3) I1b - (2/3) eta (I4b - 1) I4b + kappa J (J - 1)) C^{-1}.
+ * (Table 8, TLED column), C = X^T X, and S = 2 dPsi/dC of Eq. 7 for the
+ * Table 3 energies, with the invariants taken from C directly:
+ *   S = J^{-2/3} (2 d1 I + 2 d4 A + 2 d6 B) + 2 d2 J^{-4/3} (I1 I - C)
+ *       + (-(2/3) (d1 I1b + 2 d2 I2b + d4 I4b + d6 I6b) + kappa J (J - 1)) C^{-1},
+ * d1 = mu/2 (C10), d2 = C01, d4 = eta_a (I4b - 1), d6 = eta_b (I6b - 1).
  */
 static double force_tled(const ora_ctx *c, int e, const double Ue[8][3], double Fe[8][3]) {
     const int ne = c->ne;
@@ -468,19 +543,28 @@ static double force_tled(const ora_ctx *c, int e, const double Ue[8][3], double 
     tr3(X, XT);
     mul3(XT, X, C);
     inv3(C, Cinv);
-    const double *a = c->fibre + 3 * e;
-    double I1 = trace3(C), I4 = 0.0;
+    const double *a = c->fibre + 3 * e, *bb = c->fibre_b + 3 * e;
+    double C2[9];
+    mul3(C, C, C2);
+    double I1 = trace3(C), I2 = 0.5 * (I1 * I1 - trace3(C2)), I4 = 0.0, I6 = 0.0;
     for (int i = 0; i < 3; i++)
-        for (int j = 0; j < 3; j++) I4 += a[i] * C[3 * i + j] * a[j];
+        for (int j = 0; j < 3; j++) {
+            I4 += a[i] * C[3 * i + j] * a[j];
+            I6 += bb[i] * C[3 * i + j] * bb[j];
+        }
     double Jm23 = pow(J, -2.0 / 3.0);
-    double I1b = Jm23 * I1, I4b = Jm23 * I4;
-    double mu = c->mu[e], kap = c->kappa[e], eta = (c->model == ORA_TI) ? c->eta[e] : 0.0;
-    double p = -(mu / 3.0) * I1b - 2.0 / 3.0 * eta * (I4b - 1.0) * I4b + kap * J * (J - 1.0);
+    double I1b = Jm23 * I1, I2b = Jm23 * Jm23 * I2, I4b = Jm23 * I4, I6b = Jm23 * I6;
+    double mu = c->mu[e], kap = c->kappa[e];
+    double d1 = 0.5 * mu, d2 = (c->model == ORA_MR) ? c->c01[e] : 0.0;
+    double d4 = c->eta[e] * (I4b - 1.0), d6 = c->eta_b[e] * (I6b - 1.0);
+    double p = -2.0 / 3.0 * (d1 * I1b + 2.0 * d2 * I2b + d4 * I4b + d6 * I6b) + kap * J * (J - 1.0);
     double S[9];
     for (int i = 0; i < 3; i++)
-        for (int j = 0; j < 3; j++)
-            S[3 * i + j] = Jm23 * (mu * (i == j ? 1.0 : 0.0) + 2.0 * eta * (I4b - 1.0) * a[i] * a[j]) +
-                           p * Cinv[3 * i + j];
+        for (int j = 0; j < 3; j++) {
+            const double dij = (i == j ? 1.0 : 0.0);
+            S[3 * i + j] = Jm23 * (2.0 * d1 * dij + 2.0 * d4 * a[i] * a[j] + 2.0 * d6 * bb[i] * bb[j]) +
+                           2.0 * d2 * Jm23 * Jm23 * (I1 * dij - C[3 * i + j]) + p * Cinv[3 * i + j];
+        }
     double XS[9];
     mul3(X, S, XS);
     for (int b = 0; b < ne; b++)
@@ -552,13 +636,21 @@ double ora_energy(const ora_ctx *c, const double *u) {
         double XT[9], C[9];
         tr3(X, XT);
         mul3(XT, X, C);
-        const double *av = c->fibre + 3 * e;
-        double I1 = trace3(C), I4 = 0.0;
+        const double *av = c->fibre + 3 * e, *bv = c->fibre_b + 3 * e;
+        double C2[9];
+        mul3(C, C, C2);
+        double I1 = trace3(C), I2 = 0.5 * (I1 * I1 - trace3(C2)), I4 = 0.0, I6 = 0.0;
         for (int i = 0; i < 3; i++)
-            for (int j = 0; j < 3; j++) I4 += av[i] * C[3 * i + j] * av[j];
+            for (int j = 0; j < 3; j++) {
+                I4 += av[i] * C[3 * i + j] * av[j];
+                I6 += bv[i] * C[3 * i + j] * bv[j];
+            }
         double Jm23 = pow(J, -2.0 / 3.0);
+        /* Table 3 energies: mu/2 (I1b - 3) is C10 (I1b - 3) with C10 = mu / 2 */
         double psi = 0.5 * c->mu[e] * (Jm23 * I1 - 3.0) + 0.5 * c->kappa[e] * (J - 1.0) * (J - 1.0);
-        if (c->model == ORA_TI) psi += 0.5 * c->eta[e] * (Jm23 * I4 - 1.0) * (Jm23 * I4 - 1.0);
+        psi += 0.5 * c->eta[e] * (Jm23 * I4 - 1.0) * (Jm23 * I4 - 1.0);
+        psi += 0.5 * c->eta_b[e] * (Jm23 * I6 - 1.0) * (Jm23 * I6 - 1.0);
+        if (c->model == ORA_MR) psi += c->c01[e] * (Jm23 * Jm23 * I2 - 3.0);
         Etot += c->V[e] * psi;
         if (ne == 8) {
             const double *g = c->gam + 32 * e;

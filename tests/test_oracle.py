@@ -48,18 +48,25 @@ def _h8_dmap(P):
     return np.stack(cols, axis=1)  # columns: d x / d xi_i
 
 
-def _psi(F, mu, kappa, eta=0.0, a=None):
-    """Strain energy densities of Table 3 (NH; TI with fibre a)."""
+def _psi(F, mu, kappa, eta=0.0, a=None, eta_b=0.0, b=None, c01=0.0):
+    """Strain energy densities of Table 3 (NH; TI with fibre a; OT with fibres
+    a and b; MR with C10 = mu / 2 and C01)."""
     J = np.linalg.det(F)
     C = F.T @ F
     Jm23 = J ** (-2.0 / 3.0)
     psi = 0.5 * mu * (Jm23 * np.trace(C) - 3.0) + 0.5 * kappa * (J - 1.0) ** 2
     if eta:
         psi += 0.5 * eta * (Jm23 * (a @ C @ a) - 1.0) ** 2
+    if eta_b:
+        psi += 0.5 * eta_b * (Jm23 * (b @ C @ b) - 1.0) ** 2
+    if c01:
+        I2 = 0.5 * (np.trace(C) ** 2 - np.trace(C @ C))
+        psi += c01 * (Jm23 * Jm23 * I2 - 3.0)
     return psi
 
 
-def _independent_energy(mesh_X, conn, u, mu, kappa, eta=None, fibre=None, hg_kappa=0.1):
+def _independent_energy(mesh_X, conn, u, mu, kappa, eta=None, fibre=None, hg_kappa=0.1, eta_b=None, fibre_b=None,
+                        c01=None):
     Etot = 0.0
     Gam = np.stack([_H8C[:, 0] * _H8C[:, 1], _H8C[:, 1] * _H8C[:, 2],
                     _H8C[:, 2] * _H8C[:, 0], _H8C[:, 0] * _H8C[:, 1] * _H8C[:, 2]])
@@ -76,7 +83,10 @@ def _independent_energy(mesh_X, conn, u, mu, kappa, eta=None, fibre=None, hg_kap
             V = 8.0 * np.linalg.det(dX)
         et = eta[e] if eta is not None else 0.0
         a = fibre[e] if fibre is not None else None
-        Etot += V * _psi(F, mu[e], kappa[e], et, a)
+        eb = eta_b[e] if eta_b is not None else 0.0
+        b = fibre_b[e] if fibre_b is not None else None
+        c1 = c01[e] if c01 is not None else 0.0
+        Etot += V * _psi(F, mu[e], kappa[e], et, a, eb, b, c1)
         if conn.shape[1] == 8:
             # Flanagan-Belytschko hourglass energy (reading of the paper's cited control)
             dX = _h8_dmap(P)
@@ -84,7 +94,8 @@ def _independent_energy(mesh_X, conn, u, mu, kappa, eta=None, fibre=None, hg_kap
             B = dNdxi @ np.linalg.inv(dX)            # (8, 3): dN_a / dX_j
             Pr = P - P[0]
             gam = Gam - (Gam @ Pr) @ B.T             # (4, 8)
-            k = hg_kappa * (kappa[e] + 4.0 * mu[e] / 3.0) * V * np.sum(B * B) / 8.0
+            mu0 = mu[e] + (2.0 * c01[e] if c01 is not None else 0.0)   # initial shear modulus
+            k = hg_kappa * (kappa[e] + 4.0 * mu0 / 3.0) * V * np.sum(B * B) / 8.0
             q = gam @ u[conn[e]]                     # (4, 3)
             Etot += 0.5 * k * np.sum(q * q)
     return Etot
@@ -99,12 +110,30 @@ def _small_case(elem, model, n=2, seed=3, jitter=0.08):
     mesh = W.cube_mesh(n, 0.01, elem, jitter=jitter, seed=seed)
     E = rng.uniform(2000, 6000, mesh.n_elems)
     nu = np.full(mesh.n_elems, 0.45)
-    kw = {}
-    if model == W.TI:
-        v = rng.normal(size=(mesh.n_elems, 3))
-        kw = dict(eta_ratio=rng.uniform(2, 10, mesh.n_elems), fibre=v / np.linalg.norm(v, axis=1, keepdims=True))
+    kw = _model_kw(model, mesh.n_elems, E, nu, rng)
     o = oracle.Oracle(mesh.X, mesh.conn, E, nu, model=model, rho=1000.0, **kw)
     return mesh, o, E, nu, kw, rng
+
+
+def _model_kw(model, n, E, nu, rng):
+    """Per-element parameters of the fibre and Mooney-Rivlin models."""
+    def unit(v):
+        return v / np.linalg.norm(v, axis=1, keepdims=True)
+    kw = {}
+    if model in (W.TI, W.OT):
+        kw.update(eta_ratio=rng.uniform(2, 10, n), fibre=unit(rng.normal(size=(n, 3))))
+    if model == W.OT:
+        kw.update(eta_b_ratio=rng.uniform(2, 10, n), fibre_b=unit(rng.normal(size=(n, 3))))
+    if model == W.MR:
+        kw.update(c01=rng.uniform(0.2, 1.0, n) * _lame(E, nu)[0] / 2)
+    return kw
+
+
+def _energy_kw(kw, mu):
+    """Arguments of _independent_energy from the oracle's material keywords."""
+    return dict(eta=kw["eta_ratio"] * mu if "eta_ratio" in kw else None, fibre=kw.get("fibre"),
+                eta_b=kw["eta_b_ratio"] * mu if "eta_b_ratio" in kw else None, fibre_b=kw.get("fibre_b"),
+                c01=kw.get("c01"))
 
 
 # ---------------------------------------------------------------------------
@@ -133,7 +162,7 @@ def test_table1_invariants_match_conventional():
 # Check 1: DJ-TLED force == classical TLED force (Eq. 55 vs Eq. 56, App. A)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("elem", [W.T4, W.H8])
-@pytest.mark.parametrize("model", [W.NH, W.TI])
+@pytest.mark.parametrize("model", [W.NH, W.TI, W.OT, W.MR])
 def test_djtled_equals_tled(elem, model):
     mesh, o, *_ , rng = _small_case(elem, model, n=3)
     for scale in (1e-6, 3e-4, 6e-4):
@@ -147,12 +176,11 @@ def test_djtled_equals_tled(elem, model):
 # Check 4: nodal forces are the gradient of an independently computed energy
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("elem", [W.T4, W.H8])
-@pytest.mark.parametrize("model", [W.NH, W.TI])
+@pytest.mark.parametrize("model", [W.NH, W.TI, W.OT, W.MR])
 def test_forces_are_energy_gradient(elem, model):
     mesh, o, E, nu, kw, rng = _small_case(elem, model, n=1 if elem == W.T4 else 2, seed=5)
     mu, ka = _lame(E, nu)
-    eta = kw["eta_ratio"] * mu if kw else None
-    fib = kw.get("fibre")
+    ekw = _energy_kw(kw, mu)
     u = rng.normal(size=(mesh.n_nodes, 3)) * 1e-3
     f = o.forces(u)
     h = 1e-8
@@ -161,20 +189,20 @@ def test_forces_are_energy_gradient(elem, model):
         up, um = u.copy(), u.copy()
         up[i, k] += h
         um[i, k] -= h
-        g_ind = (_independent_energy(mesh.X, mesh.conn, up, mu, ka, eta, fib)
-                 - _independent_energy(mesh.X, mesh.conn, um, mu, ka, eta, fib)) / (2 * h)
+        g_ind = (_independent_energy(mesh.X, mesh.conn, up, mu, ka, **ekw)
+                 - _independent_energy(mesh.X, mesh.conn, um, mu, ka, **ekw)) / (2 * h)
         g_ora = (o.energy(up) - o.energy(um)) / (2 * h)
         assert abs(g_ind - f[i, k]) <= 1e-6 * scale, (i, k, g_ind, f[i, k])
         assert abs(g_ora - f[i, k]) <= 1e-6 * scale
     # the two energies themselves agree
-    assert abs(o.energy(u) - _independent_energy(mesh.X, mesh.conn, u, mu, ka, eta, fib)) <= 1e-12 * max(1e-30, abs(o.energy(u))) + 1e-18
+    assert abs(o.energy(u) - _independent_energy(mesh.X, mesh.conn, u, mu, ka, **ekw)) <= 1e-12 * max(1e-30, abs(o.energy(u))) + 1e-18
 
 
 # ---------------------------------------------------------------------------
 # Check 2: zero internal force under rigid rotation + translation
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("elem", [W.T4, W.H8])
-@pytest.mark.parametrize("model", [W.NH, W.TI])
+@pytest.mark.parametrize("model", [W.NH, W.TI, W.OT, W.MR])
 def test_rigid_motion_gives_zero_force(elem, model):
     mesh, o, E, nu, kw, rng = _small_case(elem, model, n=3, seed=11)
     Rm = _rand_rotation(rng)
@@ -190,6 +218,43 @@ def test_rigid_motion_gives_zero_force(elem, model):
     u2 = mesh.X @ (Rm @ S).T - mesh.X
     f1, f2 = o.forces(u1), o.forces(u2)
     np.testing.assert_allclose(f2, f1 @ Rm.T, atol=1e-10 * np.abs(f1).max())
+
+
+@pytest.mark.parametrize("elem", [W.T4, W.H8])
+def test_special_cases_reduce_to_pinned_models(elem):
+    """MR with C01 = 0 is NH (Sec. 5.1); OT with eta_b = 0 is TI; OT whose
+    second fibre repeats the first is TI with the fibre modulus eta_a + eta_b."""
+    mesh, _, E, nu, _, rng = _small_case(elem, W.NH, n=2, seed=9)
+    u = rng.normal(size=(mesh.n_nodes, 3)) * 4e-4
+    nh = oracle.Oracle(mesh.X, mesh.conn, E, nu, model=W.NH)
+    mr0 = oracle.Oracle(mesh.X, mesh.conn, E, nu, model=W.MR, c01=0.0)
+    np.testing.assert_array_equal(mr0.forces(u), nh.forces(u))
+    kw = _model_kw(W.TI, mesh.n_elems, E, nu, rng)
+    ti = oracle.Oracle(mesh.X, mesh.conn, E, nu, model=W.TI, **kw)
+    ot0 = oracle.Oracle(mesh.X, mesh.conn, E, nu, model=W.OT, eta_b_ratio=0.0, fibre_b=[0.0, 0.0, 1.0], **kw)
+    np.testing.assert_allclose(ot0.forces(u), ti.forces(u), rtol=0, atol=1e-14 * np.abs(ti.forces(u)).max())
+    # a second fibre along the first doubles the fibre energy
+    ot2 = oracle.Oracle(mesh.X, mesh.conn, E, nu, model=W.OT, eta_b_ratio=kw["eta_ratio"], fibre_b=kw["fibre"],
+                        **kw)
+    ti2 = oracle.Oracle(mesh.X, mesh.conn, E, nu, model=W.TI, eta_ratio=2 * kw["eta_ratio"], fibre=kw["fibre"])
+    np.testing.assert_allclose(ot2.forces(u), ti2.forces(u), rtol=0, atol=1e-12 * np.abs(ti2.forces(u)).max())
+
+
+def test_mooney_rivlin_paper_constants():
+    """Sec. 5.1: C10 = mu / 2 with mu = 6567 Pa and C01 = 3000 Pa give an
+    initial shear modulus 2 (C10 + C01) = 12567 Pa; a small simple shear of
+    an MR cube therefore carries the shear stress 12567 gamma."""
+    mesh = W.cube_mesh(2, 0.01, W.H8, jitter=0.0)
+    nu = 0.49
+    E = 2 * 6567.0 * (1 + nu)
+    o = oracle.Oracle(mesh.X, mesh.conn, E, nu, model=W.MR, c01=3000.0, hg_kappa=0.0)
+    g = 1e-6
+    u = np.zeros_like(mesh.X)
+    u[:, 0] = g * mesh.X[:, 2]                      # simple shear in the x-z plane
+    f = o.forces(u)
+    top = mesh.top
+    tau = f[top, 0].sum() / (0.02 * 0.02)         # shear traction on the top face
+    np.testing.assert_allclose(tau, 12567.0 * g, rtol=1e-5)
 
 
 def test_hourglass_vectors_annihilate_affine_fields():
