@@ -47,7 +47,8 @@ extern "C" {
 #define DJ_ERR_BARRIER (-8)      /* the persistent kernel's grid barrier timed out */
 
 enum { DJ_T4 = 4, DJ_H8 = 8 };                 /* linear tetrahedron, 8-node hexahedron */
-enum { DJ_NH = 0, DJ_TI = 1 };                 /* neo-Hookean, transversely isotropic NH */
+enum { DJ_NH = 0, DJ_TI = 1, DJ_OT = 2, DJ_MR = 3 };  /* Table 3 rows: neo-Hookean, transversely isotropic NH,
+                                                       orthotropic NH, Mooney-Rivlin */
 enum { DJ_FP32 = 0, DJ_FP64 = 1 };
 enum { DJ_RAMP_NONE = 0, DJ_RAMP_LINEAR = 1, DJ_RAMP_SMOOTH = 2 };
 enum { DJ_MODE_FIXED = 0, DJ_MODE_RELAX = 1 };
@@ -64,17 +65,24 @@ typedef struct {
 } djtled_mesh;
 
 /* Material (host memory).  mu = E / (2 (1 + nu)), kappa = E / (3 (1 - 2 nu)).
-   Per-element arrays may be NULL, in which case the *_uniform value is used. */
+   Per-element arrays may be NULL, in which case the *_uniform value is used.
+   DJ_MR takes C10 = mu / 2 (as Sec. 5.1 does) and C01 below; its initial
+   shear modulus is 2 (C10 + C01). */
 typedef struct {
-    int32_t model;          /* DJ_NH or DJ_TI (Table 3) */
+    int32_t model;          /* DJ_NH, DJ_TI, DJ_OT or DJ_MR (Table 3) */
     const double *E;        /* n_elems Young's modulus [Pa] or NULL */
     const double *nu;       /* n_elems Poisson's ratio or NULL */
     double E_uniform, nu_uniform;
     double rho;             /* mass density [kg / m^3] */
-    const double *eta_ratio;   /* DJ_TI: eta_a / mu per element, or NULL */
+    const double *eta_ratio;   /* DJ_TI, DJ_OT: eta_a / mu per element, or NULL */
     double eta_ratio_uniform;
-    const double *fibre;    /* DJ_TI: n_elems x 3 fibre directions a (normalised internally) */
+    const double *fibre;    /* DJ_TI, DJ_OT: n_elems x 3 fibre directions a (normalised internally) */
     double hg_kappa;        /* DJ_H8: hourglass coefficient (Flanagan-Belytschko form); <0 -> 0.1 */
+    const double *fibre_b;  /* DJ_OT: n_elems x 3 second fibre directions b */
+    const double *eta_b_ratio;  /* DJ_OT: eta_b / mu per element, or NULL */
+    double eta_b_ratio_uniform;
+    const double *c01;      /* DJ_MR: C01 [Pa] per element, or NULL */
+    double c01_uniform;
 } djtled_material;
 
 /* Solver parameters. */
@@ -202,7 +210,8 @@ int djtled_export_constants(djtled_ctx *ctx, double *V, double *dhdX, double *ma
  * grid barrier per step for the whole batch), replayed from a captured
  * hipGraph.  The batch owns the state of every instance (initially u = 0 at
  * step 0).  External forces R are not supported in batches (loads[i].R must be
- * NULL); all instances of a kind share rho and hg_kappa.  In a batch, a
+ * NULL); batches take the DJ_NH and DJ_TI models; all instances of a kind
+ * share rho and hg_kappa.  In a batch, a
  * negative loads[i].t_ramp means a ramp of |t_ramp| steps of the instance's
  * own dt.
  * ------------------------------------------------------------------------ */

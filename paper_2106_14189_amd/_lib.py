@@ -22,7 +22,7 @@ DJ_OK, DJ_CONVERGED = 0, 1
 DJ_ERR_ARG, DJ_ERR_BAD_MESH, DJ_ERR_INVERTED, DJ_ERR_NONFINITE = -1, -2, -3, -4
 DJ_ERR_UNSUPPORTED, DJ_ERR_UNSTABLE_DT, DJ_ERR_HIP, DJ_ERR_BARRIER = -5, -6, -7, -8
 DJ_T4, DJ_H8 = 4, 8
-DJ_NH, DJ_TI = 0, 1
+DJ_NH, DJ_TI, DJ_OT, DJ_MR = 0, 1, 2, 3
 DJ_FP32, DJ_FP64 = 0, 1
 DJ_RAMP_NONE, DJ_RAMP_LINEAR, DJ_RAMP_SMOOTH = 0, 1, 2
 DJ_MODE_FIXED, DJ_MODE_RELAX = 0, 1
@@ -44,7 +44,9 @@ class djtled_mesh(ctypes.Structure):
 class djtled_material(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int32), ("E", _dp), ("nu", _dp), ("E_uniform", ctypes.c_double),
                 ("nu_uniform", ctypes.c_double), ("rho", ctypes.c_double), ("eta_ratio", _dp),
-                ("eta_ratio_uniform", ctypes.c_double), ("fibre", _dp), ("hg_kappa", ctypes.c_double)]
+                ("eta_ratio_uniform", ctypes.c_double), ("fibre", _dp), ("hg_kappa", ctypes.c_double),
+                ("fibre_b", _dp), ("eta_b_ratio", _dp), ("eta_b_ratio_uniform", ctypes.c_double), ("c01", _dp),
+                ("c01_uniform", ctypes.c_double)]
 
 
 class djtled_params(ctypes.Structure):

@@ -387,7 +387,7 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     DJ_HIP(hipEventCreate(&c.ev1));
 
     // ---- per-element inputs in internal order; pre-computation on the GPU (FP64)
-    std::vector<double> Xi(size_t(3) * N), Ei(E), nui(E), etai, fibi;
+    std::vector<double> Xi(size_t(3) * N), Ei(E), nui(E), etai, fibi, etabi, fibbi, c01i;
     for (int n = 0; n < N; n++)
         for (int k = 0; k < 3; k++) Xi[3 * size_t(n) + k] = mesh->X[3 * size_t(c.node_perm[n]) + k];
     for (int e = 0; e < E; e++) {
@@ -397,25 +397,56 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
         if (!(Ei[e] > 0) || !(nui[e] > -1.0 && nui[e] < 0.5))
             return fail(DJ_ERR_ARG, "element " + std::to_string(o) + ": need E > 0 and -1 < nu < 0.5");
     }
-    if (c.model == DJ_TI) {
-        etai.resize(E);
-        fibi.resize(size_t(3) * E);
-        for (int e = 0; e < E; e++) {
-            const int o = c.elem_perm[e];
-            etai[e] = mat->eta_ratio ? mat->eta_ratio[o] : mat->eta_ratio_uniform;
-            for (int k = 0; k < 3; k++) fibi[3 * size_t(e) + k] = mat->fibre[3 * size_t(o) + k];
-        }
+    // per-element copies in internal order, with the uniform fallbacks
+    auto gather = [&](const double *arr, double uni, std::vector<double> &out) {
+        out.resize(E);
+        for (int e = 0; e < E; e++) out[e] = arr ? arr[c.elem_perm[e]] : uni;
+    };
+    auto gather3 = [&](const double *arr, std::vector<double> &out) {
+        out.resize(size_t(3) * E);
+        for (int e = 0; e < E; e++)
+            for (int k = 0; k < 3; k++) out[3 * size_t(e) + k] = arr[3 * size_t(c.elem_perm[e]) + k];
+    };
+    const bool fib_a = c.model == DJ_TI || c.model == DJ_OT, fib_b = c.model == DJ_OT;
+    if (fib_a) {
+        gather(mat->eta_ratio, mat->eta_ratio_uniform, etai);
+        gather3(mat->fibre, fibi);
+    }
+    if (fib_b) {
+        gather(mat->eta_b_ratio, mat->eta_b_ratio_uniform, etabi);
+        gather3(mat->fibre_b, fibbi);
+    }
+    if (c.model == DJ_MR) gather(mat->c01, mat->c01_uniform, c01i);
+    for (int e = 0; e < E; e++) {
+        const bool okm = (!fib_a || etai[e] >= 0) && (!fib_b || etabi[e] >= 0) && (c.model != DJ_MR || c01i[e] >= 0);
+        if (!okm) return fail(DJ_ERR_ARG, "element " + std::to_string(c.elem_perm[e]) + ": negative fibre or C01 modulus");
     }
     TempBufs tb;
-    double *dX, *dE, *dnu, *deta = nullptr, *dfib = nullptr, *ddt;
+    double *dX, *dE, *dnu, *ddt;
     int32_t *dconn, *dbad, *dneoff, *dnelist;
+    MatDev md{};
     DJ_HIP(tb.up(&dX, Xi));
     DJ_HIP(tb.up(&dconn, conn));
     DJ_HIP(tb.up(&dE, Ei));
     DJ_HIP(tb.up(&dnu, nui));
-    if (c.model == DJ_TI) {
-        DJ_HIP(tb.up(&deta, etai));
-        DJ_HIP(tb.up(&dfib, fibi));
+    md.E = dE;
+    md.nu = dnu;
+    double *tmp = nullptr;
+    if (fib_a) {
+        DJ_HIP(tb.up(&tmp, etai));
+        md.eta = tmp;
+        DJ_HIP(tb.up(&tmp, fibi));
+        md.fib = tmp;
+    }
+    if (fib_b) {
+        DJ_HIP(tb.up(&tmp, etabi));
+        md.etab = tmp;
+        DJ_HIP(tb.up(&tmp, fibbi));
+        md.fibb = tmp;
+    }
+    if (c.model == DJ_MR) {
+        DJ_HIP(tb.up(&tmp, c01i));
+        md.c01 = tmp;
     }
     const double inf = std::numeric_limits<double>::infinity();
     int32_t *dei = nullptr;
@@ -428,7 +459,7 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     DJ_HIP(tb.up(&dbad, std::vector<int32_t>{0}));
     DJ_HIP(tb.up(&dneoff, ne_off));
     DJ_HIP(tb.up(&dnelist, ne_list));
-    DJ_HIP(launch_precompute(c, dX, dconn, dE, dnu, deta, dfib, dei, ddt, dbad, nullptr));
+    DJ_HIP(launch_precompute(c, dX, dconn, md, dei, ddt, dbad, nullptr));
     int32_t bad = 0;
     std::vector<double> dtc(NI);
     DJ_HIP(hipMemcpy(&bad, dbad, sizeof(int32_t), hipMemcpyDeviceToHost));
@@ -565,10 +596,14 @@ int djtled_precompute(const djtled_mesh *mesh, const djtled_material *mat, const
     if (mesh->n_nodes <= 0 || mesh->n_elems <= 0 || !mesh->X || !mesh->conn)
         return fail(DJ_ERR_ARG, "empty mesh or null arrays");
     if (mesh->elem_type != DJ_T4 && mesh->elem_type != DJ_H8) return fail(DJ_ERR_UNSUPPORTED, "elem_type must be 4 or 8");
-    if (mat->model != DJ_NH && mat->model != DJ_TI) return fail(DJ_ERR_UNSUPPORTED, "model must be DJ_NH or DJ_TI");
+    if (mat->model < DJ_NH || mat->model > DJ_MR) return fail(DJ_ERR_UNSUPPORTED, "model must be DJ_NH, DJ_TI, DJ_OT or DJ_MR");
     if (prm->precision != DJ_FP32 && prm->precision != DJ_FP64) return fail(DJ_ERR_UNSUPPORTED, "precision");
     if (!(mat->rho > 0)) return fail(DJ_ERR_ARG, "rho must be > 0");
-    if (mat->model == DJ_TI && !mat->fibre) return fail(DJ_ERR_ARG, "DJ_TI needs fibre directions");
+    if ((mat->model == DJ_TI || mat->model == DJ_OT) && !mat->fibre)
+        return fail(DJ_ERR_ARG, "DJ_TI and DJ_OT need fibre directions");
+    if (mat->model == DJ_OT && !mat->fibre_b) return fail(DJ_ERR_ARG, "DJ_OT needs second fibre directions");
+    if ((mat->model == DJ_OT || mat->model == DJ_MR) && prm->variant >= 4)
+        return fail(DJ_ERR_UNSUPPORTED, "variants 4 and 5 are built for DJ_NH and DJ_TI only");
     if (!(prm->alpha >= 0) || !(prm->dt >= 0)) return fail(DJ_ERR_ARG, "alpha and dt must be >= 0");
     if (prm->variant < 0 || prm->variant >= int(variants(mesh->elem_type, prm->precision).size()))
         return fail(DJ_ERR_ARG, "unknown kernel variant");

@@ -172,30 +172,61 @@ __device__ __forceinline__ T element_force(const T *__restrict__ cst, const T (&
     const T Jm23 = dj_rcp(c * c);                             // J^-2/3
     const T muV = cst[P::MUV], kaV = cst[P::KAV];
     T c0 = -(muV * T(1.0 / 3.0)) * Jm23 * I1m3 + kaV * J * Jm1;  // (mu J^-2/3 + p) 0V
+    T ciso = muV * Jm23;                                          // the O(1) identity part of c0 - p 0V
     T Q[3][3];
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int k = 0; k < 3; k++) Q[i][k] = muV * Jm23 * D[k][i];
-    if constexpr (MODEL == DJ_TI) {
-        const T av[3] = {cst[P::FIB], cst[P::FIB + 1], cst[P::FIB + 2]};
-        const T etaV = cst[P::ETAV];
-        T Dta[3];
+    // fibre terms (TI: a; OT: a and b): 2 J^-2/3 psi 0V (f + D^T f) f^T, psi = eta (Ibar - 1)
+    auto fibre_term = [&](const T *fv, T etaV) {
+        const T f[3] = {fv[0], fv[1], fv[2]};
+        T Dtf[3];
 #pragma unroll
-        for (int k = 0; k < 3; k++) Dta[k] = D[0][k] * av[0] + D[1][k] * av[1] + D[2][k] * av[2];
-        const T aDa = av[0] * Dta[0] + av[1] * Dta[1] + av[2] * Dta[2];
-        const T I4m1 = T(2) * aDa + Dta[0] * Dta[0] + Dta[1] * Dta[1] + Dta[2] * Dta[2];  // I4 - 1 (Eq. 31)
-        const T Jm23m1 = -Jm1 * (c + T(1)) * dj_rcp(c * c * (c * c + c + T(1)));      // J^-2/3 - 1
-        const T I4bm1 = Jm23 * I4m1 + Jm23m1;                                            // I4bar - 1
-        const T psi4V = etaV * I4bm1;                                                    // eta (I4bar - 1) 0V
-        c0 -= T(2.0 / 3.0) * psi4V * (T(1) + I4bm1);
-        const T w = T(2) * Jm23 * psi4V;
+        for (int k = 0; k < 3; k++) Dtf[k] = D[0][k] * f[0] + D[1][k] * f[1] + D[2][k] * f[2];
+        const T fDf = f[0] * Dtf[0] + f[1] * Dtf[1] + f[2] * Dtf[2];
+        const T Im1 = T(2) * fDf + Dtf[0] * Dtf[0] + Dtf[1] * Dtf[1] + Dtf[2] * Dtf[2];  // I4 - 1 (Eq. 31, 32)
+        const T Jm23m1 = -Jm1 * (c + T(1)) * dj_rcp(c * c * (c * c + c + T(1)));     // J^-2/3 - 1
+        const T Ibm1 = Jm23 * Im1 + Jm23m1;                                             // Ibar - 1
+        const T psiV = etaV * Ibm1;
+        c0 -= T(2.0 / 3.0) * psiV * (T(1) + Ibm1);
+        const T w = T(2) * Jm23 * psiV;
 #pragma unroll
         for (int i = 0; i < 3; i++)
 #pragma unroll
-            for (int k = 0; k < 3; k++) Q[i][k] += w * (av[i] + Dta[i]) * av[k];
+            for (int k = 0; k < 3; k++) Q[i][k] += w * (f[i] + Dtf[i]) * f[k];
+    };
+    if constexpr (MODEL == DJ_TI || MODEL == DJ_OT) fibre_term(cst + P::FIB, cst[P::ETAV]);
+    if constexpr (MODEL == DJ_OT) fibre_term(cst + P::FIBB, cst[P::ETABV]);
+    if constexpr (MODEL == DJ_MR) {
+        // C01 term: 2 C01 0V J^-4/3 (I + D^T)(I1 I - C) with C = I + G, G = D + D^T + D D^T;
+        // its identity part 4 C01 0V J^-4/3 joins c0, the rest is O(strain)
+        const T c01V = cst[P::C01V];
+        const T Jm43 = Jm23 * Jm23;
+        T G[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++)
+                G[i][j] = D[i][j] + D[j][i] + D[i][0] * D[j][0] + D[i][1] * D[j][1] + D[i][2] * D[j][2];
+        T trG2 = 0;
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) trG2 += G[i][j] * G[i][j];
+        const T I2m3 = T(2) * I1m3 + T(0.5) * (I1m3 * I1m3 - trG2);  // I2 - 3 (Eq. 28)
+        const T w = T(2) * c01V * Jm43;
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const T DtG = D[0][i] * G[0][k] + D[1][i] * G[1][k] + D[2][i] * G[2][k];
+                Q[i][k] += w * (T(2) * D[k][i] + I1m3 * ((i == k ? T(1) : T(0)) + D[k][i]) - G[i][k] - DtG);
+            }
+        c0 -= T(4.0 / 3.0) * c01V * Jm43 * I2m3;  // p_MR 0V + 4 C01 0V J^-4/3
+        ciso += T(4) * c01V * Jm43;
     }
-    const T pJ = (c0 - muV * Jm23) * dj_rcp(J);  // p 0V / J
+    const T pJ = (c0 - ciso) * dj_rcp(J);  // p 0V / J
     // adj(I + D)
     const T A00 = T(1) + D[0][0], A11 = T(1) + D[1][1], A22 = T(1) + D[2][2];
     T adj[3][3];

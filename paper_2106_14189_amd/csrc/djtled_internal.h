@@ -40,20 +40,27 @@ inline int kind_of(int ne, int model) { return (ne == 8 ? 2 : 0) + (model == DJ_
 
 // Element-constant plane indices.  Each plane holds one scalar per element
 // (structure of arrays, element stride `estride`).
+constexpr int model_planes(int model) {  // planes of the material part, after 0J^-1, mu 0V, kappa 0V
+    return model == DJ_TI ? 4 : model == DJ_OT ? 8 : model == DJ_MR ? 1 : 0;
+}
+
 template <int NE, int MODEL>
 struct Planes {
     static constexpr int JINV = 0;                        // 0J^-1, row-major 3 x 3
-    static constexpr int MUV = 9;                         // mu * 0V
+    static constexpr int MUV = 9;                         // mu * 0V (MR: 2 C10 0V)
     static constexpr int KAV = 10;                        // kappa * 0V
-    static constexpr int FIB = 11;                        // TI: unit fibre a (3)
-    static constexpr int ETAV = 14;                       // TI: eta_a * 0V
-    static constexpr int HG = (MODEL == DJ_TI) ? 15 : 11; // H8: g_alpha (4 x 3)
+    static constexpr int FIB = 11;                        // TI, OT: unit fibre a (3)
+    static constexpr int ETAV = 14;                       // TI, OT: eta_a * 0V
+    static constexpr int FIBB = 15;                       // OT: unit fibre b (3)
+    static constexpr int ETABV = 18;                      // OT: eta_b * 0V
+    static constexpr int C01V = 11;                       // MR: C01 * 0V
+    static constexpr int HG = 11 + model_planes(MODEL);   // H8: g_alpha (4 x 3)
     static constexpr int KHG = HG + 12;                   // H8: hourglass stiffness
     static constexpr int N = (NE == 8) ? KHG + 1 : HG;    // number of planes
 };
 
 inline int n_planes(int ne, int model) {
-    int n = (model == DJ_TI) ? 15 : 11;
+    const int n = 11 + model_planes(model);
     return ne == 8 ? n + 13 : n;
 }
 
@@ -180,9 +187,16 @@ int make_loadset(Ctx &c, const djtled_loads *ld, const double *node_rate, LoadSe
 
 // ---- kernel launchers (djtled_kernels.hip) ----
 hipError_t occupancy(int ne, int model, int prec, int variant, int *blocks_per_cu, size_t *lds_bytes);
-hipError_t launch_precompute(Ctx &c, const double *dX, const int32_t *dconn, const double *dE, const double *dnu,
-                             const double *deta, const double *dfib, const int32_t *d_einst, double *d_dtmin,
-                             int32_t *d_bad, hipStream_t s);
+// per-element material arrays (device, FP64, original element order); the
+// fibre and C01 arrays are read only by the models that use them
+struct MatDev {
+    const double *E, *nu;
+    const double *eta, *fib;    // TI, OT: fibre a
+    const double *etab, *fibb;  // OT: fibre b
+    const double *c01;          // MR
+};
+hipError_t launch_precompute(Ctx &c, const double *dX, const int32_t *dconn, const MatDev &m, const int32_t *d_einst,
+                             double *d_dtmin, int32_t *d_bad, hipStream_t s);
 // c2: per internal node 2 dt^2 / (2 + alpha dt) of its instance; bp: per node
 // B' (written per copy to c.d_bpc when that is allocated)
 hipError_t launch_mass_acoef(Ctx &c, const int32_t *d_ne_off, const int32_t *d_ne_list, const double *d_c2,

@@ -181,8 +181,9 @@ __device__ __forceinline__ double tri_area(const double *p, const double *q, con
 template <typename T, int NE, int MODEL>
 __global__ void k_precompute(const double *__restrict__ X, const int32_t *__restrict__ conn, int E,
                              const double *__restrict__ Ein, const double *__restrict__ nuin,
-                             const double *__restrict__ etar, const double *__restrict__ fib, double hg_kappa,
-                             double rho, T *__restrict__ planes, int64_t es, double *__restrict__ V64,
+                             const double *__restrict__ etar, const double *__restrict__ fib,
+                             const double *__restrict__ etabr, const double *__restrict__ fibb,
+                             const double *__restrict__ c01in, double hg_kappa, double rho, T *__restrict__ planes, int64_t es, double *__restrict__ V64,
                              double *__restrict__ jinv64, const int32_t *__restrict__ einst,
                              unsigned long long *__restrict__ dtmin, int32_t *__restrict__ bad) {
     using P = Planes<NE, MODEL>;
@@ -231,20 +232,29 @@ __global__ void k_precompute(const double *__restrict__ X, const int32_t *__rest
     planes[P::MUV * es + e] = T(mu * V);
     planes[P::KAV * es + e] = T(ka * V);
     V64[e] = V;
-    double eta = 0.0;
-    if (MODEL == DJ_TI) {
-        double a0 = fib[3 * int64_t(e)], a1 = fib[3 * int64_t(e) + 1], a2 = fib[3 * int64_t(e) + 2];
-        const double nrm = sqrt(a0 * a0 + a1 * a1 + a2 * a2);
-        if (!(nrm > 0.0)) {
-            atomicAdd(bad, 1);
-            return;
+    // fibre stiffness (TI: a; OT: a and b) and the Mooney-Rivlin C01; they
+    // raise the dilatational wave speed of Eq. 14 and the hourglass stiffness
+    double eta = 0.0, c01 = 0.0;
+    if constexpr (MODEL == DJ_TI || MODEL == DJ_OT) {
+        for (int f = 0; f < (MODEL == DJ_OT ? 2 : 1); f++) {
+            const double *v = (f == 0 ? fib : fibb) + 3 * int64_t(e);
+            const double nrm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            if (!(nrm > 0.0)) {
+                atomicAdd(bad, 1);
+                return;
+            }
+            const double et = (f == 0 ? etar : etabr)[e] * mu;
+            const int fp = f == 0 ? P::FIB : P::FIBB, ep = f == 0 ? P::ETAV : P::ETABV;
+            for (int k = 0; k < 3; k++) planes[(fp + k) * es + e] = T(v[k] / nrm);
+            planes[ep * es + e] = T(et * V);
+            eta += et;
         }
-        eta = etar[e] * mu;
-        planes[(P::FIB + 0) * es + e] = T(a0 / nrm);
-        planes[(P::FIB + 1) * es + e] = T(a1 / nrm);
-        planes[(P::FIB + 2) * es + e] = T(a2 / nrm);
-        planes[P::ETAV * es + e] = T(eta * V);
     }
+    if constexpr (MODEL == DJ_MR) {
+        c01 = c01in[e];
+        planes[P::C01V * es + e] = T(c01 * V);
+    }
+    const double mu_eff = mu + 2.0 * c01;  // initial shear modulus 2 (C10 + C01)
     // characteristic length of Eq. 14
     double L;
     if (NE == 4) {
@@ -267,10 +277,10 @@ __global__ void k_precompute(const double *__restrict__ X, const int32_t *__rest
                 for (int b = 1; b < 8; b++) g += hgG(al, b) * (x[b][i] - x[0][i]);
                 planes[(P::HG + 3 * al + i) * es + e] = T(g);
             }
-        planes[P::KHG * es + e] = T(hg_kappa * (ka + 4.0 * mu / 3.0) * V * sb / 8.0);
+        planes[P::KHG * es + e] = T(hg_kappa * (ka + 4.0 * mu_eff / 3.0) * V * sb / 8.0);
         L = 1.0 / sqrt(2.0 * sb);
     }
-    const double cw = sqrt((ka + 4.0 * mu / 3.0 + 4.0 * eta) / rho);
+    const double cw = sqrt((ka + 4.0 * mu_eff / 3.0 + 4.0 * eta) / rho);
     const double dte = L / cw;
     // positive doubles order like their bit patterns
     atomicMin(dtmin + (einst ? einst[e] : 0), __double_as_longlong(dte));
@@ -409,6 +419,8 @@ template <typename T, int NE, int MODEL, int V>
 using InstV = Inst<T, NE, MODEL, var_table<T, NE>()[V].block, var_table<T, NE>()[V].ept, var_table<T, NE>()[V].mcopy,
                   var_table<T, NE>()[V].wpe>;
 
+// The three-waves-per-SIMD variants (4, 5) are built for the neo-Hookean and
+// transversely isotropic models only; the others have too little register room.
 template <typename T, int NE, int MODEL, typename F>
 static hipError_t with_variant(int v, F &&f) {
     switch (v) {
@@ -416,20 +428,30 @@ static hipError_t with_variant(int v, F &&f) {
         case 1: return f(InstV<T, NE, MODEL, 1>());
         case 2: return f(InstV<T, NE, MODEL, 2>());
         case 3: return f(InstV<T, NE, MODEL, 3>());
-        case 4: return f(InstV<T, NE, MODEL, 4>());
-        case 5: return f(InstV<T, NE, MODEL, 5>());
+        default: break;
+    }
+    if constexpr (MODEL == DJ_NH || MODEL == DJ_TI) {
+        if (v == 4) return f(InstV<T, NE, MODEL, 4>());
+        if (v == 5) return f(InstV<T, NE, MODEL, 5>());
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int NE, typename F>
+static hipError_t with_model(int model, int v, F &&f) {
+    switch (model) {
+        case DJ_NH: return with_variant<T, NE, DJ_NH>(v, f);
+        case DJ_TI: return with_variant<T, NE, DJ_TI>(v, f);
+        case DJ_OT: return with_variant<T, NE, DJ_OT>(v, f);
+        case DJ_MR: return with_variant<T, NE, DJ_MR>(v, f);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename F>
 static hipError_t dispatch(int prec, int ne, int model, int v, F &&f) {
-    if (prec == DJ_FP32) {
-        if (ne == 4) return model == DJ_NH ? with_variant<float, 4, DJ_NH>(v, f) : with_variant<float, 4, DJ_TI>(v, f);
-        return model == DJ_NH ? with_variant<float, 8, DJ_NH>(v, f) : with_variant<float, 8, DJ_TI>(v, f);
-    }
-    if (ne == 4) return model == DJ_NH ? with_variant<double, 4, DJ_NH>(v, f) : with_variant<double, 4, DJ_TI>(v, f);
-    return model == DJ_NH ? with_variant<double, 8, DJ_NH>(v, f) : with_variant<double, 8, DJ_TI>(v, f);
+    if (prec == DJ_FP32) return ne == 4 ? with_model<float, 4>(model, v, f) : with_model<float, 8>(model, v, f);
+    return ne == 4 ? with_model<double, 4>(model, v, f) : with_model<double, 8>(model, v, f);
 }
 
 const std::vector<Variant> &variants(int ne, int prec) {
@@ -453,34 +475,37 @@ hipError_t launch_step(Ctx &c, const StepArgs &a, const void *u_cur_in, const vo
                     [&](auto inst) { return decltype(inst)::step(c, a, u_cur_in, u_prev_in, s, ev0, ev1); });
 }
 
-template <typename T>
-static hipError_t precompute_t(Ctx &c, const double *dX, const int32_t *dconn, const double *dE, const double *dnu,
-                               const double *deta, const double *dfib, const int32_t *dei, double *d_dtmin,
-                               int32_t *d_bad, hipStream_t s) {
+template <typename T, int NE, int MODEL>
+static void precompute_m(Ctx &c, const double *dX, const int32_t *dconn, const MatDev &m, const int32_t *dei,
+                         unsigned long long *dtm, int32_t *d_bad, hipStream_t s) {
     const int B = 256, G = (c.n_elems + B - 1) / B;
-    T *planes = static_cast<T *>(c.d_elem);
-    auto *dtm = reinterpret_cast<unsigned long long *>(d_dtmin);
-    const int64_t es = c.topo.estride;
-    if (c.ne == 4 && c.model == DJ_NH)
-        hipLaunchKernelGGL((k_precompute<T, 4, DJ_NH>), dim3(G), dim3(B), 0, s, dX, dconn, c.n_elems, dE, dnu, deta,
-                           dfib, c.hg_kappa, c.rho, planes, es, c.d_V64, c.d_jinv64, dei, dtm, d_bad);
-    else if (c.ne == 4)
-        hipLaunchKernelGGL((k_precompute<T, 4, DJ_TI>), dim3(G), dim3(B), 0, s, dX, dconn, c.n_elems, dE, dnu, deta,
-                           dfib, c.hg_kappa, c.rho, planes, es, c.d_V64, c.d_jinv64, dei, dtm, d_bad);
-    else if (c.model == DJ_NH)
-        hipLaunchKernelGGL((k_precompute<T, 8, DJ_NH>), dim3(G), dim3(B), 0, s, dX, dconn, c.n_elems, dE, dnu, deta,
-                           dfib, c.hg_kappa, c.rho, planes, es, c.d_V64, c.d_jinv64, dei, dtm, d_bad);
-    else
-        hipLaunchKernelGGL((k_precompute<T, 8, DJ_TI>), dim3(G), dim3(B), 0, s, dX, dconn, c.n_elems, dE, dnu, deta,
-                           dfib, c.hg_kappa, c.rho, planes, es, c.d_V64, c.d_jinv64, dei, dtm, d_bad);
-    return hipGetLastError();
+    hipLaunchKernelGGL((k_precompute<T, NE, MODEL>), dim3(G), dim3(B), 0, s, dX, dconn, c.n_elems, m.E, m.nu, m.eta,
+                       m.fib, m.etab, m.fibb, m.c01, c.hg_kappa, c.rho, static_cast<T *>(c.d_elem), c.topo.estride,
+                       c.d_V64, c.d_jinv64, dei, dtm, d_bad);
 }
 
-hipError_t launch_precompute(Ctx &c, const double *dX, const int32_t *dconn, const double *dE, const double *dnu,
-                             const double *deta, const double *dfib, const int32_t *d_einst, double *d_dtmin,
-                             int32_t *d_bad, hipStream_t s) {
-    if (c.prec == DJ_FP32) return precompute_t<float>(c, dX, dconn, dE, dnu, deta, dfib, d_einst, d_dtmin, d_bad, s);
-    return precompute_t<double>(c, dX, dconn, dE, dnu, deta, dfib, d_einst, d_dtmin, d_bad, s);
+template <typename T, int NE>
+static void precompute_ne(Ctx &c, const double *dX, const int32_t *dconn, const MatDev &m, const int32_t *dei,
+                          unsigned long long *dtm, int32_t *d_bad, hipStream_t s) {
+    switch (c.model) {
+        case DJ_NH: return precompute_m<T, NE, DJ_NH>(c, dX, dconn, m, dei, dtm, d_bad, s);
+        case DJ_TI: return precompute_m<T, NE, DJ_TI>(c, dX, dconn, m, dei, dtm, d_bad, s);
+        case DJ_OT: return precompute_m<T, NE, DJ_OT>(c, dX, dconn, m, dei, dtm, d_bad, s);
+        default: return precompute_m<T, NE, DJ_MR>(c, dX, dconn, m, dei, dtm, d_bad, s);
+    }
+}
+
+hipError_t launch_precompute(Ctx &c, const double *dX, const int32_t *dconn, const MatDev &m, const int32_t *d_einst,
+                             double *d_dtmin, int32_t *d_bad, hipStream_t s) {
+    auto *dtm = reinterpret_cast<unsigned long long *>(d_dtmin);
+    if (c.prec == DJ_FP32) {
+        if (c.ne == 4) precompute_ne<float, 4>(c, dX, dconn, m, d_einst, dtm, d_bad, s);
+        else precompute_ne<float, 8>(c, dX, dconn, m, d_einst, dtm, d_bad, s);
+    } else {
+        if (c.ne == 4) precompute_ne<double, 4>(c, dX, dconn, m, d_einst, dtm, d_bad, s);
+        else precompute_ne<double, 8>(c, dX, dconn, m, d_einst, dtm, d_bad, s);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_mass_acoef(Ctx &c, const int32_t *d_ne_off, const int32_t *d_ne_list, const double *d_c2,

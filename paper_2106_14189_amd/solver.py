@@ -59,7 +59,7 @@ class Solver:
 
     def __init__(self, X, conn, E, nu, model=L.DJ_NH, rho=1000.0, eta_ratio=None, fibre=None, hg_kappa=0.1,
                  precision="fp32", dt=0.0, dt_factor=0.9, alpha=0.0, chunk_elems=0, variant=0, device=0,
-                 allow_unstable_dt=False):
+                 allow_unstable_dt=False, eta_b_ratio=None, fibre_b=None, c01=None):
         torch.cuda.init()
         self.X = np.ascontiguousarray(X, dtype=np.float64)
         self.conn = np.ascontiguousarray(conn, dtype=np.int32)
@@ -74,11 +74,20 @@ class Solver:
         mat.E, mat.nu = _dptr(Ea), _dptr(nua)
         mat.rho = float(rho)
         mat.hg_kappa = float(hg_kappa)
-        if model == L.DJ_TI:
-            er = np.ascontiguousarray(np.broadcast_to(np.asarray(eta_ratio, np.float64), (self.n_elems,)))
-            fb = np.ascontiguousarray(np.broadcast_to(np.asarray(fibre, np.float64), (self.n_elems, 3)))
+        E1 = lambda a: np.ascontiguousarray(np.broadcast_to(np.asarray(a, np.float64), (self.n_elems,)))
+        E3 = lambda a: np.ascontiguousarray(np.broadcast_to(np.asarray(a, np.float64), (self.n_elems, 3)))
+        if model in (L.DJ_TI, L.DJ_OT):
+            er, fb = E1(eta_ratio), E3(fibre)
             keep += [er, fb]
             mat.eta_ratio, mat.fibre = _dptr(er), _dptr(fb)
+        if model == L.DJ_OT:
+            er, fb = E1(eta_b_ratio), E3(fibre_b)
+            keep += [er, fb]
+            mat.eta_b_ratio, mat.fibre_b = _dptr(er), _dptr(fb)
+        if model == L.DJ_MR:
+            cc = E1(c01)
+            keep.append(cc)
+            mat.c01 = _dptr(cc)
         self.precision = L.DJ_FP64 if precision in ("fp64", L.DJ_FP64) else L.DJ_FP32
         self.dtype = torch.float64 if self.precision == L.DJ_FP64 else torch.float32
         prm = L.djtled_params(self.precision, float(dt), float(dt_factor), float(alpha), int(allow_unstable_dt),
@@ -170,8 +179,12 @@ def from_workload(wl, **kw) -> Solver:
     mat = wl.material
     args = dict(model=mat.model, rho=mat.rho, hg_kappa=mat.hg_kappa, precision="fp64" if wl.fp64 else "fp32",
                 dt_factor=wl.dt_factor, alpha=wl.alpha)
-    if mat.model == L.DJ_TI:
+    if mat.model in (L.DJ_TI, L.DJ_OT):
         args.update(eta_ratio=mat.eta_ratio, fibre=mat.fibre)
+    if mat.model == L.DJ_OT:
+        args.update(eta_b_ratio=mat.eta_b_ratio, fibre_b=mat.fibre_b)
+    if mat.model == L.DJ_MR:
+        args.update(c01=mat.c01)
     args.update(kw)
     return Solver(wl.mesh.X, wl.mesh.conn, mat.E, mat.nu, **args)
 

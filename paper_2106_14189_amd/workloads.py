@@ -24,7 +24,7 @@ import numpy as np
 SEED_BASE = 210614189
 
 T4, H8 = 4, 8
-NH, TI = 0, 1
+NH, TI, OT, MR = 0, 1, 2, 3
 RAMP_NONE, RAMP_LINEAR, RAMP_SMOOTH = 0, 1, 2
 
 
@@ -59,9 +59,12 @@ class Material:
     E: np.ndarray                       # (E,) Young's modulus [Pa]
     nu: np.ndarray                      # (E,) Poisson's ratio
     rho: float = 1000.0
-    eta_ratio: np.ndarray | None = None  # (E,) fibre stiffness ratio (TI)
-    fibre: np.ndarray | None = None      # (E, 3) unit fibre directions (TI)
+    eta_ratio: np.ndarray | None = None  # (E,) fibre stiffness ratio eta_a / mu (TI, OT)
+    fibre: np.ndarray | None = None      # (E, 3) unit fibre directions a (TI, OT)
     hg_kappa: float = 0.1
+    eta_b_ratio: np.ndarray | None = None  # (E,) second fibre ratio eta_b / mu (OT)
+    fibre_b: np.ndarray | None = None      # (E, 3) unit fibre directions b, orthogonal to a (OT)
+    c01: np.ndarray | None = None          # (E,) Mooney-Rivlin C01 [Pa] (MR; C10 = mu / 2)
 
 
 @dataclass
@@ -252,15 +255,28 @@ def compression_loads(mesh: Mesh, strain: float = -0.2, ramp=RAMP_SMOOTH, t_ramp
     return Loads(bc_node=bc_node, bc_mask=bc_mask, bc_target=tgt, ramp=ramp, t_ramp=t_ramp)
 
 
-def uniform_material(n_elems, E, nu, rho=1000.0, model=NH, rng=None, eta_ratio_range=(2.0, 10.0)):
+def uniform_material(n_elems, E, nu, rho=1000.0, model=NH, rng=None, eta_ratio_range=(2.0, 10.0),
+                     c01_ratio_range=(0.2, 1.0)):
+    """Material of one model.  TI/OT: fibre a uniform on the sphere and
+    eta_a / mu ~ U(eta_ratio_range); OT adds b uniform on the circle orthogonal
+    to a and eta_b / mu from the same range; MR: C01 / C10 ~ U(c01_ratio_range)
+    with C10 = mu / 2."""
     E = np.broadcast_to(np.asarray(E, np.float64), (n_elems,)).copy()
     nu = np.broadcast_to(np.asarray(nu, np.float64), (n_elems,)).copy()
     mat = Material(model=model, E=E, nu=nu, rho=rho)
-    if model == TI:
-        rng = rng or np.random.default_rng(0)
+    rng = rng or np.random.default_rng(0)
+    if model in (TI, OT):
         v = rng.normal(size=(n_elems, 3))
         mat.fibre = v / np.linalg.norm(v, axis=1, keepdims=True)
         mat.eta_ratio = rng.uniform(*eta_ratio_range, size=n_elems)
+    if model == OT:
+        w = rng.normal(size=(n_elems, 3))
+        w -= np.sum(w * mat.fibre, axis=1, keepdims=True) * mat.fibre
+        mat.fibre_b = w / np.linalg.norm(w, axis=1, keepdims=True)
+        mat.eta_b_ratio = rng.uniform(*eta_ratio_range, size=n_elems)
+    if model == MR:
+        mu = E / (2.0 * (1.0 + nu))
+        mat.c01 = rng.uniform(*c01_ratio_range, size=n_elems) * mu / 2.0
     return mat
 
 

@@ -38,9 +38,13 @@ def _case(elem, model, n=6, seed=1, permute=True, jitter=0.05):
     mesh = W.cube_mesh(n, 0.1 / n, elem, jitter=jitter, seed=seed, permute=permute)
     E = rng.uniform(2000.0, 6000.0, mesh.n_elems)
     kw = {}
-    if model == W.TI:
+    if model in (W.TI, W.OT):
         v = rng.normal(size=(mesh.n_elems, 3))
         kw = dict(eta_ratio=rng.uniform(2.0, 10.0, mesh.n_elems), fibre=v / np.linalg.norm(v, axis=1, keepdims=True))
+    if model == W.OT:  # b not orthogonal to a and not normalised: the library normalises it
+        kw.update(eta_b_ratio=rng.uniform(2.0, 10.0, mesh.n_elems), fibre_b=rng.normal(size=(mesh.n_elems, 3)))
+    if model == W.MR:
+        kw = dict(c01=rng.uniform(0.2, 1.0, mesh.n_elems) * E / (2 * 1.45) / 2)
     return mesh, E, 0.45, kw, rng
 
 
@@ -83,10 +87,29 @@ def test_forces_parity(S, elem, model, prec, variant, chunk):
 
 
 @pytest.mark.parametrize("elem", [W.T4, W.H8])
-def test_export_constants_match_oracle(S, elem):
-    mesh, E, nu, kw, rng = _case(elem, W.NH, n=5, seed=9)
-    sv = _solver(S, mesh, E, nu, W.NH, kw, "fp32")
-    ora = _oracle(mesh, E, nu, W.NH, kw)
+@pytest.mark.parametrize("model", [W.OT, W.MR])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("variant,chunk", [(0, 0), (2, 37)])
+def test_forces_parity_ot_mr(S, elem, model, prec, variant, chunk):
+    """Orthotropic and Mooney-Rivlin rows of Table 3, same tolerances as above."""
+    test_forces_parity(S, elem, model, prec, variant, chunk)
+
+
+@pytest.mark.parametrize("model", [W.OT, W.MR])
+def test_ot_mr_reject_three_wave_variants(S, model):
+    mesh, E, nu, kw, rng = _case(W.T4, model, n=3, seed=1)
+    with pytest.raises(Exception, match="variants 4 and 5"):
+        _solver(S, mesh, E, nu, model, kw, "fp32", variant=4)
+
+
+@pytest.mark.parametrize("elem", [W.T4, W.H8])
+@pytest.mark.parametrize("model", [W.NH, W.OT, W.MR])
+def test_export_constants_match_oracle(S, elem, model):
+    """Volumes, shape derivatives, masses and the critical step (the OT and MR
+    moduli raise the wave speed of Eq. 14)."""
+    mesh, E, nu, kw, rng = _case(elem, model, n=5, seed=9)
+    sv = _solver(S, mesh, E, nu, model, kw, "fp32")
+    ora = _oracle(mesh, E, nu, model, kw)
     V, B, m = sv.export_constants()
     np.testing.assert_allclose(m, ora.mass(), rtol=1e-12)
     for e in range(0, mesh.n_elems, 17):
@@ -141,8 +164,8 @@ def test_full_run_config0_fp64(S):
 
 
 @pytest.mark.parametrize("elem", [W.T4, W.H8])
-@pytest.mark.parametrize("model", [W.NH, W.TI])
-@pytest.mark.parametrize("variant", [0, 4, 5])
+@pytest.mark.parametrize("model,variant", [(W.NH, 0), (W.NH, 4), (W.NH, 5), (W.TI, 0), (W.TI, 4), (W.TI, 5),
+                                           (W.OT, 0), (W.MR, 0)])
 def test_full_run_fp32_small(S, elem, model, variant):
     """FP32 run on a 10^3 cube (permuted, per-element E): <= 1e-4 after 600 steps."""
     mesh, E, nu, kw, rng = _case(elem, model, n=10, seed=21)
