@@ -17,6 +17,8 @@ Further measurements, reported under "extra" (each skippable):
   * batch: 256 box instances (5k-200k elements, T4/H8 x NH/TI, own loads),
     500 steps in one batched persistent launch from a hipGraph, autotuned;
     aggregate element-steps/s and per-instance completion p50/p99;
+  * models: the config-1 cubes with each material model of Table 3 (NH,
+    TI, OT, MR): time per step and overhead over NH;
   * relaxation: the ~1.2M-tet transversely isotropic ellipsoid relaxed to
     r <= 1e-3 in FP32 and finished to r <= 1e-6 in FP64;
   * warm start: surrogate trained on the GPU from relaxation steady states
@@ -135,6 +137,48 @@ def bench_batch(log, variant: int = -1) -> dict:
     return out
 
 
+def bench_models(log, steps: int = 500) -> dict:
+    """The four material models of Table 3 on the config-1 cubes (T4 and H8,
+    FP32, kernel variant 0): kernel time per step and the overhead of TI, OT
+    and MR over NH (Table 7 reports the same overheads on the paper's GPU).
+    Fibre and C01 inputs as workloads.uniform_material draws them."""
+    import numpy as np
+    import torch
+    from paper_2106_14189_amd import solver as S
+    from paper_2106_14189_amd import workloads as W
+    out = {}
+    for elem in (W.T4, W.H8):
+        wl = W.config1(elem)
+        tag = "t4" if elem == W.T4 else "h8"
+        ms = {}
+        for model, name in ((W.NH, "nh"), (W.TI, "ti"), (W.OT, "ot"), (W.MR, "mr")):
+            mat = W.uniform_material(wl.mesh.n_elems, wl.material.E, 0.45, 1000.0, model=model,
+                                     rng=np.random.default_rng(11 + model))
+            sv = S.Solver(wl.mesh.X, wl.mesh.conn, mat.E, mat.nu, model=model, rho=mat.rho, eta_ratio=mat.eta_ratio,
+                          fibre=mat.fibre, eta_b_ratio=mat.eta_b_ratio, fibre_b=mat.fibre_b, c01=mat.c01,
+                          hg_kappa=mat.hg_kappa, alpha=wl.alpha, variant=0)
+            info = sv.info()
+            ld = wl.loads
+            ls = sv.loadset(ld.bc_node, ld.bc_mask, ld.bc_target, ld.ramp, 1000 * info["dt"])
+            u, up = sv.zeros(), sv.zeros()
+            st, step = sv.step(u, up, 50, ls)
+            st, step = sv.step(u, up, steps, ls, step0=step)
+            torch.cuda.synchronize()
+            assert st.code == 0 and st.steps_done == steps, st
+            ms[name] = st.kernel_ms / steps
+            out[f"{tag}_{name}_kernel_us_per_step"] = ms[name] * 1e3
+            out[f"{tag}_{name}_element_steps_per_s"] = info["n_elems"] / (ms[name] / 1e3)
+            out[f"{tag}_{name}_bytes_per_step"] = info["bytes_per_step"]
+            out[f"{tag}_{name}_effective_GBps"] = info["bytes_per_step"] / (ms[name] / 1e3) / 1e9
+            sv.close()
+        for name in ("ti", "ot", "mr"):
+            out[f"{tag}_{name}_overhead_vs_nh"] = ms[name] / ms["nh"] - 1.0
+        log(f"models {tag}: " + ", ".join(f"{k} {v * 1e3:.1f} us" for k, v in ms.items()))
+    out["workload"] = "cube64_t4+h8_fp32_compression_nh/ti/ot/mr"
+    out["steps"] = steps
+    return out
+
+
 def bench_relaxation(log) -> dict:
     """Config 2: FP32 relaxation to 1e-3 (above its rounding floor), FP64 finish to 1e-6."""
     import torch
@@ -247,6 +291,7 @@ def main():
                     help="after the run, copy a 256 MiB buffer 4 times (calibrates rocprofv3 byte counters)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-instance batch measurement")
     ap.add_argument("--batch-variant", type=int, default=-1, help="batch kernel variant (-1: autotune)")
+    ap.add_argument("--no-models", action="store_true", help="skip the four-material-model measurement")
     ap.add_argument("--no-relax", action="store_true", help="skip the ellipsoid relaxation measurement")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start measurement")
     ap.add_argument("--no-mlp", action="store_true", help="skip the full-size network timing")
@@ -351,6 +396,7 @@ def main():
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
     extra = {}
     for name, skip, fn in (("batch", args.no_batch, lambda lg: bench_batch(lg, args.batch_variant)),
+                           ("models", args.no_models, bench_models),
                            ("relaxation", args.no_relax, bench_relaxation),
                            ("mlp", args.no_mlp, bench_mlp), ("warm_start", args.no_warm, bench_warm_start),
                            ("warm_start_full", not args.warm_full, bench_warm_start_full)):

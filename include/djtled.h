@@ -93,7 +93,8 @@ typedef struct {
     double alpha;           /* mass-proportional damping D = alpha M [1/s] (Eq. 13) */
     int32_t allow_unstable_dt;  /* nonzero: accept dt above the critical step */
     int32_t chunk_elems;    /* elements per workgroup tile; 0 -> automatic */
-    int32_t variant;        /* step kernel variant 0..5 (threads, elements per thread, register budget) */
+    int32_t variant;        /* step kernel variant 0..5 (threads, elements per thread, register budget);
+                               -1: automatic (FP32 H8: 2, otherwise 0) */
     int32_t device;         /* HIP device ordinal; < 0 -> current device */
 } djtled_params;
 

@@ -133,7 +133,9 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     c.rho = mat->rho;
     c.alpha = prm->alpha;
     c.hg_kappa = mat->hg_kappa < 0 ? 0.1 : mat->hg_kappa;
-    c.variant = prm->variant;
+    // automatic: the fastest variant measured on the 64^3 cubes (FP32 H8: 512
+    // threads with one workgroup per compute unit; otherwise variant 0)
+    c.variant = prm->variant >= 0 ? prm->variant : (NE == 8 && c.prec == DJ_FP32 ? 2 : 0);
     const Variant var = variants(NE, c.prec)[c.variant];
     c.block = var.block;
     c.ept = var.ept;
@@ -605,7 +607,7 @@ int djtled_precompute(const djtled_mesh *mesh, const djtled_material *mat, const
     if ((mat->model == DJ_OT || mat->model == DJ_MR) && prm->variant >= 4)
         return fail(DJ_ERR_UNSUPPORTED, "variants 4 and 5 are built for DJ_NH and DJ_TI only");
     if (!(prm->alpha >= 0) || !(prm->dt >= 0)) return fail(DJ_ERR_ARG, "alpha and dt must be >= 0");
-    if (prm->variant < 0 || prm->variant >= int(variants(mesh->elem_type, prm->precision).size()))
+    if (prm->variant < -1 || prm->variant >= int(variants(mesh->elem_type, prm->precision).size()))
         return fail(DJ_ERR_ARG, "unknown kernel variant");
     if (prm->chunk_elems < 0) return fail(DJ_ERR_ARG, "chunk_elems must be >= 0");
     const int64_t nconn = int64_t(mesh->n_elems) * mesh->elem_type;

@@ -445,84 +445,121 @@ struct Chunk {
         }
     }
 
+    // Registers of one chunk's element data and of its node copies, so that
+    // the loads of the next chunk can be issued while this one is summed.
+    struct ElemRegs {
+        T cst[EPT][NP];
+        int wp[EPT][NE];
+    };
+    struct CopyRegs {
+        uint32_t cr[MC], fl[MC];
+        int pb[MC];
+        T ux[MC][3], upv[MC][3], A[MC], Bp[MC], rr[MC], rv[MC][3];
+    };
+
+    // Element planes and slot positions (register path).  Lanes past the
+    // chunk's end load its last element again: the loads are unconditional, so
+    // no lane keeps an older value and nothing waits on them before use.
+    __device__ static void load_elems(const DevTopo &tp, const ChunkDesc &ch, ElemRegs &er) {
+        if constexpr (!PF) {
+            const T *__restrict__ ep = static_cast<const T *>(tp.elem);
+            const int64_t es = tp.estride;
+#pragma unroll
+            for (int j = 0; j < EPT; j++) {
+                const int e = min(int(threadIdx.x) + j * BLOCK, ch.elem_count - 1);
+                const T *src = ep + ch.elem_begin + e;
+#pragma unroll
+                for (int q = 0; q < NP; q++) er.cst[j][q] = __builtin_nontemporal_load(src + q * es);
+                const uint16_t *w = tp.wpos + ch.elem_begin + e;
+#pragma unroll
+                for (int a = 0; a < NE; a++) er.wp[j][a] = __builtin_nontemporal_load(w + a * es);
+            }
+        }
+    }
+
+    // Per-copy data of the chunk's node copies (MODE 1 adds what the update
+    // needs, except the load values, which load_rv fetches once the flags are
+    // in).  Range, flags and u^n as in load_elems (clamped, unconditional).
+    template <int MODE>
+    __device__ static void load_copies(const DevTopo &tp, const ChunkDesc &ch, const StepPtrs<T> &sp, CopyRegs &c) {
+        const int tid = threadIdx.x;
+#pragma unroll
+        for (int m = 0; m < MC; m++) {
+            const int i = tid + m * BLOCK;
+            const int l = ch.copy_begin + min(i, ch.copy_count - 1);
+            c.cr[m] = tp.crange[l];
+            c.fl[m] = sp.flags[l];
+#pragma unroll
+            for (int k = 0; k < 3; k++) c.ux[m][k] = sp.uc[k][l];
+            if (i < ch.copy_count) {
+                if (i >= ch.n_interior) {
+                    c.pb[m] = tp.pidx[l];
+                } else if (MODE == 1) {
+#pragma unroll
+                    for (int k = 0; k < 3; k++) c.upv[m][k] = sp.up[k][l];
+                    c.A[m] = sp.acoef[l];
+                    if constexpr (PC) c.Bp[m] = sp.bpc[l];
+                }
+            }
+        }
+    }
+
+    // loads (BC targets / forces) of interior copies, needed only at the update
+    template <int MODE>
+    __device__ static void load_rv(const ChunkDesc &ch, const StepPtrs<T> &sp, CopyRegs &c) {
+#pragma unroll
+        for (int m = 0; m < MC; m++) {
+            const int i = threadIdx.x + m * BLOCK;
+#pragma unroll
+            for (int k = 0; k < 3; k++) c.rv[m][k] = T(0);
+            if constexpr (PC) c.rr[m] = T(0);
+            if (MODE == 1 && i < ch.n_interior && (c.fl[m] & FLAG_RU)) {
+                const int l = ch.copy_begin + i;
+#pragma unroll
+                for (int k = 0; k < 3; k++) c.rv[m][k] = sp.ru[k][l];
+                if constexpr (PC) c.rr[m] = sp.rrate[l];
+            }
+        }
+    }
+
     // MODE 0: forces to the caller array; MODE 1: time-step update.  `after`
     // runs once the element forces are in LDS (PF: issues the next prefetch).
     template <int MODE, typename After = NoOp>
     __device__ static void element_phase(const DevTopo &tp, const ChunkDesc &ch, const StepPtrs<T> &sp,
                                          unsigned char *smem, PhaseOut &po, After after = After()) {
+        ElemRegs er;
+        CopyRegs cp;
+        load_elems(tp, ch, er);
+        load_copies<MODE>(tp, ch, sp, cp);
+        load_rv<MODE>(ch, sp, cp);
+        process<MODE, false>(tp, ch, sp, smem, po, er, cp, after);
+    }
+
+    // One chunk from registers loaded beforehand (RV: fetch the load values
+    // here, after the scatter).  `after` runs once the element forces are in
+    // LDS and the chunk's registers are consumed or copied, so it may reload
+    // `er` and `cin` with the next chunk's data.
+    template <int MODE, bool RV, typename After>
+    __device__ static void process(const DevTopo &tp, const ChunkDesc &ch, const StepPtrs<T> &sp, unsigned char *smem,
+                                   PhaseOut &po, ElemRegs &er, CopyRegs &cin, After after) {
         const int tid = threadIdx.x;
         T *lx = reinterpret_cast<T *>(smem);
         T *ly = lx + NE * CMAX;
         T *lz = lx + 2 * NE * CMAX;
-        const T *__restrict__ ep = static_cast<const T *>(tp.elem);
-        const int64_t es = tp.estride;
-        // ---- one round of requests (element data from registers, or staged in LDS)
-        T cst[EPT][NP];
-        int wp[EPT][NE];
-        if constexpr (!PF) {
-#pragma unroll
-            for (int j = 0; j < EPT; j++) {
-                const int e = tid + j * BLOCK;
-                if (e < ch.elem_count) {
-                    const T *src = ep + ch.elem_begin + e;
-#pragma unroll
-                    for (int q = 0; q < NP; q++) cst[j][q] = __builtin_nontemporal_load(src + q * es);
-                    const uint16_t *w = tp.wpos + ch.elem_begin + e;
-#pragma unroll
-                    for (int a = 0; a < NE; a++) wp[j][a] = __builtin_nontemporal_load(w + a * es);
-                }
-            }
-        }
-        uint32_t cr[MC], fl[MC];
-        int pb[MC];
-        T ux[MC][3], upv[MC][3], A[MC], Bp[MC], rr[MC];
-#pragma unroll
-        for (int m = 0; m < MC; m++) {
-            const int i = tid + m * BLOCK;
-            if (i < ch.copy_count) {
-                const int l = ch.copy_begin + i;
-                cr[m] = tp.crange[l];
-                fl[m] = sp.flags[l];
-#pragma unroll
-                for (int k = 0; k < 3; k++) ux[m][k] = sp.uc[k][l];
-                if (i >= ch.n_interior) {
-                    pb[m] = tp.pidx[l];
-                } else if (MODE == 1) {
-#pragma unroll
-                    for (int k = 0; k < 3; k++) upv[m][k] = sp.up[k][l];
-                    A[m] = sp.acoef[l];
-                    if constexpr (PC) Bp[m] = sp.bpc[l];
-                }
-            }
-        }
-        // loads (BC targets / forces) of interior copies, needed only at the update
-        T rv[MC][3];
-#pragma unroll
-        for (int m = 0; m < MC; m++) {
-            const int i = tid + m * BLOCK;
-#pragma unroll
-            for (int k = 0; k < 3; k++) rv[m][k] = T(0);
-            if constexpr (PC) rr[m] = T(0);
-            if (MODE == 1 && i < ch.n_interior && (fl[m] & FLAG_RU)) {
-                const int l = ch.copy_begin + i;
-#pragma unroll
-                for (int k = 0; k < 3; k++) rv[m][k] = sp.ru[k][l];
-                if constexpr (PC) rr[m] = sp.rrate[l];
-            }
-        }
         // ---- scatter u^n over each copy's contiguous incidence range
 #pragma unroll
         for (int m = 0; m < MC; m++) {
             const int i = tid + m * BLOCK;
             if (i < ch.copy_count) {
-                const int b = cr[m] & 0xffffu, n = cr[m] >> 16;
+                const int b = cin.cr[m] & 0xffffu, n = cin.cr[m] >> 16;
                 for (int q = b; q < b + n; q++) {
-                    lx[q] = ux[m][0];
-                    ly[q] = ux[m][1];
-                    lz[q] = ux[m][2];
+                    lx[q] = cin.ux[m][0];
+                    ly[q] = cin.ux[m][1];
+                    lz[q] = cin.ux[m][2];
                 }
             }
         }
+        if constexpr (RV) load_rv<MODE>(ch, sp, cin);
         if constexpr (PF) __builtin_amdgcn_s_waitcnt(0);  // this thread's staged loads have landed
         __syncthreads();
         if constexpr (PF) {
@@ -533,13 +570,13 @@ struct Chunk {
                 const int e = tid + j * BLOCK;
                 if (e < ch.elem_count) {
 #pragma unroll
-                    for (int q = 0; q < NP; q++) cst[j][q] = stage[q * CMAX + e];
+                    for (int q = 0; q < NP; q++) er.cst[j][q] = stage[q * CMAX + e];
 #pragma unroll
-                    for (int a = 0; a < NE; a++) wp[j][a] = wstage[a * 2 * WDW + e];
+                    for (int a = 0; a < NE; a++) er.wp[j][a] = wstage[a * 2 * WDW + e];
                 }
             }
         }
-        // ---- element forces, written back over the element's own positions
+    // ---- element forces, written back over the element's own positions
 #pragma unroll
         for (int j = 0; j < EPT; j++) {
             const int e = tid + j * BLOCK;
@@ -547,19 +584,19 @@ struct Chunk {
                 T u[NE][3], F[NE][3];
 #pragma unroll
                 for (int a = 0; a < NE; a++) {
-                    u[a][0] = lx[wp[j][a]];
-                    u[a][1] = ly[wp[j][a]];
-                    u[a][2] = lz[wp[j][a]];
+                    u[a][0] = lx[er.wp[j][a]];
+                    u[a][1] = ly[er.wp[j][a]];
+                    u[a][2] = lz[er.wp[j][a]];
                 }
-                const T J = element_force<T, NE, MODEL>(cst[j], u, F);
+                const T J = element_force<T, NE, MODEL>(er.cst[j], u, F);
                 // an inverted (or non-finite) element stops the run; its force is
                 // left out so that the error is reported at the element itself
                 const bool ok = J > T(0);
 #pragma unroll
                 for (int a = 0; a < NE; a++) {
-                    lx[wp[j][a]] = ok ? F[a][0] : T(0);
-                    ly[wp[j][a]] = ok ? F[a][1] : T(0);
-                    lz[wp[j][a]] = ok ? F[a][2] : T(0);
+                    lx[er.wp[j][a]] = ok ? F[a][0] : T(0);
+                    ly[er.wp[j][a]] = ok ? F[a][1] : T(0);
+                    lz[er.wp[j][a]] = ok ? F[a][2] : T(0);
                 }
                 if (!isfinite(J)) {
                     po.bad = DJ_ERR_NONFINITE;
@@ -571,13 +608,14 @@ struct Chunk {
             }
         }
         __syncthreads();
+        const CopyRegs c = cin;
         after();
         // ---- node sums over each copy's range, in fixed order
 #pragma unroll
         for (int m = 0; m < MC; m++) {
             const int i = tid + m * BLOCK;
             if (i < ch.copy_count) {
-                const int b = cr[m] & 0xffffu, n = cr[m] >> 16;
+                const int b = c.cr[m] & 0xffffu, n = c.cr[m] >> 16;
                 T f[3] = {T(0), T(0), T(0)};
                 for (int q = b; q < b + n; q++) {
                     f[0] += lx[q];
@@ -586,7 +624,7 @@ struct Chunk {
                 }
                 const int l = ch.copy_begin + i;
                 if (i >= ch.n_interior) {
-                    const int q = pb[m] + int((fl[m] >> FLAG_RANK_SHIFT) & 255u);
+                    const int q = c.pb[m] + int((c.fl[m] >> FLAG_RANK_SHIFT) & 255u);
                     put_partial(sp.pp, q, f);
                     if (!(isfinite(f[0]) && isfinite(f[1]) && isfinite(f[2])) && po.bad == 0) {
                         po.bad = DJ_ERR_NONFINITE;
@@ -598,9 +636,10 @@ struct Chunk {
                     sp.fout[3 * nd + 1] = f[1];
                     sp.fout[3 * nd + 2] = f[2];
                 } else if constexpr (PC) {
-                    node_update<T>(l, fl[m], f, ux[m], upv[m], A[m], Bp[m], ramp_rate(rr[m], sp.n1), rv[m], sp, po);
+                    node_update<T>(l, c.fl[m], f, c.ux[m], c.upv[m], c.A[m], c.Bp[m], ramp_rate(c.rr[m], sp.n1), c.rv[m],
+                                   sp, po);
                 } else {
-                    node_update<T>(l, fl[m], f, ux[m], upv[m], A[m], sp.bprime, sp.sval, rv[m], sp, po);
+                    node_update<T>(l, c.fl[m], f, c.ux[m], c.upv[m], c.A[m], sp.bprime, sp.sval, c.rv[m], sp, po);
                 }
             }
         }

@@ -75,7 +75,25 @@ __global__ void __launch_bounds__(BLOCK, WPE) k_step(DevTopo tp, StepArgs a) {
         sp.rrate = nullptr;
         sp.n1 = T(n + 1);
         PhaseOut po{0.0, 0.0, 0, -1};
-        for (int k = 0; k < nmine; k++) C::template element_phase<1>(tp, s_ch[k], sp, smem, po);
+        // The copy data of chunk k + 1 is loaded while chunk k is summed and
+        // updated; the element data of chunk k is in flight during its
+        // scatter.  (Element data loaded one chunk ahead, or across the step
+        // boundary, measured slower: it does not fit the register budget of
+        // two waves per SIMD, or it competes with the shared phase's loads.)
+        // Variants built for three waves per SIMD keep the plain order.
+        if constexpr (WPE >= 3) {
+            for (int k = 0; k < nmine; k++) C::template element_phase<1>(tp, s_ch[k], sp, smem, po);
+        } else {
+            typename C::CopyRegs cp;
+            if (nmine > 0) C::template load_copies<1>(tp, s_ch[0], sp, cp);
+            for (int k = 0; k < nmine; k++) {
+                typename C::ElemRegs er;
+                C::load_elems(tp, s_ch[k], er);
+                C::template process<1, true>(tp, s_ch[k], sp, smem, po, er, cp, [&]() {
+                    if (k + 1 < nmine) C::template load_copies<1>(tp, s_ch[k + 1], sp, cp);
+                });
+            }
+        }
         // round A of the first batch of shared copies, in flight during the barrier
         SharedRegs<T, KB> sr;
         C::template shared_load<1, KB>(tp, s_ch, min(KB, nmine), 0, sp, sr);

@@ -58,7 +58,7 @@ class Solver:
     """One mesh + material + time step on one GPU (``djtled_precompute``)."""
 
     def __init__(self, X, conn, E, nu, model=L.DJ_NH, rho=1000.0, eta_ratio=None, fibre=None, hg_kappa=0.1,
-                 precision="fp32", dt=0.0, dt_factor=0.9, alpha=0.0, chunk_elems=0, variant=0, device=0,
+                 precision="fp32", dt=0.0, dt_factor=0.9, alpha=0.0, chunk_elems=0, variant=-1, device=0,
                  allow_unstable_dt=False, eta_b_ratio=None, fibre_b=None, c01=None):
         torch.cuda.init()
         self.X = np.ascontiguousarray(X, dtype=np.float64)
