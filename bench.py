@@ -18,7 +18,8 @@ Further measurements, reported under "extra" (each skippable):
     500 steps in one batched persistent launch from a hipGraph, autotuned;
     aggregate element-steps/s and per-instance completion p50/p99;
   * models: the config-1 cubes with each material model of Table 3 (NH,
-    TI, OT, MR): time per step and overhead over NH;
+    TI, OT, MR): time per step, overhead over NH, and the ratio to the same
+    step with the classical TLED force;
   * relaxation: the ~1.2M-tet transversely isotropic ellipsoid relaxed to
     r <= 1e-3 in FP32 and finished to r <= 1e-6 in FP64;
   * warm start: surrogate trained on the GPU from relaxation steady states
@@ -139,8 +140,10 @@ def bench_batch(log, variant: int = -1) -> dict:
 
 def bench_models(log, steps: int = 500) -> dict:
     """The four material models of Table 3 on the config-1 cubes (T4 and H8,
-    FP32, kernel variant 0): kernel time per step and the overhead of TI, OT
-    and MR over NH (Table 7 reports the same overheads on the paper's GPU).
+    FP32, automatic kernel variant): kernel time per step, the overhead of
+    TI, OT and MR over NH (Table 7 reports these overheads on the paper's
+    GPU), and the same step with the classical TLED force (Eq. 4) for the
+    DJ-TLED / TLED time ratio (Table 5 reports it on the paper's CPU).
     Fibre and C01 inputs as workloads.uniform_material draws them."""
     import numpy as np
     import torch
@@ -154,23 +157,29 @@ def bench_models(log, steps: int = 500) -> dict:
         for model, name in ((W.NH, "nh"), (W.TI, "ti"), (W.OT, "ot"), (W.MR, "mr")):
             mat = W.uniform_material(wl.mesh.n_elems, wl.material.E, 0.45, 1000.0, model=model,
                                      rng=np.random.default_rng(11 + model))
-            sv = S.Solver(wl.mesh.X, wl.mesh.conn, mat.E, mat.nu, model=model, rho=mat.rho, eta_ratio=mat.eta_ratio,
-                          fibre=mat.fibre, eta_b_ratio=mat.eta_b_ratio, fibre_b=mat.fibre_b, c01=mat.c01,
-                          hg_kappa=mat.hg_kappa, alpha=wl.alpha, variant=0)
-            info = sv.info()
-            ld = wl.loads
-            ls = sv.loadset(ld.bc_node, ld.bc_mask, ld.bc_target, ld.ramp, 1000 * info["dt"])
-            u, up = sv.zeros(), sv.zeros()
-            st, step = sv.step(u, up, 50, ls)
-            st, step = sv.step(u, up, steps, ls, step0=step)
-            torch.cuda.synchronize()
-            assert st.code == 0 and st.steps_done == steps, st
-            ms[name] = st.kernel_ms / steps
-            out[f"{tag}_{name}_kernel_us_per_step"] = ms[name] * 1e3
-            out[f"{tag}_{name}_element_steps_per_s"] = info["n_elems"] / (ms[name] / 1e3)
-            out[f"{tag}_{name}_bytes_per_step"] = info["bytes_per_step"]
-            out[f"{tag}_{name}_effective_GBps"] = info["bytes_per_step"] / (ms[name] / 1e3) / 1e9
-            sv.close()
+            for form, suffix in (("jacobian", ""), ("classical", "_classical")):
+                sv = S.Solver(wl.mesh.X, wl.mesh.conn, mat.E, mat.nu, model=model, rho=mat.rho,
+                              eta_ratio=mat.eta_ratio, fibre=mat.fibre, eta_b_ratio=mat.eta_b_ratio,
+                              fibre_b=mat.fibre_b, c01=mat.c01, hg_kappa=mat.hg_kappa, alpha=wl.alpha,
+                              formulation=form)
+                info = sv.info()
+                ld = wl.loads
+                ls = sv.loadset(ld.bc_node, ld.bc_mask, ld.bc_target, ld.ramp, 1000 * info["dt"])
+                u, up = sv.zeros(), sv.zeros()
+                st, step = sv.step(u, up, 50, ls)
+                st, step = sv.step(u, up, steps, ls, step0=step)
+                torch.cuda.synchronize()
+                assert st.code == 0 and st.steps_done == steps, st
+                key = name + suffix
+                ms[key] = st.kernel_ms / steps
+                out[f"{tag}_{key}_kernel_us_per_step"] = ms[key] * 1e3
+                out[f"{tag}_{key}_element_steps_per_s"] = info["n_elems"] / (ms[key] / 1e3)
+                if not suffix:
+                    out[f"{tag}_{name}_bytes_per_step"] = info["bytes_per_step"]
+                    out[f"{tag}_{name}_effective_GBps"] = info["bytes_per_step"] / (ms[key] / 1e3) / 1e9
+                    out[f"{tag}_variant"] = info["variant"]
+                sv.close()
+            out[f"{tag}_{name}_ratio_jacobian_over_classical"] = ms[name] / ms[name + "_classical"]
         for name in ("ti", "ot", "mr"):
             out[f"{tag}_{name}_overhead_vs_nh"] = ms[name] / ms["nh"] - 1.0
         log(f"models {tag}: " + ", ".join(f"{k} {v * 1e3:.1f} us" for k, v in ms.items()))

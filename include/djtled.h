@@ -50,6 +50,10 @@ enum { DJ_T4 = 4, DJ_H8 = 8 };                 /* linear tetrahedron, 8-node hex
 enum { DJ_NH = 0, DJ_TI = 1, DJ_OT = 2, DJ_MR = 3 };  /* Table 3 rows: neo-Hookean, transversely isotropic NH,
                                                        orthotropic NH, Mooney-Rivlin */
 enum { DJ_FP32 = 0, DJ_FP64 = 1 };
+/* Element force: the Jacobian form of Table 3 (the method), or the classical
+   TLED form of Eq. 4 (deformation gradient, C^-1 and the second Piola-Kirchhoff
+   stress of the same strain energy), kept as a comparison path (FP32 only). */
+enum { DJ_FORM_JACOBIAN = 0, DJ_FORM_CLASSICAL = 1 };
 enum { DJ_RAMP_NONE = 0, DJ_RAMP_LINEAR = 1, DJ_RAMP_SMOOTH = 2 };
 enum { DJ_MODE_FIXED = 0, DJ_MODE_RELAX = 1 };
 
@@ -96,6 +100,7 @@ typedef struct {
     int32_t variant;        /* step kernel variant 0..5 (threads, elements per thread, register budget);
                                -1: automatic (FP32 H8: 2, otherwise 0) */
     int32_t device;         /* HIP device ordinal; < 0 -> current device */
+    int32_t formulation;    /* DJ_FORM_JACOBIAN (0) or DJ_FORM_CLASSICAL; batches take 0 only */
 } djtled_params;
 
 typedef struct djtled_ctx djtled_ctx;
@@ -125,6 +130,7 @@ typedef struct {
     double bytes_per_step;     /* algorithmic HBM bytes of one fused step */
     double elem_bytes;         /* per-element part of bytes_per_step */
     double mass_total;         /* sum of lumped masses [kg] */
+    int32_t formulation;       /* DJ_FORM_JACOBIAN or DJ_FORM_CLASSICAL */
 } djtled_info_t;
 
 /* Fills *out with sizes, the time step and the traffic model. */

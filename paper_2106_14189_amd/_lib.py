@@ -24,6 +24,7 @@ DJ_ERR_UNSUPPORTED, DJ_ERR_UNSTABLE_DT, DJ_ERR_HIP, DJ_ERR_BARRIER = -5, -6, -7,
 DJ_T4, DJ_H8 = 4, 8
 DJ_NH, DJ_TI, DJ_OT, DJ_MR = 0, 1, 2, 3
 DJ_FP32, DJ_FP64 = 0, 1
+DJ_FORM_JACOBIAN, DJ_FORM_CLASSICAL = 0, 1
 DJ_RAMP_NONE, DJ_RAMP_LINEAR, DJ_RAMP_SMOOTH = 0, 1, 2
 DJ_MODE_FIXED, DJ_MODE_RELAX = 0, 1
 
@@ -52,7 +53,7 @@ class djtled_material(ctypes.Structure):
 class djtled_params(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("dt", ctypes.c_double), ("dt_factor", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("allow_unstable_dt", ctypes.c_int32), ("chunk_elems", ctypes.c_int32),
-                ("variant", ctypes.c_int32), ("device", ctypes.c_int32)]
+                ("variant", ctypes.c_int32), ("device", ctypes.c_int32), ("formulation", ctypes.c_int32)]
 
 
 class djtled_info_t(ctypes.Structure):
@@ -62,7 +63,7 @@ class djtled_info_t(ctypes.Structure):
                 ("chunk_elems", ctypes.c_int32), ("n_copies", ctypes.c_int32), ("n_shared_copies", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("block_threads", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("bytes_per_step", ctypes.c_double), ("elem_bytes", ctypes.c_double),
-                ("mass_total", ctypes.c_double)]
+                ("mass_total", ctypes.c_double), ("formulation", ctypes.c_int32)]
 
 
 class djtled_loads(ctypes.Structure):

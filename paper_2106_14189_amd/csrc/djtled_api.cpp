@@ -130,6 +130,7 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     c.ne = NE;
     c.model = mat->model;
     c.prec = prm->precision;
+    c.form = prm->formulation;
     c.rho = mat->rho;
     c.alpha = prm->alpha;
     c.hg_kappa = mat->hg_kappa < 0 ? 0.1 : mat->hg_kappa;
@@ -211,7 +212,7 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     // ---- grid size from occupancy, then balanced chunks
     int bpc = 0;
     size_t lds = 0;
-    DJ_HIP(occupancy(NE, c.model, c.prec, c.variant, &bpc, &lds));
+    DJ_HIP(occupancy(NE, c.model, c.form, c.prec, c.variant, &bpc, &lds));
     hipDeviceProp_t prop;
     DJ_HIP(hipGetDeviceProperties(&prop, c.device));
     if (bpc < 1) return fail(DJ_ERR_UNSUPPORTED, "kernel variant does not fit on a compute unit");
@@ -606,6 +607,10 @@ int djtled_precompute(const djtled_mesh *mesh, const djtled_material *mat, const
     if (mat->model == DJ_OT && !mat->fibre_b) return fail(DJ_ERR_ARG, "DJ_OT needs second fibre directions");
     if ((mat->model == DJ_OT || mat->model == DJ_MR) && prm->variant >= 4)
         return fail(DJ_ERR_UNSUPPORTED, "variants 4 and 5 are built for DJ_NH and DJ_TI only");
+    if (prm->formulation != DJ_FORM_JACOBIAN && prm->formulation != DJ_FORM_CLASSICAL)
+        return fail(DJ_ERR_ARG, "formulation must be DJ_FORM_JACOBIAN or DJ_FORM_CLASSICAL");
+    if (prm->formulation == DJ_FORM_CLASSICAL && (prm->precision != DJ_FP32 || prm->variant >= 4))
+        return fail(DJ_ERR_UNSUPPORTED, "the classical TLED form is built for FP32 and variants 0..3");
     if (!(prm->alpha >= 0) || !(prm->dt >= 0)) return fail(DJ_ERR_ARG, "alpha and dt must be >= 0");
     if (prm->variant < -1 || prm->variant >= int(variants(mesh->elem_type, prm->precision).size()))
         return fail(DJ_ERR_ARG, "unknown kernel variant");
@@ -661,6 +666,7 @@ int djtled_info(const djtled_ctx *ctx, djtled_info_t *o) {
     o->grid_blocks = c.grid;
     o->block_threads = c.block;
     o->variant = c.variant;
+    o->formulation = c.form;
     o->bytes_per_step = c.bytes_per_step;
     o->elem_bytes = c.elem_bytes;
     o->mass_total = c.mass_total;

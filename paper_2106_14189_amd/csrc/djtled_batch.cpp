@@ -466,6 +466,8 @@ int djtled_batch_create(int32_t n, const djtled_mesh *meshes, const djtled_mater
     *out = nullptr;
     if (n <= 0 || !meshes || !materials || !loads || !params) return fail(DJ_ERR_ARG, "empty batch or null arrays");
     if (params->precision != DJ_FP32 && params->precision != DJ_FP64) return fail(DJ_ERR_UNSUPPORTED, "precision");
+    if (params->formulation != DJ_FORM_JACOBIAN)
+        return fail(DJ_ERR_UNSUPPORTED, "batches use the Jacobian form (DJ_FORM_JACOBIAN) only");
     if (params->dt != 0.0) return fail(DJ_ERR_ARG, "batches take each instance's own step: dt must be 0");
     if (!(params->alpha >= 0)) return fail(DJ_ERR_ARG, "alpha must be >= 0");
     for (int i = 0; i < n; i++) {

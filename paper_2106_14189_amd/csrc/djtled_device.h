@@ -119,6 +119,103 @@ __device__ __forceinline__ void get_partial(T *const (&pp)[3], int q, T (&f)[3])
 // element force (register-resident).  cst: the element's planes.  u: nodal
 // displacements.  F: nodal forces.  Returns J.
 // ---------------------------------------------------------------------------
+// Classical TLED (Eq. 4 with the second Piola-Kirchhoff stress of each
+// model), for comparison with the Table 3 force: deformation gradient
+// X = I + D^T, C = X^T X, C^-1 from its cofactors, the invariants of Table 1,
+// S 0V from the decoupled strain energies of Table 3, and M = X S 0V 0J^-1.
+// Evaluated literally: its O(1) terms cancel to an O(strain) force.
+template <typename T, int NE, int MD>
+__device__ __forceinline__ T tled_stress_m(const T *__restrict__ cst, const T (&D)[3][3], T (&M)[3][3]) {
+    using P = Planes<NE, MD>;
+    T X[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) X[i][j] = (i == j ? T(1) : T(0)) + D[j][i];
+    const T J = X[0][0] * (X[1][1] * X[2][2] - X[1][2] * X[2][1]) - X[0][1] * (X[1][0] * X[2][2] - X[1][2] * X[2][0]) +
+                X[0][2] * (X[1][0] * X[2][1] - X[1][1] * X[2][0]);
+    T C[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) C[i][j] = X[0][i] * X[0][j] + X[1][i] * X[1][j] + X[2][i] * X[2][j];
+    T Ci[3][3];  // adj(C) / det C
+    Ci[0][0] = C[1][1] * C[2][2] - C[1][2] * C[2][1];
+    Ci[0][1] = C[0][2] * C[2][1] - C[0][1] * C[2][2];
+    Ci[0][2] = C[0][1] * C[1][2] - C[0][2] * C[1][1];
+    Ci[1][0] = C[1][2] * C[2][0] - C[1][0] * C[2][2];
+    Ci[1][1] = C[0][0] * C[2][2] - C[0][2] * C[2][0];
+    Ci[1][2] = C[0][2] * C[1][0] - C[0][0] * C[1][2];
+    Ci[2][0] = C[1][0] * C[2][1] - C[1][1] * C[2][0];
+    Ci[2][1] = C[0][1] * C[2][0] - C[0][0] * C[2][1];
+    Ci[2][2] = C[0][0] * C[1][1] - C[0][1] * C[1][0];
+    const T rdet = dj_rcp(C[0][0] * Ci[0][0] + C[0][1] * Ci[1][0] + C[0][2] * Ci[2][0]);
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) Ci[i][j] *= rdet;
+    const T I1 = C[0][0] + C[1][1] + C[2][2];
+    const T c = dj_cbrt(J);
+    const T Jm23 = dj_rcp(c * c);
+    const T muV = cst[P::MUV], kaV = cst[P::KAV];
+    // S 0V = J^-2/3 (mu I + 2 d4 a a^T + 2 d6 b b^T) + 2 C01 J^-4/3 (I1 I - C) + p C^-1
+    T W[3][3];  // the part multiplying J^-2/3
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) W[i][j] = (i == j ? muV : T(0));
+    T pV = -(muV * T(1.0 / 3.0)) * Jm23 * I1 + kaV * J * (J - T(1));
+    auto fibre = [&](const T *fv, T etaV) {
+        const T f[3] = {fv[0], fv[1], fv[2]};
+        T Cf[3];
+#pragma unroll
+        for (int i = 0; i < 3; i++) Cf[i] = C[i][0] * f[0] + C[i][1] * f[1] + C[i][2] * f[2];
+        const T Ib = Jm23 * (f[0] * Cf[0] + f[1] * Cf[1] + f[2] * Cf[2]);
+        const T dV = etaV * (Ib - T(1));
+        pV -= T(2.0 / 3.0) * dV * Ib;
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) W[i][j] += T(2) * dV * f[i] * f[j];
+    };
+    if constexpr (MD == DJ_TI || MD == DJ_OT) fibre(cst + P::FIB, cst[P::ETAV]);
+    if constexpr (MD == DJ_OT) fibre(cst + P::FIBB, cst[P::ETABV]);
+    T SV[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) SV[i][j] = Jm23 * W[i][j];
+    if constexpr (MD == DJ_MR) {
+        const T c01V = cst[P::C01V], Jm43 = Jm23 * Jm23;
+        T trC2 = 0;
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) trC2 += C[i][j] * C[j][i];
+        const T I2 = T(0.5) * (I1 * I1 - trC2);
+        pV -= T(4.0 / 3.0) * c01V * Jm43 * I2;
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) SV[i][j] += T(2) * c01V * Jm43 * ((i == j ? I1 : T(0)) - C[i][j]);
+    }
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) SV[i][j] += pV * Ci[i][j];
+    const T *Ji = cst + P::JINV;
+    T Q[3][3];  // X S 0V
+#pragma unroll
+    for (int k = 0; k < 3; k++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) Q[k][j] = X[k][0] * SV[0][j] + X[k][1] * SV[1][j] + X[k][2] * SV[2][j];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) M[i][j] = Q[i][0] * Ji[j] + Q[i][1] * Ji[3 + j] + Q[i][2] * Ji[6 + j];
+    return J;
+}
+
 template <typename T, int NE, int MODEL>
 __device__ __forceinline__ T element_force(const T *__restrict__ cst, const T (&u)[NE][3], T (&F)[NE][3]) {
     using P = Planes<NE, MODEL>;
@@ -154,103 +251,110 @@ __device__ __forceinline__ T element_force(const T *__restrict__ cst, const T (&
     for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int k = 0; k < 3; k++) D[i][k] = Ji[3 * i] * dJ[0][k] + Ji[3 * i + 1] * dJ[1][k] + Ji[3 * i + 2] * dJ[2][k];
-    const T trD = D[0][0] + D[1][1] + D[2][2];
-    T trD2 = 0, nD2 = 0;
-#pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-        for (int j = 0; j < 3; j++) {
-            trD2 += D[i][j] * D[j][i];
-            nD2 += D[i][j] * D[i][j];
-        }
-    const T detD = D[0][0] * (D[1][1] * D[2][2] - D[1][2] * D[2][1]) - D[0][1] * (D[1][0] * D[2][2] - D[1][2] * D[2][0]) +
-                   D[0][2] * (D[1][0] * D[2][1] - D[1][1] * D[2][0]);
-    const T Jm1 = trD + T(0.5) * (trD * trD - trD2) + detD;  // J - 1  (Eq. 12)
-    const T J = T(1) + Jm1;
-    const T I1m3 = T(2) * trD + nD2;                          // I1 - 3 (Eq. 27)
-    const T c = dj_cbrt(J);
-    const T Jm23 = dj_rcp(c * c);                             // J^-2/3
-    const T muV = cst[P::MUV], kaV = cst[P::KAV];
-    T c0 = -(muV * T(1.0 / 3.0)) * Jm23 * I1m3 + kaV * J * Jm1;  // (mu J^-2/3 + p) 0V
-    T ciso = muV * Jm23;                                          // the O(1) identity part of c0 - p 0V
-    T Q[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-        for (int k = 0; k < 3; k++) Q[i][k] = muV * Jm23 * D[k][i];
-    // fibre terms (TI: a; OT: a and b): 2 J^-2/3 psi 0V (f + D^T f) f^T, psi = eta (Ibar - 1)
-    auto fibre_term = [&](const T *fv, T etaV) {
-        const T f[3] = {fv[0], fv[1], fv[2]};
-        T Dtf[3];
-#pragma unroll
-        for (int k = 0; k < 3; k++) Dtf[k] = D[0][k] * f[0] + D[1][k] * f[1] + D[2][k] * f[2];
-        const T fDf = f[0] * Dtf[0] + f[1] * Dtf[1] + f[2] * Dtf[2];
-        const T Im1 = T(2) * fDf + Dtf[0] * Dtf[0] + Dtf[1] * Dtf[1] + Dtf[2] * Dtf[2];  // I4 - 1 (Eq. 31, 32)
-        const T Jm23m1 = -Jm1 * (c + T(1)) * dj_rcp(c * c * (c * c + c + T(1)));     // J^-2/3 - 1
-        const T Ibm1 = Jm23 * Im1 + Jm23m1;                                             // Ibar - 1
-        const T psiV = etaV * Ibm1;
-        c0 -= T(2.0 / 3.0) * psiV * (T(1) + Ibm1);
-        const T w = T(2) * Jm23 * psiV;
-#pragma unroll
-        for (int i = 0; i < 3; i++)
-#pragma unroll
-            for (int k = 0; k < 3; k++) Q[i][k] += w * (f[i] + Dtf[i]) * f[k];
-    };
-    if constexpr (MODEL == DJ_TI || MODEL == DJ_OT) fibre_term(cst + P::FIB, cst[P::ETAV]);
-    if constexpr (MODEL == DJ_OT) fibre_term(cst + P::FIBB, cst[P::ETABV]);
-    if constexpr (MODEL == DJ_MR) {
-        // C01 term: 2 C01 0V J^-4/3 (I + D^T)(I1 I - C) with C = I + G, G = D + D^T + D D^T;
-        // its identity part 4 C01 0V J^-4/3 joins c0, the rest is O(strain)
-        const T c01V = cst[P::C01V];
-        const T Jm43 = Jm23 * Jm23;
-        T G[3][3];
-#pragma unroll
-        for (int i = 0; i < 3; i++)
-#pragma unroll
-            for (int j = 0; j < 3; j++)
-                G[i][j] = D[i][j] + D[j][i] + D[i][0] * D[j][0] + D[i][1] * D[j][1] + D[i][2] * D[j][2];
-        T trG2 = 0;
-#pragma unroll
-        for (int i = 0; i < 3; i++)
-#pragma unroll
-            for (int j = 0; j < 3; j++) trG2 += G[i][j] * G[i][j];
-        const T I2m3 = T(2) * I1m3 + T(0.5) * (I1m3 * I1m3 - trG2);  // I2 - 3 (Eq. 28)
-        const T w = T(2) * c01V * Jm43;
-#pragma unroll
-        for (int i = 0; i < 3; i++)
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                const T DtG = D[0][i] * G[0][k] + D[1][i] * G[1][k] + D[2][i] * G[2][k];
-                Q[i][k] += w * (T(2) * D[k][i] + I1m3 * ((i == k ? T(1) : T(0)) + D[k][i]) - G[i][k] - DtG);
-            }
-        c0 -= T(4.0 / 3.0) * c01V * Jm43 * I2m3;  // p_MR 0V + 4 C01 0V J^-4/3
-        ciso += T(4) * c01V * Jm43;
-    }
-    const T pJ = (c0 - ciso) * dj_rcp(J);  // p 0V / J
-    // adj(I + D)
-    const T A00 = T(1) + D[0][0], A11 = T(1) + D[1][1], A22 = T(1) + D[2][2];
-    T adj[3][3];
-    adj[0][0] = A11 * A22 - D[1][2] * D[2][1];
-    adj[0][1] = D[0][2] * D[2][1] - D[0][1] * A22;
-    adj[0][2] = D[0][1] * D[1][2] - D[0][2] * A11;
-    adj[1][0] = D[1][2] * D[2][0] - D[1][0] * A22;
-    adj[1][1] = A00 * A22 - D[0][2] * D[2][0];
-    adj[1][2] = D[0][2] * D[1][0] - A00 * D[1][2];
-    adj[2][0] = D[1][0] * D[2][1] - A11 * D[2][0];
-    adj[2][1] = D[0][1] * D[2][0] - A00 * D[2][1];
-    adj[2][2] = A00 * A11 - D[0][1] * D[1][0];
-#pragma unroll
-    for (int i = 0; i < 3; i++) {
-        Q[i][i] += c0;
-#pragma unroll
-        for (int k = 0; k < 3; k++) Q[i][k] -= pJ * (D[i][0] * adj[0][k] + D[i][1] * adj[1][k] + D[i][2] * adj[2][k]);
-    }
-    // M = Q 0J^-1  (rows: force component, columns: natural direction)
+    constexpr int MD = base_model(MODEL);
     T M[3][3];
+    T J;
+    if constexpr ((MODEL & DJ_FORM_TLED) != 0) {
+        J = tled_stress_m<T, NE, MD>(cst, D, M);
+    } else {
+        const T trD = D[0][0] + D[1][1] + D[2][2];
+        T trD2 = 0, nD2 = 0;
 #pragma unroll
-    for (int i = 0; i < 3; i++)
+        for (int i = 0; i < 3; i++)
 #pragma unroll
-        for (int j = 0; j < 3; j++) M[i][j] = Q[i][0] * Ji[j] + Q[i][1] * Ji[3 + j] + Q[i][2] * Ji[6 + j];
+            for (int j = 0; j < 3; j++) {
+                trD2 += D[i][j] * D[j][i];
+                nD2 += D[i][j] * D[i][j];
+            }
+        const T detD = D[0][0] * (D[1][1] * D[2][2] - D[1][2] * D[2][1]) - D[0][1] * (D[1][0] * D[2][2] - D[1][2] * D[2][0]) +
+                       D[0][2] * (D[1][0] * D[2][1] - D[1][1] * D[2][0]);
+        const T Jm1 = trD + T(0.5) * (trD * trD - trD2) + detD;  // J - 1  (Eq. 12)
+        J = T(1) + Jm1;
+        const T I1m3 = T(2) * trD + nD2;                          // I1 - 3 (Eq. 27)
+        const T c = dj_cbrt(J);
+        const T Jm23 = dj_rcp(c * c);                             // J^-2/3
+        const T muV = cst[P::MUV], kaV = cst[P::KAV];
+        T c0 = -(muV * T(1.0 / 3.0)) * Jm23 * I1m3 + kaV * J * Jm1;  // (mu J^-2/3 + p) 0V
+        T ciso = muV * Jm23;                                          // the O(1) identity part of c0 - p 0V
+        T Q[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int k = 0; k < 3; k++) Q[i][k] = muV * Jm23 * D[k][i];
+        // fibre terms (TI: a; OT: a and b): 2 J^-2/3 psi 0V (f + D^T f) f^T, psi = eta (Ibar - 1)
+        auto fibre_term = [&](const T *fv, T etaV) {
+            const T f[3] = {fv[0], fv[1], fv[2]};
+            T Dtf[3];
+#pragma unroll
+            for (int k = 0; k < 3; k++) Dtf[k] = D[0][k] * f[0] + D[1][k] * f[1] + D[2][k] * f[2];
+            const T fDf = f[0] * Dtf[0] + f[1] * Dtf[1] + f[2] * Dtf[2];
+            const T Im1 = T(2) * fDf + Dtf[0] * Dtf[0] + Dtf[1] * Dtf[1] + Dtf[2] * Dtf[2];  // I4 - 1 (Eq. 31, 32)
+            const T Jm23m1 = -Jm1 * (c + T(1)) * dj_rcp(c * c * (c * c + c + T(1)));     // J^-2/3 - 1
+            const T Ibm1 = Jm23 * Im1 + Jm23m1;                                             // Ibar - 1
+            const T psiV = etaV * Ibm1;
+            c0 -= T(2.0 / 3.0) * psiV * (T(1) + Ibm1);
+            const T w = T(2) * Jm23 * psiV;
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int k = 0; k < 3; k++) Q[i][k] += w * (f[i] + Dtf[i]) * f[k];
+        };
+        if constexpr (MD == DJ_TI || MD == DJ_OT) fibre_term(cst + P::FIB, cst[P::ETAV]);
+        if constexpr (MD == DJ_OT) fibre_term(cst + P::FIBB, cst[P::ETABV]);
+        if constexpr (MD == DJ_MR) {
+            // C01 term: 2 C01 0V J^-4/3 (I + D^T)(I1 I - C) with C = I + G, G = D + D^T + D D^T;
+            // its identity part 4 C01 0V J^-4/3 joins c0, the rest is O(strain)
+            const T c01V = cst[P::C01V];
+            const T Jm43 = Jm23 * Jm23;
+            T G[3][3];
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int j = 0; j < 3; j++)
+                    G[i][j] = D[i][j] + D[j][i] + D[i][0] * D[j][0] + D[i][1] * D[j][1] + D[i][2] * D[j][2];
+            T trG2 = 0;
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int j = 0; j < 3; j++) trG2 += G[i][j] * G[i][j];
+            const T I2m3 = T(2) * I1m3 + T(0.5) * (I1m3 * I1m3 - trG2);  // I2 - 3 (Eq. 28)
+            const T w = T(2) * c01V * Jm43;
+#pragma unroll
+            for (int i = 0; i < 3; i++)
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    const T DtG = D[0][i] * G[0][k] + D[1][i] * G[1][k] + D[2][i] * G[2][k];
+                    Q[i][k] += w * (T(2) * D[k][i] + I1m3 * ((i == k ? T(1) : T(0)) + D[k][i]) - G[i][k] - DtG);
+                }
+            c0 -= T(4.0 / 3.0) * c01V * Jm43 * I2m3;  // p_MR 0V + 4 C01 0V J^-4/3
+            ciso += T(4) * c01V * Jm43;
+        }
+        const T pJ = (c0 - ciso) * dj_rcp(J);  // p 0V / J
+        // adj(I + D)
+        const T A00 = T(1) + D[0][0], A11 = T(1) + D[1][1], A22 = T(1) + D[2][2];
+        T adj[3][3];
+        adj[0][0] = A11 * A22 - D[1][2] * D[2][1];
+        adj[0][1] = D[0][2] * D[2][1] - D[0][1] * A22;
+        adj[0][2] = D[0][1] * D[1][2] - D[0][2] * A11;
+        adj[1][0] = D[1][2] * D[2][0] - D[1][0] * A22;
+        adj[1][1] = A00 * A22 - D[0][2] * D[2][0];
+        adj[1][2] = D[0][2] * D[1][0] - A00 * D[1][2];
+        adj[2][0] = D[1][0] * D[2][1] - A11 * D[2][0];
+        adj[2][1] = D[0][1] * D[2][0] - A00 * D[2][1];
+        adj[2][2] = A00 * A11 - D[0][1] * D[1][0];
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            Q[i][i] += c0;
+#pragma unroll
+            for (int k = 0; k < 3; k++) Q[i][k] -= pJ * (D[i][0] * adj[0][k] + D[i][1] * adj[1][k] + D[i][2] * adj[2][k]);
+        }
+        // M = Q 0J^-1  (rows: force component, columns: natural direction)
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = 0; j < 3; j++) M[i][j] = Q[i][0] * Ji[j] + Q[i][1] * Ji[3 + j] + Q[i][2] * Ji[6 + j];
+
+    }
     if constexpr (NE == 4) {
         // F = M H_xi with H_xi = [-1 1 0 0; -1 0 1 0; -1 0 0 1]: node 1 takes minus the sum
 #pragma unroll

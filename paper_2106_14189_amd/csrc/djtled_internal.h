@@ -40,8 +40,13 @@ inline int kind_of(int ne, int model) { return (ne == 8 ? 2 : 0) + (model == DJ_
 
 // Element-constant plane indices.  Each plane holds one scalar per element
 // (structure of arrays, element stride `estride`).
+// Kernel template MODEL = material model | DJ_FORM_TLED for the classical
+// TLED force (Eq. 4) instead of the Table 3 force; both read the same planes.
+constexpr int DJ_FORM_TLED = 16;
+constexpr int base_model(int model) { return model & 15; }
+
 constexpr int model_planes(int model) {  // planes of the material part, after 0J^-1, mu 0V, kappa 0V
-    return model == DJ_TI ? 4 : model == DJ_OT ? 8 : model == DJ_MR ? 1 : 0;
+    return base_model(model) == DJ_TI ? 4 : base_model(model) == DJ_OT ? 8 : base_model(model) == DJ_MR ? 1 : 0;
 }
 
 template <int NE, int MODEL>
@@ -119,7 +124,7 @@ struct StepArgs {
 
 struct Ctx {
     int device = 0;
-    int n_nodes = 0, n_elems = 0, ne = 4, model = DJ_NH, prec = DJ_FP32;
+    int n_nodes = 0, n_elems = 0, ne = 4, model = DJ_NH, prec = DJ_FP32, form = DJ_FORM_JACOBIAN;
     int variant = 0, block = 256, ept = 4, mcopy = 2, cmax = 1024, grid = 1, chunk_elems = 0;
     double dt = 0, dt_crit = 0, alpha = 0, rho = 0, hg_kappa = 0.1, mass_total = 0;
     int n_shared_copies = 0;
@@ -186,7 +191,7 @@ int make_loadset(Ctx &c, const djtled_loads *ld, const double *node_rate, LoadSe
     } while (0)
 
 // ---- kernel launchers (djtled_kernels.hip) ----
-hipError_t occupancy(int ne, int model, int prec, int variant, int *blocks_per_cu, size_t *lds_bytes);
+hipError_t occupancy(int ne, int model, int form, int prec, int variant, int *blocks_per_cu, size_t *lds_bytes);
 // per-element material arrays (device, FP64, original element order); the
 // fibre and C01 arrays are read only by the models that use them
 struct MatDev {

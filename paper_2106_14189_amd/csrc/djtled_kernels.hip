@@ -455,19 +455,24 @@ static hipError_t with_variant(int v, F &&f) {
     return hipErrorInvalidValue;
 }
 
-template <typename T, int NE, typename F>
+template <typename T, int NE, int FORM = 0, typename F>
 static hipError_t with_model(int model, int v, F &&f) {
     switch (model) {
-        case DJ_NH: return with_variant<T, NE, DJ_NH>(v, f);
-        case DJ_TI: return with_variant<T, NE, DJ_TI>(v, f);
-        case DJ_OT: return with_variant<T, NE, DJ_OT>(v, f);
-        case DJ_MR: return with_variant<T, NE, DJ_MR>(v, f);
+        case DJ_NH: return with_variant<T, NE, DJ_NH | FORM>(v, f);
+        case DJ_TI: return with_variant<T, NE, DJ_TI | FORM>(v, f);
+        case DJ_OT: return with_variant<T, NE, DJ_OT | FORM>(v, f);
+        case DJ_MR: return with_variant<T, NE, DJ_MR | FORM>(v, f);
         default: return hipErrorInvalidValue;
     }
 }
 
+// The classical TLED form is built in FP32 only (a comparison path).
 template <typename F>
-static hipError_t dispatch(int prec, int ne, int model, int v, F &&f) {
+static hipError_t dispatch(int prec, int ne, int model, int form, int v, F &&f) {
+    if (form == DJ_FORM_CLASSICAL) {
+        if (prec != DJ_FP32) return hipErrorInvalidValue;
+        return ne == 4 ? with_model<float, 4, DJ_FORM_TLED>(model, v, f) : with_model<float, 8, DJ_FORM_TLED>(model, v, f);
+    }
     if (prec == DJ_FP32) return ne == 4 ? with_model<float, 4>(model, v, f) : with_model<float, 8>(model, v, f);
     return ne == 4 ? with_model<double, 4>(model, v, f) : with_model<double, 8>(model, v, f);
 }
@@ -479,17 +484,19 @@ const std::vector<Variant> &variants(int ne, int prec) {
     return ne == 4 ? t4d : h8d;
 }
 
-hipError_t occupancy(int ne, int model, int prec, int variant, int *blocks_per_cu, size_t *lds_bytes) {
-    return dispatch(prec, ne, model, variant, [&](auto inst) { return decltype(inst)::occ(blocks_per_cu, lds_bytes); });
+hipError_t occupancy(int ne, int model, int form, int prec, int variant, int *blocks_per_cu, size_t *lds_bytes) {
+    return dispatch(prec, ne, model, form, variant,
+                    [&](auto inst) { return decltype(inst)::occ(blocks_per_cu, lds_bytes); });
 }
 
 hipError_t launch_forces(Ctx &c, const void *u, void *f, hipStream_t s) {
-    return dispatch(c.prec, c.ne, c.model, c.variant, [&](auto inst) { return decltype(inst)::forces(c, u, f, s); });
+    return dispatch(c.prec, c.ne, c.model, c.form, c.variant,
+                    [&](auto inst) { return decltype(inst)::forces(c, u, f, s); });
 }
 
 hipError_t launch_step(Ctx &c, const StepArgs &a, const void *u_cur_in, const void *u_prev_in, hipStream_t s,
                        hipEvent_t ev0, hipEvent_t ev1) {
-    return dispatch(c.prec, c.ne, c.model, c.variant,
+    return dispatch(c.prec, c.ne, c.model, c.form, c.variant,
                     [&](auto inst) { return decltype(inst)::step(c, a, u_cur_in, u_prev_in, s, ev0, ev1); });
 }
 

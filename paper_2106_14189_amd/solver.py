@@ -59,7 +59,7 @@ class Solver:
 
     def __init__(self, X, conn, E, nu, model=L.DJ_NH, rho=1000.0, eta_ratio=None, fibre=None, hg_kappa=0.1,
                  precision="fp32", dt=0.0, dt_factor=0.9, alpha=0.0, chunk_elems=0, variant=-1, device=0,
-                 allow_unstable_dt=False, eta_b_ratio=None, fibre_b=None, c01=None):
+                 allow_unstable_dt=False, eta_b_ratio=None, fibre_b=None, c01=None, formulation="jacobian"):
         torch.cuda.init()
         self.X = np.ascontiguousarray(X, dtype=np.float64)
         self.conn = np.ascontiguousarray(conn, dtype=np.int32)
@@ -90,8 +90,9 @@ class Solver:
             mat.c01 = _dptr(cc)
         self.precision = L.DJ_FP64 if precision in ("fp64", L.DJ_FP64) else L.DJ_FP32
         self.dtype = torch.float64 if self.precision == L.DJ_FP64 else torch.float32
+        form = {"jacobian": L.DJ_FORM_JACOBIAN, "classical": L.DJ_FORM_CLASSICAL}.get(formulation, formulation)
         prm = L.djtled_params(self.precision, float(dt), float(dt_factor), float(alpha), int(allow_unstable_dt),
-                              int(chunk_elems), int(variant), int(device))
+                              int(chunk_elems), int(variant), int(device), int(form))
         self.device = torch.device("cuda", device)
         h = ctypes.c_void_p()
         L.check(L.lib.djtled_precompute(ctypes.byref(mesh), ctypes.byref(mat), ctypes.byref(prm), ctypes.byref(h)),

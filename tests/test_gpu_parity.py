@@ -95,6 +95,56 @@ def test_forces_parity_ot_mr(S, elem, model, prec, variant, chunk):
     test_forces_parity(S, elem, model, prec, variant, chunk)
 
 
+@pytest.mark.parametrize("elem", [W.T4, W.H8])
+@pytest.mark.parametrize("model", [W.NH, W.TI, W.OT, W.MR])
+@pytest.mark.parametrize("variant,chunk", [(0, 0), (2, 37)])
+def test_classical_form_parity(S, elem, model, variant, chunk):
+    """Classical TLED form (Eq. 4, FP32) against the oracle's classical TLED
+    force.  It is evaluated literally, so FP32 rounding of its O(1) terms
+    leaves a relative error of about 1e-6 / strain (measured with a float32
+    emulation of the same steps): tolerance 1e-5 + 2e-6 / strain."""
+    say(f"classical elem={elem} model={model} variant={variant} chunk={chunk}")
+    mesh, E, nu, kw, rng = _case(elem, model, n=7, seed=11 + variant)
+    sv = _solver(S, mesh, E, nu, model, kw, "fp32", variant=variant, chunk_elems=chunk, formulation="classical")
+    assert sv.info()["formulation"] == 1
+    ora = _oracle(mesh, E, nu, model, kw)
+    for amp in (0.01, 0.05, 0.2):
+        u = _smooth_u(mesh, rng, amp).astype(np.float32).astype(np.float64)
+        f = sv.forces(torch.tensor(u, dtype=torch.float32, device="cuda"))
+        torch.cuda.synchronize()
+        fo = ora.forces(u, route=1)
+        err = np.abs(f.double().cpu().numpy() - fo).max() / np.abs(fo).max()
+        tol = 1e-5 + 2e-6 / amp
+        say(f"  amp={amp} rel max-norm error {err:.3e} (tol {tol:.1e})")
+        assert err <= tol
+
+
+@pytest.mark.parametrize("elem", [W.T4, W.H8])
+def test_classical_form_full_run(S, elem):
+    """The classical form steps the same dynamics: FP32 run vs the oracle's
+    (Table 3) run, <= 1e-4 after 600 steps, as for the Jacobian form."""
+    mesh, E, nu, kw, rng = _case(elem, W.NH, n=10, seed=21)
+    n_steps = 600
+    ora = _oracle(mesh, E, nu, W.NH, kw)
+    dt = 0.9 * ora.dt_crit
+    loads = W.compression_loads(mesh, -0.2, W.RAMP_SMOOTH, n_steps * dt)
+    wl = W.Workload("small", mesh, W.Material(W.NH, E, np.full(mesh.n_elems, nu)), loads, 0.9, alpha=37.0)
+    uo, _ = _run_oracle(ora, wl, n_steps, dt, wl.alpha)
+    sv = _solver(S, mesh, E, nu, W.NH, kw, "fp32", alpha=wl.alpha, formulation="classical")
+    ug, _ = _run_gpu(sv, wl, n_steps)
+    err = np.abs(ug.double().cpu().numpy() - uo).max() / np.abs(uo).max()
+    say(f"classical full run elem={elem}: rel max displacement error {err:.3e}")
+    assert err <= 1e-4
+
+
+def test_classical_form_limits(S):
+    mesh, E, nu, kw, rng = _case(W.T4, W.NH, n=3, seed=1)
+    with pytest.raises(Exception, match="classical TLED form"):
+        _solver(S, mesh, E, nu, W.NH, kw, "fp64", formulation="classical")
+    with pytest.raises(Exception, match="classical TLED form"):
+        _solver(S, mesh, E, nu, W.NH, kw, "fp32", variant=4, formulation="classical")
+
+
 @pytest.mark.parametrize("model", [W.OT, W.MR])
 def test_ot_mr_reject_three_wave_variants(S, model):
     mesh, E, nu, kw, rng = _case(W.T4, model, n=3, seed=1)

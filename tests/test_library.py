@@ -42,12 +42,12 @@ def _mesh(X, conn):
     return m, (X, conn)
 
 
-def _call_precompute(m, model=0, variant=0, precision=0, rho=1000.0):
+def _call_precompute(m, model=0, variant=0, precision=0, rho=1000.0, formulation=0):
     from paper_2106_14189_amd import _lib as L
     mat = L.djtled_material()
     mat.model = model
     mat.E_uniform, mat.nu_uniform, mat.rho = 3000.0, 0.45, rho
-    prm = L.djtled_params(precision, 0.0, 0.9, 0.0, 0, 0, variant, 0)
+    prm = L.djtled_params(precision, 0.0, 0.9, 0.0, 0, 0, variant, 0, formulation)
     h = ctypes.c_void_p()
     return L.lib.djtled_precompute(ctypes.byref(m), ctypes.byref(mat), ctypes.byref(prm), ctypes.byref(h))
 
@@ -63,6 +63,19 @@ def test_host_validation_errors():
     assert _call_precompute(m, variant=99) == L.DJ_ERR_ARG
     assert _call_precompute(m, precision=7) == L.DJ_ERR_UNSUPPORTED
     assert _call_precompute(m, rho=-1.0) == L.DJ_ERR_ARG
+    assert _call_precompute(m, variant=-2) == L.DJ_ERR_ARG
+    assert _call_precompute(m, formulation=2) == L.DJ_ERR_ARG
+    assert _call_precompute(m, formulation=L.DJ_FORM_CLASSICAL, precision=L.DJ_FP64) == L.DJ_ERR_UNSUPPORTED
+    assert "classical TLED form" in L.lib.djtled_last_error().decode()
+    assert _call_precompute(m, model=L.DJ_OT) == L.DJ_ERR_ARG  # OT needs both fibre families
+    # batches take the Jacobian form only (checked before any device call)
+    mat = L.djtled_material()
+    mat.E_uniform, mat.nu_uniform, mat.rho = 3000.0, 0.45, 1000.0
+    ld = L.djtled_loads()
+    prm = L.djtled_params(L.DJ_FP32, 0.0, 0.9, 0.0, 0, 0, 0, 0, L.DJ_FORM_CLASSICAL)
+    h = ctypes.c_void_p()
+    assert L.lib.djtled_batch_create(1, ctypes.byref(m), ctypes.byref(mat), ctypes.byref(ld), None, ctypes.byref(prm),
+                                     None, ctypes.byref(h)) == L.DJ_ERR_UNSUPPORTED
     Xn = X.copy()
     Xn[1, 0] = np.nan
     m, keep = _mesh(Xn, [[0, 1, 2, 3]])
