@@ -20,6 +20,8 @@ Further measurements, reported under "extra" (each skippable):
   * models: the config-1 cubes with each material model of Table 3 (NH,
     TI, OT, MR): time per step, overhead over NH, and the ratio to the same
     step with the classical TLED force;
+  * realtime (--realtime): step time over cube sizes and the model sizes
+    for one step per 33.3 ms / 2 ms (Sec. 5.5), checked at the 2 ms size;
   * relaxation: the ~1.2M-tet transversely isotropic ellipsoid relaxed to
     r <= 1e-3 in FP32 and finished to r <= 1e-6 in FP64;
   * warm start: surrogate trained on the GPU from relaxation steady states
@@ -188,6 +190,70 @@ def bench_models(log, steps: int = 500) -> dict:
     return out
 
 
+def bench_realtime(log) -> dict:
+    """Real-time sizing (Sec. 5.5): kernel time per explicit step of the
+    compression cube (NH, FP32, automatic variant) over a range of sizes, a
+    least-squares line t = a + b E over the sizes with E >= 1M elements, the
+    element counts at which one step takes 33.3 ms (30 Hz visual feedback) and
+    2 ms (500 Hz haptic feedback), and a measurement at the 2 ms size."""
+    import numpy as np
+    import torch
+    from paper_2106_14189_amd import solver as S
+    from paper_2106_14189_amd import workloads as W
+
+    def measure(elem, n):
+        mesh = W.cube_mesh(n, 0.1 / n, elem, jitter=0.05, seed=7, permute=True)
+        E = np.random.default_rng(n).uniform(2000.0, 6000.0, mesh.n_elems)
+        try:
+            sv = S.Solver(mesh.X, mesh.conn, E, 0.45, alpha=37.0)
+        except Exception as e:  # beyond the automatic variant's chunk list: the 512-workgroup variant
+            log(f"realtime n={n}: {e}; variant 0")
+            sv = S.Solver(mesh.X, mesh.conn, E, 0.45, alpha=37.0, variant=0)
+        info = sv.info()
+        ld = W.compression_loads(mesh, -0.2, W.RAMP_SMOOTH, 1000 * info["dt"])
+        ls = sv.loadset(ld.bc_node, ld.bc_mask, ld.bc_target, ld.ramp, ld.t_ramp)
+        u, up = sv.zeros(), sv.zeros()
+        st, step = sv.step(u, up, 20, ls)
+        est = st.kernel_ms / 20
+        k = int(min(2000, max(20, 30.0 / max(est, 1e-3))))
+        st, step = sv.step(u, up, k, ls, step0=step)
+        torch.cuda.synchronize()
+        assert st.code == 0, st
+        row = {"n": n, "elems": info["n_elems"], "nodes": info["n_nodes"], "dofs": 3 * info["n_nodes"],
+               "steps": k, "us_per_step": st.kernel_ms / k * 1e3, "variant": info["variant"]}
+        sv.close()
+        del mesh
+        log(f"realtime {'t4' if elem == W.T4 else 'h8'} {row}")
+        return row
+
+    out = {"workload": "cube_t4/h8_nh_fp32_compression_sizes"}
+    for elem, tag, sizes in ((W.T4, "t4", (8, 16, 24, 32, 48, 64, 96, 128, 160)),
+                             (W.H8, "h8", (8, 16, 32, 48, 64, 96, 128, 192, 256))):
+        rows = [measure(elem, n) for n in sizes]
+        big = [r for r in rows if r["elems"] >= 1_000_000]
+        x = np.array([r["elems"] for r in big], float)
+        y = np.array([r["us_per_step"] for r in big]) * 1e-6
+        b, a = np.polyfit(x, y, 1)
+        pred = {hz: (1.0 / hz - a) / b for hz in (30, 500)}
+        # measured point past the fitted 500 Hz size; the 500 Hz size is then
+        # interpolated between measured points, and the 30 Hz size (beyond this
+        # host-side mesh generator) extrapolated with the slope of the two largest
+        per = 6 if elem == W.T4 else 1
+        n500 = int(round((pred[500] / per) ** (1.0 / 3.0)))
+        check = measure(elem, n500)
+        pts = sorted(rows + [check], key=lambda r: r["elems"])
+        ex = np.array([r["elems"] for r in pts], float)
+        ey = np.array([r["us_per_step"] for r in pts]) * 1e-6
+        e500 = float(np.interp(2e-3, ey, ex)) if ey[-1] >= 2e-3 else None
+        slope = (ey[-1] - ey[-2]) / (ex[-1] - ex[-2])
+        e30 = float(ex[-1] + (1.0 / 30 - ey[-1]) / slope)
+        out[tag] = {"sizes": rows, "fit_s_per_step": {"a": a, "b_per_element": b},
+                    "fit_elements_at_30Hz": pred[30], "fit_elements_at_500Hz": pred[500], "check": check,
+                    "elements_at_500Hz_measured": e500, "elements_at_30Hz_extrapolated": e30,
+                    "min_us_per_step": min(r["us_per_step"] for r in rows)}
+    return out
+
+
 def bench_relaxation(log) -> dict:
     """Config 2: FP32 relaxation to 1e-3 (above its rounding floor), FP64 finish to 1e-6."""
     import torch
@@ -304,6 +370,8 @@ def main():
     ap.add_argument("--no-relax", action="store_true", help="skip the ellipsoid relaxation measurement")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start measurement")
     ap.add_argument("--no-mlp", action="store_true", help="skip the full-size network timing")
+    ap.add_argument("--realtime", action="store_true",
+                    help="also measure step time over cube sizes up to ~60M elements (real-time sizing)")
     ap.add_argument("--warm-full", action="store_true",
                     help="also run the warm-start pipeline on the full ellipsoid (several GPU-minutes)")
     args = ap.parse_args()
@@ -406,6 +474,7 @@ def main():
     extra = {}
     for name, skip, fn in (("batch", args.no_batch, lambda lg: bench_batch(lg, args.batch_variant)),
                            ("models", args.no_models, bench_models),
+                           ("realtime", not args.realtime, bench_realtime),
                            ("relaxation", args.no_relax, bench_relaxation),
                            ("mlp", args.no_mlp, bench_mlp), ("warm_start", args.no_warm, bench_warm_start),
                            ("warm_start_full", not args.warm_full, bench_warm_start_full)):

@@ -241,8 +241,9 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     if (nch > E) nch = E;
     c.chunk_elems = int((E + nch - 1) / nch);
     c.grid = int(std::min<int64_t>(nch, gmax));
-    if (!in_batch && (nch + c.grid - 1) / c.grid > 32)
-        return fail(DJ_ERR_UNSUPPORTED, "mesh needs more than 32 chunks per workgroup; use a larger variant");
+    if (!in_batch && (nch + c.grid - 1) / c.grid > KMAX)
+        return fail(DJ_ERR_UNSUPPORTED, "mesh needs more than " + std::to_string(KMAX) +
+                                            " chunks per workgroup; use a variant with more workgroups");
     chunks.assign(nch, ChunkDesc{});
     crange.clear();
     wpos.assign(size_t(NE) * estride, 0);

@@ -29,6 +29,10 @@ enum : uint32_t {
 // chunk's (element, node) incidences are numbered in node-copy order; copy l
 // owns the contiguous positions crange[l], and wpos[a][e] is the position of
 // node a of element e.
+// chunks per workgroup of the single-context step kernel (its LDS list:
+// 4 KB, which still lets three 1024-element FP32 chunks share a CU)
+constexpr int KMAX = 128;
+
 struct ChunkDesc {
     int32_t elem_begin, elem_count, copy_begin, copy_count;
     int32_t n_interior, tag, pad1, pad2;  // tag: element kind (batches)

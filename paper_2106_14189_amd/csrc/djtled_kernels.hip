@@ -26,7 +26,6 @@ __global__ void __launch_bounds__(BLOCK) k_forces_shared(DevTopo tp, StepPtrs<T>
 // chunk -> grid barrier -> shared-node phase}, one barrier per step (plus one
 // on residual-check steps).  All workgroups take every decision from values
 // published before a common barrier, so they leave the loop together.
-constexpr int KMAX = 32;  // chunks per workgroup
 
 template <typename T, int NE, int MODEL, int BLOCK, int EPT, int MC, int WPE>
 __global__ void __launch_bounds__(BLOCK, WPE) k_step(DevTopo tp, StepArgs a) {
