@@ -20,6 +20,8 @@ Further measurements, reported under "extra" (each skippable):
   * models: the config-1 cubes with each material model of Table 3 (NH,
     TI, OT, MR): time per step, overhead over NH, and the ratio to the same
     step with the classical TLED force;
+  * multi: k = 1, 2, 4, 8 compression cases per launch on the config-1
+    cubes (djtled_step_multi): time per step and element-steps/s over cases;
   * realtime (--realtime): step time over cube sizes and the model sizes
     for one step per 33.3 ms / 2 ms (Sec. 5.5), checked at the 2 ms size;
   * relaxation: the ~1.2M-tet transversely isotropic ellipsoid relaxed to
@@ -254,6 +256,42 @@ def bench_realtime(log) -> dict:
     return out
 
 
+def bench_multi(log, steps: int = 300) -> dict:
+    """Several load cases per launch (djtled_step_multi) on the config-1 cubes
+    (automatic kernel variant): k compression cases of different strain share
+    each step's grid barrier; kernel time per step and element-steps/s
+    counting every case (k = 1: the single-case kernel)."""
+    import torch
+    from paper_2106_14189_amd import solver as S
+    from paper_2106_14189_amd import workloads as W
+    out = {"workload": "cube64_t4+h8_nh_fp32_compression_k_cases", "steps": steps}
+    for elem in (W.T4, W.H8):
+        wl = W.config1(elem)
+        tag = "t4" if elem == W.T4 else "h8"
+        sv = S.from_workload(wl)
+        info = sv.info()
+        per = {}
+        for k in (1, 2, 4, 8):
+            lss = []
+            for i in range(k):
+                ld = W.compression_loads(wl.mesh, -0.2 + 0.01 * i, W.RAMP_SMOOTH, 1000 * info["dt"])
+                lss.append(sv.loadset(ld.bc_node, ld.bc_mask, ld.bc_target, ld.ramp, ld.t_ramp))
+            U, UP = sv.zeros_multi(k), sv.zeros_multi(k)
+            st, step, _, _ = sv.step_multi(U, UP, 20, lss)
+            st, step, _, _ = sv.step_multi(U, UP, steps, lss, step0=step)
+            torch.cuda.synchronize()
+            assert st.code == 0 and st.steps_done == steps, st
+            us = st.kernel_ms / steps * 1e3
+            per[k] = us
+            out[f"{tag}_k{k}_kernel_us_per_step"] = us
+            out[f"{tag}_k{k}_element_steps_per_s"] = k * info["n_elems"] / (us * 1e-6)
+            for ls in lss:
+                ls.close()
+        log(f"multi {tag}: " + ", ".join(f"k={k} {v:.1f} us ({v / k:.1f} per case)" for k, v in per.items()))
+        sv.close()
+    return out
+
+
 def bench_relaxation(log) -> dict:
     """Config 2: FP32 relaxation to 1e-3 (above its rounding floor), FP64 finish to 1e-6."""
     import torch
@@ -367,6 +405,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-instance batch measurement")
     ap.add_argument("--batch-variant", type=int, default=-1, help="batch kernel variant (-1: autotune)")
     ap.add_argument("--no-models", action="store_true", help="skip the four-material-model measurement")
+    ap.add_argument("--no-multi", action="store_true", help="skip the several-load-cases measurement")
     ap.add_argument("--no-relax", action="store_true", help="skip the ellipsoid relaxation measurement")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start measurement")
     ap.add_argument("--no-mlp", action="store_true", help="skip the full-size network timing")
@@ -474,6 +513,7 @@ def main():
     extra = {}
     for name, skip, fn in (("batch", args.no_batch, lambda lg: bench_batch(lg, args.batch_variant)),
                            ("models", args.no_models, bench_models),
+                           ("multi", args.no_multi, bench_multi),
                            ("realtime", not args.realtime, bench_realtime),
                            ("relaxation", args.no_relax, bench_relaxation),
                            ("mlp", args.no_mlp, bench_mlp), ("warm_start", args.no_warm, bench_warm_start),

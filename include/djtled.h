@@ -200,6 +200,29 @@ int djtled_step(djtled_ctx *ctx, djtled_state *state, const djtled_loadset *load
                 const djtled_step_opts *opts, djtled_status *out, void *stream);
 
 /*
+ * djtled_step_multi -- djtled_step for nrhs (1..8) load cases of the same
+ * mesh, material and time step in one persistent launch (Eq. 13 for each
+ * case): per step the element phase of every case, one grid barrier for all
+ * of them, then their shared-node phases.  Each case has its own state,
+ * boundary values and node sums, and its result equals a separate
+ * djtled_step call bit for bit.
+ *   state: u_cur and u_prev each hold nrhs consecutive n_nodes x 3 arrays
+ *          (device); one step counter for all cases;
+ *   loads: nrhs load sets of this context sharing the ramp kind and
+ *          duration, or NULL (no loads for any case).
+ * RELAX: the run stops when every case's residual is <= tol.  out->residual
+ * is the largest of the cases' last residuals; residuals (nrhs doubles, host,
+ * may be NULL) receives each.  An error in any case stops every case at the
+ * same step; *error_case (may be NULL) names the case, else -1.
+ * Built for FP32 contexts with the Jacobian form and variants 0..3 (nrhs > 1).
+ * Errors: as djtled_step; DJ_ERR_ARG for nrhs out of range, missing or
+ * mismatched load sets; DJ_ERR_UNSUPPORTED for other contexts.
+ */
+int djtled_step_multi(djtled_ctx *ctx, int32_t nrhs, djtled_state *state, const djtled_loadset *const *loads,
+                      int32_t n_steps, const djtled_step_opts *opts, djtled_status *out, double *residuals,
+                      int32_t *error_case, void *stream);
+
+/*
  * djtled_export_constants -- copies per-element constants to host memory in
  * caller element order, in FP64: V[n_elems], dhdX[n_elems x 3 x elem_type]
  * (row i = d h_a / d X_i, Eq. 6), and the lumped masses mass[n_nodes] in

@@ -121,6 +121,9 @@ EXPORTS = {
     "djtled_loadset_destroy": (ctypes.c_int, [_vp]),
     "djtled_step": (ctypes.c_int, [_vp, ctypes.POINTER(djtled_state), _vp, ctypes.c_int32,
                                    ctypes.POINTER(djtled_step_opts), ctypes.POINTER(djtled_status), _vp]),
+    "djtled_step_multi": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(djtled_state), ctypes.POINTER(_vp),
+                                         ctypes.c_int32, ctypes.POINTER(djtled_step_opts),
+                                         ctypes.POINTER(djtled_status), _dp, ctypes.POINTER(ctypes.c_int32), _vp]),
     "djtled_export_constants": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
     "djtled_last_error": (ctypes.c_char_p, []),
     "djtled_batch_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(djtled_mesh), ctypes.POINTER(djtled_material),

@@ -65,6 +65,11 @@ void free_all(Ctx *c) {
         delete ls;
     }
     for (void *p : c->allocs) hipFree(p);
+    for (int b = 0; b < 3; b++) hipFree(c->d_mubuf[b]);
+    hipFree(c->d_mpart);
+    hipFree(c->d_mred);
+    hipFree(c->d_mflags);
+    hipFree(c->d_mru);
     if (c->ev0) hipEventDestroy(c->ev0);
     if (c->ev1) hipEventDestroy(c->ev1);
     if (c->h_status) hipHostFree(c->h_status);
@@ -588,6 +593,150 @@ int make_loadset(Ctx &c, const djtled_loads *ld, const double *node_rate, LoadSe
 
 }  // namespace dj
 
+namespace dj {
+
+// n_steps explicit steps of nrhs load cases (one persistent launch); see
+// djtled_step and djtled_step_multi.  st->u_cur / u_prev: nrhs x n_nodes x 3.
+int step_cases(djtled_ctx *ctx, int nrhs, djtled_state *st, const djtled_loadset *const *lsp, int32_t n_steps,
+               const djtled_step_opts *opts, djtled_status *out, double *residuals, int32_t *error_case,
+               void *stream) {
+    if (!ctx || !st || !st->u_cur || !st->u_prev) return fail(DJ_ERR_ARG, "null argument");
+    if (nrhs < 1 || nrhs > MAX_RHS) return fail(DJ_ERR_ARG, "nrhs must be 1.." + std::to_string(MAX_RHS));
+    if (n_steps < 0) return fail(DJ_ERR_ARG, "n_steps must be >= 0");
+    if (st->u_cur == st->u_prev) return fail(DJ_ERR_ARG, "u_cur and u_prev must be distinct arrays");
+    Ctx &c = *reinterpret_cast<Ctx *>(ctx);
+    if (c.n_inst > 1) return fail(DJ_ERR_ARG, "batch contexts step through djtled_batch_run");
+    if (nrhs > 1 && (c.prec != DJ_FP32 || c.form != DJ_FORM_JACOBIAN || c.variant >= 4))
+        return fail(DJ_ERR_UNSUPPORTED, "several load cases per launch: FP32, Jacobian form, variants 0..3");
+    // load sets: all absent, or one per case with a common ramp
+    const bool has_loads = lsp && lsp[0];
+    for (int r = 0; r < nrhs; r++) {
+        const LoadSet *ls = lsp ? reinterpret_cast<const LoadSet *>(lsp[r]) : nullptr;
+        if (bool(ls) != has_loads) return fail(DJ_ERR_ARG, "give a load set for every case or for none");
+        if (!ls) continue;
+        if (ls->ctx != &c) return fail(DJ_ERR_ARG, "load set belongs to another context");
+        const LoadSet *l0 = reinterpret_cast<const LoadSet *>(lsp[0]);
+        if (ls->ramp != l0->ramp || ls->t_ramp != l0->t_ramp)
+            return fail(DJ_ERR_ARG, "the load cases of one call must share the ramp kind and duration");
+    }
+    djtled_step_opts def{DJ_MODE_FIXED, 0.0, 1};
+    const djtled_step_opts &o = opts ? *opts : def;
+    if (o.mode != DJ_MODE_FIXED && o.mode != DJ_MODE_RELAX) return fail(DJ_ERR_ARG, "bad mode");
+    if (o.mode == DJ_MODE_RELAX && o.check_every < 1) return fail(DJ_ERR_ARG, "check_every must be >= 1");
+    DJ_HIP(hipSetDevice(c.device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t ts = c.prec == DJ_FP32 ? sizeof(float) : sizeof(double);
+    const size_t L = size_t(c.topo.n_copies);
+    if (nrhs > 1) {  // the several-cases kernel's grid must be co-resident like the single-case one's
+        int bpc = 0, ncu = 0;
+        DJ_HIP(occupancy_multi(c, &bpc));
+        DJ_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c.device));
+        if (int64_t(bpc) * ncu < c.grid)
+            return fail(DJ_ERR_UNSUPPORTED, "the several-cases kernel does not fit this context's grid");
+    }
+    StepArgs a;
+    a.nrhs = nrhs;
+    const LoadSet *l0 = has_loads ? reinterpret_cast<const LoadSet *>(lsp[0]) : nullptr;
+    a.ramp = l0 ? l0->ramp : DJ_RAMP_NONE;
+    a.t_ramp = l0 ? l0->t_ramp : 0.0;
+    if (nrhs == 1) {
+        for (int b = 0; b < 3; b++) a.ubuf[b] = c.d_ubuf[b];
+        a.part = c.d_part;
+        a.red = c.d_red;
+        a.res_out = c.d_red + size_t(4) * c.grid;
+        a.flags = l0 ? l0->d_flags : c.topo.flags;
+        a.ru = l0 ? l0->d_ru : nullptr;
+    } else {
+        if (c.rhs_cap < nrhs) {  // grow the case buffers (no launch of this context is in flight)
+            DJ_HIP(hipStreamSynchronize(s));
+            for (int b = 0; b < 3; b++) {
+                hipFree(c.d_mubuf[b]);
+                c.d_mubuf[b] = nullptr;
+            }
+            hipFree(c.d_mpart);
+            hipFree(c.d_mred);
+            hipFree(c.d_mflags);
+            hipFree(c.d_mru);
+            c.d_mpart = c.d_mru = nullptr;
+            c.d_mred = nullptr;
+            c.d_mflags = nullptr;
+            c.rhs_cap = 0;
+            const size_t NP = size_t(std::max<int64_t>(c.topo.n_part, 1));
+            for (int b = 0; b < 3; b++) DJ_HIP(hipMalloc(&c.d_mubuf[b], size_t(nrhs) * 3 * L * ts));
+            DJ_HIP(hipMalloc(&c.d_mpart, size_t(nrhs) * 6 * NP * ts));
+            DJ_HIP(hipMalloc(reinterpret_cast<void **>(&c.d_mred), (size_t(4) * c.grid + 1) * nrhs * sizeof(double)));
+            DJ_HIP(hipMalloc(reinterpret_cast<void **>(&c.d_mflags), size_t(nrhs) * L * sizeof(uint32_t)));
+            DJ_HIP(hipMalloc(&c.d_mru, size_t(nrhs) * 3 * L * ts));
+            c.rhs_cap = nrhs;
+        }
+        for (int b = 0; b < 3; b++) a.ubuf[b] = c.d_mubuf[b];
+        a.part = c.d_mpart;
+        a.red = c.d_mred;
+        a.res_out = c.d_mred + size_t(4) * c.grid * nrhs;
+        // gather the cases' flags and load values into consecutive planes
+        for (int r = 0; r < nrhs; r++) {
+            const LoadSet *ls = has_loads ? reinterpret_cast<const LoadSet *>(lsp[r]) : nullptr;
+            DJ_HIP(hipMemcpyAsync(c.d_mflags + r * L, ls ? ls->d_flags : c.topo.flags, L * sizeof(uint32_t),
+                                  hipMemcpyDeviceToDevice, s));
+            // (a load set without load values flags no copy for them: its planes are never read)
+            if (has_loads && ls->d_ru)
+                DJ_HIP(hipMemcpyAsync(static_cast<char *>(c.d_mru) + r * 3 * L * ts, ls->d_ru, 3 * L * ts,
+                                      hipMemcpyDeviceToDevice, s));
+        }
+        a.flags = c.d_mflags;
+        a.ru = has_loads ? c.d_mru : nullptr;
+    }
+    a.u_out_cur = st->u_cur;
+    a.u_out_prev = st->u_prev;
+    a.out_stride = int64_t(3) * c.n_nodes;
+    a.dt = c.dt;
+    a.bprime = (2.0 - c.alpha * c.dt) / (2.0 + c.alpha * c.dt);
+    a.step0 = st->step;
+    a.n_steps = n_steps;
+    a.relax = o.mode == DJ_MODE_RELAX;
+    a.tol = o.tol;
+    a.check_every = std::max(1, o.check_every);
+    a.cur0 = 0;
+    a.bar = c.d_bar;
+    a.status = c.d_status;
+    const double nan = std::numeric_limits<double>::quiet_NaN();
+    std::vector<double> hres(nrhs, nan);
+    DJ_HIP(hipMemcpyAsync(a.res_out, hres.data(), nrhs * sizeof(double), hipMemcpyHostToDevice, s));
+    DJ_HIP(launch_step(c, a, st->u_cur, st->u_prev, s, c.ev0, c.ev1));
+    DJ_HIP(hipMemcpyAsync(c.h_status, c.d_status, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    DJ_HIP(hipMemcpyAsync(hres.data(), a.res_out, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    DJ_HIP(hipStreamSynchronize(s));
+    djtled_status r;
+    r.code = c.h_status[4] ? DJ_ERR_BARRIER : c.h_status[0];
+    r.steps_done = c.h_status[1];
+    r.error_step = -1;
+    r.error_elem = -1;
+    r.residual = hres[0];
+    for (int q = 1; q < nrhs; q++)  // the largest (NaN if any is)
+        if (!(r.residual >= hres[q])) r.residual = hres[q];
+    float ms = 0.0f;
+    r.kernel_ms = hipEventElapsedTime(&ms, c.ev0, c.ev1) == hipSuccess ? double(ms) : -1.0;
+    if (error_case) *error_case = -1;
+    if (r.code == DJ_ERR_BARRIER) {
+        r.steps_done = 0;
+        g_err = "persistent kernel grid barrier timed out";
+    } else if (r.code == DJ_ERR_INVERTED || r.code == DJ_ERR_NONFINITE) {
+        r.error_step = st->step + c.h_status[3];
+        const int ie = c.h_status[2];
+        r.error_elem = (ie >= 0 && ie < c.n_elems) ? c.elem_perm[ie] : -1;
+        if (error_case) *error_case = c.h_status[7];
+        g_err = (r.code == DJ_ERR_INVERTED ? "element inverted (J <= 0) at step " : "non-finite value at step ") +
+                std::to_string(r.error_step) + (nrhs > 1 ? " in load case " + std::to_string(c.h_status[7]) : "");
+    }
+    st->step += r.steps_done;
+    if (residuals)
+        for (int q = 0; q < nrhs; q++) residuals[q] = hres[q];
+    if (out) *out = r;
+    return r.code;
+}
+
+}  // namespace dj
+
 extern "C" {
 
 const char *djtled_last_error(void) { return g_err.c_str(); }
@@ -710,66 +859,13 @@ int djtled_loadset_destroy(djtled_loadset *p) {
 
 int djtled_step(djtled_ctx *ctx, djtled_state *st, const djtled_loadset *lsp, int32_t n_steps,
                 const djtled_step_opts *opts, djtled_status *out, void *stream) {
-    if (!ctx || !st || !st->u_cur || !st->u_prev) return fail(DJ_ERR_ARG, "null argument");
-    if (n_steps < 0) return fail(DJ_ERR_ARG, "n_steps must be >= 0");
-    Ctx &c = *reinterpret_cast<Ctx *>(ctx);
-    const LoadSet *ls = reinterpret_cast<const LoadSet *>(lsp);
-    if (ls && ls->ctx != &c) return fail(DJ_ERR_ARG, "load set belongs to another context");
-    djtled_step_opts def{DJ_MODE_FIXED, 0.0, 1};
-    const djtled_step_opts &o = opts ? *opts : def;
-    if (o.mode != DJ_MODE_FIXED && o.mode != DJ_MODE_RELAX) return fail(DJ_ERR_ARG, "bad mode");
-    if (o.mode == DJ_MODE_RELAX && o.check_every < 1) return fail(DJ_ERR_ARG, "check_every must be >= 1");
-    DJ_HIP(hipSetDevice(c.device));
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    StepArgs a;
-    a.flags = ls ? ls->d_flags : c.topo.flags;
-    a.ru = ls ? ls->d_ru : nullptr;
-    a.has_loads = ls ? 1 : 0;
-    a.ramp = ls ? ls->ramp : DJ_RAMP_NONE;
-    a.t_ramp = ls ? ls->t_ramp : 0.0;
-    a.dt = c.dt;
-    a.bprime = (2.0 - c.alpha * c.dt) / (2.0 + c.alpha * c.dt);
-    a.step0 = st->step;
-    a.n_steps = n_steps;
-    a.relax = o.mode == DJ_MODE_RELAX;
-    a.tol = o.tol;
-    a.check_every = std::max(1, o.check_every);
-    a.cur0 = 0;
-    for (int b = 0; b < 3; b++) a.ubuf[b] = c.d_ubuf[b];
-    a.part = c.d_part;
-    a.u_out_cur = st->u_cur;
-    a.u_out_prev = st->u_prev;
-    a.bar = c.d_bar;
-    a.status = c.d_status;
-    a.red = c.d_red;
-    a.res_out = c.d_red + size_t(4) * c.grid;
-    const double nan = std::numeric_limits<double>::quiet_NaN();
-    DJ_HIP(hipMemcpyAsync(a.res_out, &nan, sizeof(double), hipMemcpyHostToDevice, s));
-    DJ_HIP(launch_step(c, a, st->u_cur, st->u_prev, s, c.ev0, c.ev1));
-    DJ_HIP(hipMemcpyAsync(c.h_status, c.d_status, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    DJ_HIP(hipMemcpyAsync(c.h_res, a.res_out, sizeof(double), hipMemcpyDeviceToHost, s));
-    DJ_HIP(hipStreamSynchronize(s));
-    djtled_status r;
-    r.code = c.h_status[4] ? DJ_ERR_BARRIER : c.h_status[0];
-    r.steps_done = c.h_status[1];
-    r.error_step = -1;
-    r.error_elem = -1;
-    r.residual = *c.h_res;
-    float ms = 0.0f;
-    r.kernel_ms = hipEventElapsedTime(&ms, c.ev0, c.ev1) == hipSuccess ? double(ms) : -1.0;
-    if (r.code == DJ_ERR_BARRIER) {
-        r.steps_done = 0;
-        g_err = "persistent kernel grid barrier timed out";
-    } else if (r.code == DJ_ERR_INVERTED || r.code == DJ_ERR_NONFINITE) {
-        r.error_step = st->step + c.h_status[3];
-        const int ie = c.h_status[2];
-        r.error_elem = (ie >= 0 && ie < c.n_elems) ? c.elem_perm[ie] : -1;
-        g_err = (r.code == DJ_ERR_INVERTED ? "element inverted (J <= 0) at step " : "non-finite value at step ") +
-                std::to_string(r.error_step);
-    }
-    st->step += r.steps_done;
-    if (out) *out = r;
-    return r.code;
+    return step_cases(ctx, 1, st, &lsp, n_steps, opts, out, nullptr, nullptr, stream);
+}
+
+int djtled_step_multi(djtled_ctx *ctx, int32_t nrhs, djtled_state *state, const djtled_loadset *const *loads,
+                      int32_t n_steps, const djtled_step_opts *opts, djtled_status *out, double *residuals,
+                      int32_t *error_case, void *stream) {
+    return step_cases(ctx, nrhs, state, loads, n_steps, opts, out, residuals, error_case, stream);
 }
 
 int djtled_export_constants(djtled_ctx *ctx, double *V, double *dhdX, double *mass) {

@@ -101,11 +101,14 @@ struct DevTopo {
     const void *bpc = nullptr;           // batches: per copy B' = (2 - alpha dt) / (2 + alpha dt)
 };
 
+// load cases stepped together by one launch (multi-RHS)
+constexpr int MAX_RHS = 8;
+
 struct StepArgs {
-    const uint32_t *flags = nullptr;  // per copy: topology flags | load bits
-    const void *ru = nullptr;   // loads: 3 planes over copies (BC target or R), or null
-    int32_t has_loads = 0;
-    int32_t ramp = DJ_RAMP_NONE;
+    int32_t nrhs = 1;           // load cases; case r's planes follow those of case r - 1 in every array below
+    const uint32_t *flags = nullptr;  // nrhs x copies: topology flags | load bits
+    const void *ru = nullptr;   // nrhs x 3 planes over copies (BC target or R), or null (no loads)
+    int32_t ramp = DJ_RAMP_NONE;  // common to the cases
     double t_ramp = 0.0;
     double dt = 0.0;
     double bprime = 0.0;        // (2 - alpha dt) / (2 + alpha dt)
@@ -115,15 +118,16 @@ struct StepArgs {
     double tol = 0.0;
     int32_t check_every = 1;
     int32_t cur0 = 0;           // buffer index of u^n at entry (prev = cur0 + 2 mod 3)
-    void *ubuf[3] = {nullptr, nullptr, nullptr};  // each: 3 planes over copies
-    void *part = nullptr;       // partial forces: 2 parities x 3 planes over n_part entries
-    void *u_out_cur = nullptr;  // caller arrays written at the end
+    void *ubuf[3] = {nullptr, nullptr, nullptr};  // each: nrhs x 3 planes over copies
+    void *part = nullptr;       // partial forces: nrhs x 2 parities x 3 planes over n_part entries
+    void *u_out_cur = nullptr;  // caller arrays written at the end: nrhs x n_nodes x 3 each
     void *u_out_prev = nullptr;
+    int64_t out_stride = 0;     // 3 n_nodes
     uint32_t *bar = nullptr;    // barrier flags: (grid + 16) x 32 uint32
     int32_t *status = nullptr;  // [0] code [1] steps done [2] error element (internal) [3] error step offset
-                                // [4] barrier abort [5..6] per-parity error words
-    double *red = nullptr;      // residual partials: 2 parities x grid x 2
-    double *res_out = nullptr;  // last residual
+                                // [4] barrier abort [5..6] per-parity error words [7] case of the error
+    double *red = nullptr;      // residual partials: 2 parities x grid x nrhs x 2
+    double *res_out = nullptr;  // last residual per case
 };
 
 struct Ctx {
@@ -144,6 +148,13 @@ struct Ctx {
     uint32_t *d_bar = nullptr;
     int32_t *d_status = nullptr;
     double *d_red = nullptr;
+    // several load cases per launch: buffers grown on demand (case capacity rhs_cap)
+    int rhs_cap = 0;
+    void *d_mubuf[3] = {nullptr, nullptr, nullptr};
+    void *d_mpart = nullptr;
+    double *d_mred = nullptr;
+    uint32_t *d_mflags = nullptr;   // rhs_cap x copies
+    void *d_mru = nullptr;          // rhs_cap x 3 planes over copies
     double *d_V64 = nullptr, *d_jinv64 = nullptr, *d_mass64 = nullptr;
     int32_t *d_elem_perm = nullptr, *d_node_perm = nullptr, *d_inode = nullptr;
     int32_t *h_status = nullptr;     // pinned
@@ -196,6 +207,7 @@ int make_loadset(Ctx &c, const djtled_loads *ld, const double *node_rate, LoadSe
 
 // ---- kernel launchers (djtled_kernels.hip) ----
 hipError_t occupancy(int ne, int model, int form, int prec, int variant, int *blocks_per_cu, size_t *lds_bytes);
+hipError_t occupancy_multi(const Ctx &c, int *blocks_per_cu);  // several-cases kernel; 0 if not built
 // per-element material arrays (device, FP64, original element order); the
 // fibre and C01 arrays are read only by the models that use them
 struct MatDev {

@@ -180,6 +180,225 @@ __global__ void __launch_bounds__(BLOCK, WPE) k_step(DevTopo tp, StepArgs a) {
     }
 }
 
+// The same step for a.nrhs load cases per launch (djtled_step_multi): per
+// step, the element phase of every case, one grid barrier, the shared phase
+// of every case.  A separate kernel: the case loops, even with one case,
+// measured 3-13 % slower than k_step.  The element data is reloaded per case:
+// holding it in registers across the cases of a chunk overflowed the budget
+// of two waves per SIMD, and staging it in LDS by direct loads measured
+// 15-25 % slower per case.
+template <typename T, int NE, int MODEL, int BLOCK, int EPT, int MC, int WPE>
+__global__ void __launch_bounds__(BLOCK, WPE) k_step_multi(DevTopo tp, StepArgs a) {
+    using C = Chunk<T, NE, MODEL, BLOCK, EPT, MC>;
+    constexpr int KB = 4;  // chunks per shared-phase batch
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double sred[2 * (BLOCK / 64)];
+    __shared__ double s_res[2 * MAX_RHS];  // this workgroup's residual sums per load case (R > 1)
+    __shared__ int s_flag;
+    __shared__ ChunkDesc s_ch[KMAX];
+    const int64_t L = tp.n_copies;
+    const int64_t NPART = tp.n_part;
+    const uint32_t G = gridDim.x;
+    const int R = a.nrhs;
+    const int nmine = int(blockIdx.x) < tp.n_chunks ? (tp.n_chunks - int(blockIdx.x) + int(G) - 1) / int(G) : 0;
+    for (int k = threadIdx.x; k < nmine; k += BLOCK) s_ch[k] = tp.chunks[blockIdx.x + k * G];
+    __syncthreads();
+    uint32_t epoch = 0;  // the flags are cleared before every launch
+    T *const ub0 = static_cast<T *>(a.ubuf[0]), *const ub1 = static_cast<T *>(a.ubuf[1]),
+            *const ub2 = static_cast<T *>(a.ubuf[2]);
+    auto ub = [&](int i) { return i == 0 ? ub0 : (i == 1 ? ub1 : ub2); };  // no runtime-indexed array
+    T *part = static_cast<T *>(a.part);
+    int cur = a.cur0;
+    int done = 0;
+    int code = DJ_OK;
+    int s = 0;
+    for (s = 0; s < a.n_steps; s++) {
+        const int nxt = (cur + 1) % 3, prv = (cur + 2) % 3;
+        const int64_t n = a.step0 + s;
+        bool check = a.relax && (s % a.check_every) == 0;
+        check = check && ramp_value(a.ramp, double(n) * a.dt, a.t_ramp) >= 1.0;
+        const T sval = T(ramp_value(a.ramp, double(n + 1) * a.dt, a.t_ramp));
+        // pointers of load case r: its u planes and partials follow those of r - 1
+        auto make_sp = [&](int r) {
+            StepPtrs<T> sp;
+            const int64_t uo = int64_t(r) * 3 * L;
+            const T *ru = a.ru ? static_cast<const T *>(a.ru) + uo : nullptr;
+            for (int k = 0; k < 3; k++) {
+                sp.uc[k] = ub(cur) + uo + k * L;
+                sp.up[k] = ub(prv) + uo + k * L;
+                sp.un[k] = ub(nxt) + uo + k * L;
+                sp.ru[k] = ru ? ru + k * L : nullptr;
+                sp.pp[k] = part + ((int64_t(r) * 2 + (s & 1)) * 3 + k) * NPART;
+            }
+            sp.flags = a.flags + int64_t(r) * L;
+            sp.acoef = static_cast<const T *>(tp.acoef);
+            sp.bprime = T(a.bprime);
+            sp.sval = sval;
+            sp.want_res = check;
+            sp.fout = nullptr;
+            sp.bpc = nullptr;
+            sp.rrate = nullptr;
+            sp.n1 = T(n + 1);
+            return sp;
+        };
+        PhaseOut po{0.0, 0.0, 0, -1};
+        int bad_rhs = -1;
+        if (check && R > 1 && threadIdx.x < 2 * R) s_res[threadIdx.x] = 0.0;
+        // with several load cases, each case's residual sums are reduced after
+        // its part of a chunk (one case: once per step, below)
+        auto after_case = [&](int r) {
+            if (po.bad && bad_rhs < 0) bad_rhs = r;
+            if (check && R > 1) {
+                double x = po.num, y = po.den;
+                block_sum2<BLOCK>(x, y, sred);
+                if (threadIdx.x == 0) {
+                    s_res[2 * r] += x;
+                    s_res[2 * r + 1] += y;
+                }
+                po.num = po.den = 0.0;
+            }
+        };
+        // Element phase, case by case (the cases share the step's grid barrier).
+        // The copy data of the next chunk is loaded while the current one is
+        // summed and updated; the element data of a chunk is in flight during
+        // its scatter.  (Element data loaded one chunk ahead, across the step
+        // boundary, or held in registers for all cases of a chunk measured
+        // slower or overflowed the register budget of two waves per SIMD.)
+        // Variants built for three waves per SIMD keep the plain order.
+        if constexpr (WPE >= 3) {
+            for (int r = 0; r < R; r++) {
+                const StepPtrs<T> sp = make_sp(r);
+                for (int k = 0; k < nmine; k++) C::template element_phase<1>(tp, s_ch[k], sp, smem, po);
+                after_case(r);
+            }
+        } else {
+            typename C::CopyRegs cp;
+            if (nmine > 0) C::template load_copies<1>(tp, s_ch[0], make_sp(0), cp);
+            for (int r = 0; r < R; r++) {
+                const StepPtrs<T> sp = make_sp(r);
+                for (int k = 0; k < nmine; k++) {
+                    typename C::ElemRegs er;
+                    C::load_elems(tp, s_ch[k], er);
+                    C::template process<1, true>(tp, s_ch[k], sp, smem, po, er, cp, [&]() {
+                        if (k + 1 < nmine) C::template load_copies<1>(tp, s_ch[k + 1], sp, cp);
+                        else if (r + 1 < R) C::template load_copies<1>(tp, s_ch[0], make_sp(r + 1), cp);
+                    });
+                }
+                after_case(r);
+            }
+        }
+        // round A of the first batch of shared copies (case 0), in flight during the barrier
+        SharedRegs<T, KB> sr;
+        C::template shared_load<1, KB>(tp, s_ch, min(KB, nmine), 0, make_sp(0), sr);
+        // Errors of step s go to the error word of parity s & 1, which nobody
+        // writes again before every workgroup has read it after this barrier.
+        int32_t *errw = &a.status[5 + (s & 1)];
+        if (po.bad) {
+            if (atomicCAS(errw, 0, po.bad) == 0) {  // first reporter names the element and the case
+                a.status[2] = po.bad_elem;
+                a.status[3] = s;
+                a.status[7] = max(bad_rhs, 0);
+            }
+        }
+        if (!grid_barrier(a.bar, G, epoch, a.status)) {
+            code = DJ_ERR_BARRIER;
+            break;
+        }
+        if (threadIdx.x == 0) s_flag = ld_dev(errw);
+        __syncthreads();
+        if (s_flag != 0) {
+            code = s_flag;
+            break;
+        }
+        {
+            const StepPtrs<T> sp = make_sp(0);
+            C::template shared_finish<1, KB>(tp, sr, sp, po);
+            for (int k0 = 0; k0 < nmine; k0 += KB)
+                C::template shared_batch<1, KB>(tp, s_ch + k0, min(KB, nmine - k0), k0 == 0 ? 1 : 0, sp, po);
+            after_case(0);
+        }
+        for (int r = 1; r < R; r++) {  // the other cases: round A after the barrier
+            const StepPtrs<T> sp = make_sp(r);
+            for (int k0 = 0; k0 < nmine; k0 += KB)
+                C::template shared_batch<1, KB>(tp, s_ch + k0, min(KB, nmine - k0), 0, sp, po);
+            after_case(r);
+        }
+        if (check) {
+            // per workgroup and case: (|F - R|^2 over free, |F|^2 over constrained) components
+            double *red = a.red + size_t(s & 1) * 2 * G * R;
+            if (R == 1) {
+                double x = po.num, y = po.den;
+                block_sum2<BLOCK>(x, y, sred);
+                if (threadIdx.x == 0) {
+                    st_dev(&red[2 * blockIdx.x], x);
+                    st_dev(&red[2 * blockIdx.x + 1], y);
+                }
+            } else {
+                __syncthreads();
+                if (threadIdx.x < 2 * R) st_dev(&red[2 * size_t(blockIdx.x) * R + threadIdx.x], s_res[threadIdx.x]);
+            }
+            if (!grid_barrier(a.bar, G, epoch, a.status)) {
+                code = DJ_ERR_BARRIER;
+                break;
+            }
+            // every workgroup reduces all partials in the same order; the run
+            // stops when every case has converged
+            int conv = 1;
+            for (int r = 0; r < R; r++) {
+                double sx = 0, sy = 0;
+                for (uint32_t g = threadIdx.x; g < G; g += BLOCK) {
+                    sx += ld_dev(&red[2 * (size_t(g) * R + r)]);
+                    sy += ld_dev(&red[2 * (size_t(g) * R + r) + 1]);
+                }
+                block_sum2<BLOCK>(sx, sy, sred);
+                if (threadIdx.x == 0) {
+                    const double res = sy > 0.0 ? sqrt(sx) / sqrt(sy) : (sx > 0.0 ? INFINITY : 0.0);
+                    conv &= (res <= a.tol) ? 1 : 0;
+                    if (blockIdx.x == 0) a.res_out[r] = res;
+                }
+            }
+            if (threadIdx.x == 0) s_flag = conv;
+            __syncthreads();
+            if (s_flag) {
+                code = DJ_CONVERGED;
+                break;  // u^n is the converged state; u^{n+1} is discarded
+            }
+        }
+        // shared copies written above by one thread are read by another in the
+        // next step's scatter (and in the final write-out)
+        __syncthreads();
+        cur = nxt;
+        done = s + 1;
+    }
+    __syncthreads();
+    if (code == DJ_ERR_BARRIER) return;  // status[4] is set; the caller's state is left untouched
+    if (code != DJ_OK && code != DJ_CONVERGED) done = s;  // the failing step is not completed
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.status[0] = code;
+        a.status[1] = done;
+    }
+    // write the final state (canonical copies) of every case to the caller arrays
+    const int prv = (cur + 2) % 3;
+    for (int r = 0; r < R; r++) {
+        T *oc = static_cast<T *>(a.u_out_cur) + int64_t(r) * a.out_stride;
+        T *op = static_cast<T *>(a.u_out_prev) + int64_t(r) * a.out_stride;
+        const int64_t uo = int64_t(r) * 3 * L;
+        for (int k = 0; k < nmine; k++) {
+            const ChunkDesc ch = s_ch[k];
+            for (int i = threadIdx.x; i < ch.copy_count; i += BLOCK) {
+                const int l = ch.copy_begin + i;
+                if (!(tp.flags[l] & FLAG_CANON)) continue;
+                const int nd = tp.cnode[l];
+#pragma unroll
+                for (int c3 = 0; c3 < 3; c3++) {
+                    oc[3 * nd + c3] = ub(cur)[uo + c3 * L + l];
+                    op[3 * nd + c3] = ub(prv)[uo + c3 * L + l];
+                }
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Pre-computation (Algorithm 1) in FP64, one thread per element
 // ---------------------------------------------------------------------------
@@ -367,9 +586,23 @@ __global__ void k_reset_sync(uint32_t *sync, int n_sync, int32_t *status) {
 template <typename T, int NE, int MODEL, int BLOCK, int EPT, int MC, int WPE>
 struct Inst {
     using C = Chunk<T, NE, MODEL, BLOCK, EPT, MC>;
+    // several load cases per launch: FP32, Jacobian form, two-wave variants
+    static constexpr bool has_multi() { return sizeof(T) == 4 && (MODEL & DJ_FORM_TLED) == 0 && WPE < 3; }
     static hipError_t occ(int *bpc, size_t *lds) {
         *lds = C::LDS;
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, k_step<T, NE, MODEL, BLOCK, EPT, MC, WPE>, BLOCK, C::LDS);
+    }
+    // workgroups per CU of the several-cases kernel; 0: not built
+    static hipError_t occ_multi(int *bpc) {
+        *bpc = 0;
+        if constexpr (has_multi()) {
+            const void *kern = reinterpret_cast<const void *>(&k_step_multi<T, NE, MODEL, BLOCK, EPT, MC, WPE>);
+            hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(C::LDS));
+            if (e != hipSuccess) return e;
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, k_step_multi<T, NE, MODEL, BLOCK, EPT, MC, WPE>,
+                                                                BLOCK, C::LDS);
+        }
+        return hipSuccess;
     }
     static hipError_t forces(Ctx &c, const void *u, void *f, hipStream_t s) {
         const int L = c.topo.n_copies, B = 256;
@@ -404,6 +637,7 @@ struct Inst {
                            c.topo, sp);
         return hipGetLastError();
     }
+    // u_cur_in / u_prev_in: a.nrhs x n_nodes x 3 each
     static hipError_t step(Ctx &c, const StepArgs &a, const void *u_cur_in, const void *u_prev_in, hipStream_t s,
                            hipEvent_t ev0, hipEvent_t ev1) {
         const int L = c.topo.n_copies, B = 256;
@@ -411,21 +645,27 @@ struct Inst {
         hipLaunchKernelGGL(k_reset_sync, dim3((n_sync + 255) / 256), dim3(256), 0, s, c.d_bar, n_sync, c.d_status);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
-        T *dcur = static_cast<T *>(c.d_ubuf[a.cur0]);
-        T *dprev = static_cast<T *>(c.d_ubuf[(a.cur0 + 2) % 3]);
-        hipLaunchKernelGGL(k_scatter_in<T>, dim3((L + B - 1) / B), dim3(B), 0, s, c.topo.cnode, L,
-                           static_cast<const T *>(u_cur_in), static_cast<const T *>(u_prev_in), dcur, dprev);
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        for (int r = 0; r < a.nrhs; r++) {
+            T *dcur = static_cast<T *>(a.ubuf[a.cur0]) + int64_t(r) * 3 * L;
+            T *dprev = static_cast<T *>(a.ubuf[(a.cur0 + 2) % 3]) + int64_t(r) * 3 * L;
+            hipLaunchKernelGGL(k_scatter_in<T>, dim3((L + B - 1) / B), dim3(B), 0, s, c.topo.cnode, L,
+                               static_cast<const T *>(u_cur_in) + r * a.out_stride,
+                               static_cast<const T *>(u_prev_in) + r * a.out_stride, dcur, dprev);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
         DevTopo tp = c.topo;
         StepArgs aa = a;
         void *args[] = {&tp, &aa};
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_step<T, NE, MODEL, BLOCK, EPT, MC, WPE>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, int(C::LDS));
+        const void *kern = reinterpret_cast<const void *>(&k_step<T, NE, MODEL, BLOCK, EPT, MC, WPE>);
+        if (a.nrhs > 1) {
+            if constexpr (has_multi()) kern = reinterpret_cast<const void *>(&k_step_multi<T, NE, MODEL, BLOCK, EPT, MC, WPE>);
+            else return hipErrorInvalidValue;
+        }
+        e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(C::LDS));
         if (e != hipSuccess) return e;
         if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
-        e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_step<T, NE, MODEL, BLOCK, EPT, MC, WPE>),
-                                       dim3(c.grid), dim3(BLOCK), args, C::LDS, s);
+        e = hipLaunchCooperativeKernel(kern, dim3(c.grid), dim3(BLOCK), args, C::LDS, s);
         if (e != hipSuccess) return e;
         if (ev1) e = hipEventRecord(ev1, s);
         return e;
@@ -486,6 +726,11 @@ const std::vector<Variant> &variants(int ne, int prec) {
 hipError_t occupancy(int ne, int model, int form, int prec, int variant, int *blocks_per_cu, size_t *lds_bytes) {
     return dispatch(prec, ne, model, form, variant,
                     [&](auto inst) { return decltype(inst)::occ(blocks_per_cu, lds_bytes); });
+}
+
+hipError_t occupancy_multi(const Ctx &c, int *blocks_per_cu) {
+    return dispatch(c.prec, c.ne, c.model, c.form, c.variant,
+                    [&](auto inst) { return decltype(inst)::occ_multi(blocks_per_cu); });
 }
 
 hipError_t launch_forces(Ctx &c, const void *u, void *f, hipStream_t s) {

@@ -166,6 +166,39 @@ class Solver:
             raise L.DJError(code, "djtled_step")
         return status, st.step
 
+    def zeros_multi(self, k: int):
+        return torch.zeros((k, self.n_nodes, 3), dtype=self.dtype, device=self.device)
+
+    def step_multi(self, u_cur: torch.Tensor, u_prev: torch.Tensor, n_steps: int, loads=None, step0: int = 0,
+                   relax: bool = False, tol: float = 0.0, check_every: int = 1, stream=None,
+                   raise_on_error: bool = True):
+        """Advance k load cases in one launch: u_cur, u_prev are (k, n_nodes, 3)
+        tensors, loads a list of k LoadSets (common ramp) or None.  Returns
+        (status, new step index, per-case residuals, case of an error or -1)."""
+        if u_cur.dim() != 3 or u_cur.shape != u_prev.shape:
+            raise ValueError("u_cur and u_prev must be (k, n_nodes, 3) tensors of one shape")
+        k = u_cur.shape[0]
+        for t in (u_cur, u_prev):
+            if (t.device != self.device or t.dtype != self.dtype or tuple(t.shape[1:]) != (self.n_nodes, 3)
+                    or not t.is_contiguous()):
+                raise ValueError(f"state must be a contiguous {self.dtype} (k, {self.n_nodes}, 3) tensor")
+        st = L.djtled_state(ctypes.c_void_p(u_cur.data_ptr()), ctypes.c_void_p(u_prev.data_ptr()), int(step0))
+        lsp = None
+        if loads is not None:
+            if len(loads) != k:
+                raise ValueError("one LoadSet per load case")
+            lsp = (ctypes.c_void_p * k)(*[ls.handle for ls in loads])
+        opts = L.djtled_step_opts(L.DJ_MODE_RELAX if relax else L.DJ_MODE_FIXED, float(tol), int(check_every))
+        out = L.djtled_status()
+        res = np.full(k, np.nan)
+        ecase = ctypes.c_int32(-1)
+        code = L.lib.djtled_step_multi(self.handle, k, ctypes.byref(st), lsp, int(n_steps), ctypes.byref(opts),
+                                       ctypes.byref(out), _dptr(res), ctypes.byref(ecase), _stream(stream))
+        status = Status(out.code, out.steps_done, out.error_step, out.error_elem, out.residual, out.kernel_ms)
+        if code < 0 and raise_on_error:
+            raise L.DJError(code, "djtled_step_multi")
+        return status, st.step, res, ecase.value
+
     def export_constants(self):
         V = np.zeros(self.n_elems)
         ne = self.conn.shape[1]
