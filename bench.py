@@ -397,7 +397,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--cpu-steps", type=int, default=15, help="oracle steps per mesh for cpu_baseline (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=50, help="oracle steps per mesh for cpu_baseline (0: skip)")
     ap.add_argument("--variant", type=int, default=-1, help="kernel variant (-1: per-mesh default)")
     ap.add_argument("--mesh", choices=["both", "t4", "h8"], default="both")
     ap.add_argument("--copy-calib", action="store_true",
