@@ -3,7 +3,7 @@
  * (libdjtled.so).
  *
  * The paper names data-driven acceleration of the explicit solve as future
- * work (Sec. 7) and gives no network; this one maps a load-parameter vector p
+ * work (Sec. 8) and gives no network; this one maps a load-parameter vector p
  * (n_in values) to a displacement field u (n_out values):
  *     H1 = relu(p W1 + b1),  H2 = relu(H1 W2 + b2),  u = H2 W3^T + b3,
  * trained with the mean-squared error against steady states of the plain

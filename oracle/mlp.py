@@ -4,7 +4,7 @@ Plain NumPy (float64) forward pass, mean-squared-error loss, hand-derived
 backward pass and Adam step of the warm-start network
     H1 = relu(P W1 + b1),  H2 = relu(H1 W2 + b2),  Y = H2 W3^T + b3,
     loss = mean over (rows, outputs) of (Y - U)^2.
-The paper proposes data-driven acceleration only as future work (Sec. 7)
+The paper proposes data-driven acceleration only as future work (Sec. 8)
 and fixes no network, so these are the textbook definitions: backpropagation
 through affine maps and ReLU, and Adam (Kingma and Ba, 2015, Algorithm 1).
 
