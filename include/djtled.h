@@ -5,12 +5,16 @@
  * dynamics method (Zhang, arXiv 2106.14189) on one AMD Instinct MI355X
  * (gfx950):
  *   (a) element nodal forces from the precomputed Jacobian constants and the
- *       gathered nodal displacements (Sec. 2.2, Eq. 10; Table 3 neo-Hookean and
- *       transversely isotropic rows; invariants of Table 1),
+ *       gathered nodal displacements (Sec. 2.2, Eq. 10; the neo-Hookean,
+ *       transversely isotropic, orthotropic and Mooney-Rivlin rows of Table 3;
+ *       invariants of Table 1), or, for comparison, the classical TLED force
+ *       (Eq. 4),
  *   (b) reduction of the element forces to the nodes (the sum of Eq. 13),
  *   (c) central-difference explicit integration with lumped mass-proportional
  *       damping (Eq. 13) and displacement boundary conditions, under the
- *       critical step of Eq. 14.
+ *       critical step of Eq. 14,
+ * for one mesh (several load cases per launch if wanted) or for a batch of
+ * meshes in one launch.
  *
  * Conventions shared by every entry point
  *   - Host pointers are read during the call only; the library never keeps or
@@ -112,8 +116,11 @@ typedef struct djtled_loadset djtled_loadset;
  * per-element constant the run time needs: the Jacobian 0J (Eq. 3) and its
  * inverse, whose columns are the shape-function derivatives dh/dX of Eq. 6,
  * the volume 0V, the constant I1m = 2 0V 0J^-T 0J^-1 (Eq. 37) kept through
- * 0J^-1, and for DJ_TI the fibre factor of I4m (Eq. 45); for DJ_H8 the
- * hourglass vectors; the lumped nodal masses and the critical step (Eq. 14).
+ * 0J^-1, for DJ_TI / DJ_OT the unit fibres and moduli behind I4m and I6m
+ * (Eqs. 45, 46), for DJ_MR the C01 modulus (I2m of Eqs. 40-41 is kept
+ * through 0J^-1 as I1m is); for DJ_H8 the hourglass vectors; the lumped nodal
+ * masses and the critical step (Eq. 14).  Variants 4 and 5 are built for
+ * DJ_NH and DJ_TI; the classical form for FP32 and variants 0..3.
  * On success *out owns every device buffer of the context.
  * Errors: DJ_ERR_ARG, DJ_ERR_BAD_MESH, DJ_ERR_UNSUPPORTED, DJ_ERR_UNSTABLE_DT, DJ_ERR_HIP.
  */
@@ -138,7 +145,8 @@ int djtled_info(const djtled_ctx *ctx, djtled_info_t *out);
 
 /*
  * djtled_forces -- internal nodal forces sum_e F^(e)(u) (Eq. 13), each element
- * force from Table 3 (plus hourglass control for H8).  u_dev, f_dev: device,
+ * force from Table 3, or from Eq. 4 for the classical form (plus hourglass
+ * control for H8).  u_dev, f_dev: device,
  * n_nodes x 3.  No boundary condition is applied.  Asynchronous on stream.
  * Errors: DJ_ERR_ARG, DJ_ERR_HIP.
  */
