@@ -59,6 +59,8 @@ def _load():
         lib.ora_element_constants.argtypes = [P, I, dp]
         lib.ora_forces.restype = I
         lib.ora_forces.argtypes = [P, dp, dp, I, ip]
+        lib.ora_forces_anp.restype = I
+        lib.ora_forces_anp.argtypes = [P, dp, dp, ip]
         lib.ora_element_force.argtypes = [P, I, dp, dp, I]
         lib.ora_energy.restype = D
         lib.ora_energy.argtypes = [P, dp]
@@ -185,6 +187,16 @@ class Oracle:
         f = np.zeros((self.n_nodes, 3))
         bad = ctypes.c_int(-1)
         rc = self._lib.ora_forces(self._ctx, _dp(u), _dp(f), int(route), ctypes.byref(bad))
+        if rc != 0:
+            raise FloatingPointError(f"element {bad.value} inverted (J <= 0)")
+        return f
+
+    def forces_anp(self, u):
+        """Internal forces with the average nodal pressure (see ora_forces_anp)."""
+        u = _f64(u, (self.n_nodes, 3))
+        f = np.zeros((self.n_nodes, 3))
+        bad = ctypes.c_int(-1)
+        rc = self._lib.ora_forces_anp(self._ctx, _dp(u), _dp(f), ctypes.byref(bad))
         if rc != 0:
             raise FloatingPointError(f"element {bad.value} inverted (J <= 0)")
         return f

@@ -39,6 +39,9 @@
  *    for the isotropic models).
  *  - Mooney-Rivlin: C10 = mu / 2 from E and nu (as Sec. 5.1 does), C01 given
  *    per element; kappa from E and nu.  Orthotropic: eta_b = ratio_b * mu.
+ *  - Average nodal pressure (named in Sec. 7 against volumetric locking, not
+ *    defined there): the volumetric energy sum_n V_n kappa_n (J_n - 1)^2 / 2
+ *    on 1/n_e-weighted nodal volume averages; ora_forces_anp is its gradient.
  *  - Displacement boundary conditions overwrite the constrained components
  *    after each update with s(t) * target; s is 1, linear or the quintic
  *    smoothstep tau^3 (10 - 15 tau + 6 tau^2).
@@ -466,7 +469,9 @@ static void hourglass_force(const ora_ctx *c, int e, const double Ue[8][3], doub
  * Fe[a][k] is component k of the force at local node a (column a of the 3 x n_e F).
  * Returns J (the volume ratio of Eq. 12).
  */
-static double force_djtled(const ora_ctx *c, int e, const double Ue[8][3], double Fe[8][3]) {
+/* pvol: NULL, or per element the pressure dPsi_vol/dJ to use instead of the
+   element's own kappa (J - 1) (average nodal pressure, ora_forces_anp). */
+static double force_djtled_p(const ora_ctx *c, int e, const double Ue[8][3], double Fe[8][3], const double *pvol) {
     const int ne = c->ne;
     const double *J0 = c->J0 + 9 * e;
     /* step 1: tJ = 0J + H_xi Ue (Eq. 11), tJ^{-1}, J = det(tJ) det(0J)^{-1} (Eq. 12) */
@@ -505,7 +510,8 @@ static double force_djtled(const ora_ctx *c, int e, const double Ue[8][3], doubl
         for (int k = 0; k < 6; k++) gI2 += g[k] * c->I2m[54 * e + 9 * k + i];
         Imix[i] = d1 * c->I1m[9 * e + i] + Jm23 * d2 * gI2 + d4 * c->I4m[9 * e + i] + d6 * c->I6m[9 * e + i];
     }
-    double vol = -2.0 / 3.0 * (d1 * I1b + 2.0 * d2 * I2b + d4 * I4b + d6 * I6b) + kap * J * (J - 1.0);
+    double vol = -2.0 / 3.0 * (d1 * I1b + 2.0 * d2 * I2b + d4 * I4b + d6 * I6b) +
+                 (pvol ? J * pvol[e] : kap * J * (J - 1.0));
     double M[9], t[9];
     mul3(tJT, Imix, t);
     for (int i = 0; i < 9; i++) M[i] = Jm23 * t[i] + vol * c->V[e] * tJinv[i];
@@ -577,6 +583,10 @@ static double force_tled(const ora_ctx *c, int e, const double Ue[8][3], double 
     return J;
 }
 
+static double force_djtled(const ora_ctx *c, int e, const double Ue[8][3], double Fe[8][3]) {
+    return force_djtled_p(c, e, Ue, Fe, NULL);
+}
+
 /*
  * Global internal force sum_e F^(e) (Eq. 13), assembled in element order.
  * route 0: DJ-TLED (Table 3); route 1: classical TLED (Eq. 4).
@@ -611,6 +621,72 @@ int ora_element_force(const ora_ctx *c, int e, const double *Ue_in, double *Fe_o
     for (int a = 0; a < c->ne; a++)
         for (int k = 0; k < 3; k++) Fe_out[3 * a + k] = Fe[a][k];
     return 0;
+}
+
+/*
+ * Average nodal pressure (the locking remedy Sec. 7 mentions for nearly
+ * incompressible tissue), in its variational reading: the volumetric energy
+ * is carried by the nodes, sum_n V_n kappa_n (J_n - 1)^2 / 2, with nodal
+ * volume V_n = sum_e 0V_e / n_e, volume ratio J_n = sum_e (0V_e / n_e) J_e / V_n
+ * and modulus kappa_n = sum_e (0V_e / n_e) kappa_e / V_n over the elements
+ * around n.  Its gradient is the Table 3 force with each element's pressure
+ * kappa_e (J_e - 1) replaced by the mean of kappa_n (J_n - 1) over the
+ * element's nodes.  Returns 0, or -3 with *bad_elem if some J_e <= 0.
+ */
+int ora_forces_anp(const ora_ctx *c, const double *u, double *f, int *bad_elem) {
+    const int ne = c->ne, E_ = c->n_elems, N_ = c->n_nodes;
+    double *Je = (double *)calloc((size_t)E_, sizeof(double));
+    double *Vn = (double *)calloc((size_t)N_, sizeof(double));
+    double *Jn = (double *)calloc((size_t)N_, sizeof(double));
+    double *Kn = (double *)calloc((size_t)N_, sizeof(double));
+    double *pb = (double *)calloc((size_t)E_, sizeof(double));
+    int rc = 0;
+    if (bad_elem) *bad_elem = -1;
+    for (int e = 0; e < E_; e++) {
+        double Ue[8][3], tJ[9];
+        gather_u(c, e, u, Ue);
+        const double *J0 = c->J0 + 9 * e;
+        for (int i = 0; i < 3; i++)
+            for (int k = 0; k < 3; k++) {
+                double s = J0[3 * i + k];
+                for (int a = 0; a < ne; a++) s += c->H[i][a] * Ue[a][k];
+                tJ[3 * i + k] = s;
+            }
+        Je[e] = det3(tJ) / c->detJ0[e];  /* Eq. 12 */
+        if (!(Je[e] > 0.0) && rc == 0) {
+            rc = -3;
+            if (bad_elem) *bad_elem = e;
+        }
+        const int *cn = c->conn + (size_t)e * ne;
+        for (int a = 0; a < ne; a++) {
+            const double w = c->V[e] / ne;
+            Vn[cn[a]] += w;
+            Jn[cn[a]] += w * Je[e];
+            Kn[cn[a]] += w * c->kappa[e];
+        }
+    }
+    for (int n = 0; n < N_; n++)
+        if (Vn[n] > 0.0) {
+            Jn[n] /= Vn[n];
+            Kn[n] /= Vn[n];
+        }
+    for (int e = 0; e < E_; e++) {
+        const int *cn = c->conn + (size_t)e * ne;
+        double s = 0.0;
+        for (int a = 0; a < ne; a++) s += Kn[cn[a]] * (Jn[cn[a]] - 1.0);
+        pb[e] = s / ne;
+    }
+    memset(f, 0, sizeof(double) * 3 * (size_t)N_);
+    for (int e = 0; e < E_; e++) {
+        double Ue[8][3], Fe[8][3];
+        gather_u(c, e, u, Ue);
+        force_djtled_p(c, e, Ue, Fe, pb);
+        const int *cn = c->conn + (size_t)e * ne;
+        for (int a = 0; a < ne; a++)
+            for (int k = 0; k < 3; k++) f[3 * cn[a] + k] += Fe[a][k];
+    }
+    free(Je); free(Vn); free(Jn); free(Kn); free(pb);
+    return rc;
 }
 
 /*

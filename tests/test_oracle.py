@@ -66,8 +66,13 @@ def _psi(F, mu, kappa, eta=0.0, a=None, eta_b=0.0, b=None, c01=0.0):
 
 
 def _independent_energy(mesh_X, conn, u, mu, kappa, eta=None, fibre=None, hg_kappa=0.1, eta_b=None, fibre_b=None,
-                        c01=None):
+                        c01=None, nodal_volume=False):
+    """Total strain energy.  nodal_volume: the volumetric part is carried by the
+    nodes (average nodal pressure): sum_n V_n kappa_n (J_n - 1)^2 / 2 with
+    V_n, J_n, kappa_n the 1/n_e-weighted volume averages of the elements around n."""
     Etot = 0.0
+    ne = conn.shape[1]
+    Vn, VJn, VKn = np.zeros(len(mesh_X)), np.zeros(len(mesh_X)), np.zeros(len(mesh_X))
     Gam = np.stack([_H8C[:, 0] * _H8C[:, 1], _H8C[:, 1] * _H8C[:, 2],
                     _H8C[:, 2] * _H8C[:, 0], _H8C[:, 0] * _H8C[:, 1] * _H8C[:, 2]])
     for e in range(conn.shape[0]):
@@ -86,7 +91,13 @@ def _independent_energy(mesh_X, conn, u, mu, kappa, eta=None, fibre=None, hg_kap
         eb = eta_b[e] if eta_b is not None else 0.0
         b = fibre_b[e] if fibre_b is not None else None
         c1 = c01[e] if c01 is not None else 0.0
-        Etot += V * _psi(F, mu[e], kappa[e], et, a, eb, b, c1)
+        if nodal_volume:
+            Etot += V * (_psi(F, mu[e], 0.0, et, a, eb, b, c1))
+            np.add.at(Vn, conn[e], V / ne)
+            np.add.at(VJn, conn[e], V / ne * np.linalg.det(F))
+            np.add.at(VKn, conn[e], V / ne * kappa[e])
+        else:
+            Etot += V * _psi(F, mu[e], kappa[e], et, a, eb, b, c1)
         if conn.shape[1] == 8:
             # Flanagan-Belytschko hourglass energy (reading of the paper's cited control)
             dX = _h8_dmap(P)
@@ -98,6 +109,10 @@ def _independent_energy(mesh_X, conn, u, mu, kappa, eta=None, fibre=None, hg_kap
             k = hg_kappa * (kappa[e] + 4.0 * mu0 / 3.0) * V * np.sum(B * B) / 8.0
             q = gam @ u[conn[e]]                     # (4, 3)
             Etot += 0.5 * k * np.sum(q * q)
+    if nodal_volume:
+        m = Vn > 0
+        Jn, Kn = VJn[m] / Vn[m], VKn[m] / Vn[m]
+        Etot += np.sum(Vn[m] * 0.5 * Kn * (Jn - 1.0) ** 2)
     return Etot
 
 
@@ -451,3 +466,51 @@ def test_dynamic_relaxation_reaches_homogeneous_uniaxial_state(elem, model):
     assert np.abs(u - exact).max() <= 1e-7 * np.abs(exact).max()
     if model == W.NH:
         assert abs(lam[0] - lam[1]) < 1e-9 and 1.09 < lam[0] < 1.12   # hand estimate ~1.106
+
+
+# ---------------------------------------------------------------------------
+# Average nodal pressure (variational reading of the Sec. 7 remedy)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("elem", [W.T4, W.H8])
+@pytest.mark.parametrize("model", [W.NH, W.TI])
+def test_anp_forces_are_energy_gradient(elem, model):
+    """ANP forces equal the central differences of an independently coded
+    energy whose volumetric part lives on the nodes."""
+    mesh, o, E, nu, kw, rng = _small_case(elem, model, n=2, seed=7)
+    mu, ka = _lame(E, nu)
+    ekw = _energy_kw(kw, mu)
+    u = rng.normal(size=(mesh.n_nodes, 3)) * 1e-3
+    f = o.forces_anp(u)
+    h = 1e-8
+    scale = np.abs(f).max()
+    for (i, k) in [(j, c) for j in range(mesh.n_nodes) for c in range(3)][::5]:
+        up, um = u.copy(), u.copy()
+        up[i, k] += h
+        um[i, k] -= h
+        g = (_independent_energy(mesh.X, mesh.conn, up, mu, ka, nodal_volume=True, **ekw)
+             - _independent_energy(mesh.X, mesh.conn, um, mu, ka, nodal_volume=True, **ekw)) / (2 * h)
+        assert abs(g - f[i, k]) <= 1e-6 * scale, (i, k, g, f[i, k])
+    # and they differ from the element-pressure forces for this non-uniform field
+    assert np.abs(f - o.forces(u)).max() > 1e-3 * scale
+
+
+@pytest.mark.parametrize("elem", [W.T4, W.H8])
+def test_anp_reduces_to_standard_under_uniform_pressure(elem):
+    """Uniform material and a homogeneous deformation: every J_e is the same,
+    so the nodal pressures equal the element pressures and ANP is DJ-TLED."""
+    mesh = W.cube_mesh(2, 0.01, elem, jitter=0.08, seed=2)
+    o = oracle.Oracle(mesh.X, mesh.conn, 3000.0, 0.45)
+    Fd = np.array([[1.03, 0.02, -0.01], [0.01, 0.97, 0.03], [-0.02, 0.015, 1.05]])
+    u = mesh.X @ (Fd - np.eye(3)).T
+    f1, f0 = o.forces_anp(u), o.forces(u)
+    assert np.abs(f1 - f0).max() <= 1e-12 * np.abs(f0).max()
+
+
+def test_anp_rigid_motion_gives_zero_force():
+    mesh = W.cube_mesh(2, 0.01, W.T4, jitter=0.08, seed=4)
+    rng = np.random.default_rng(1)
+    o = oracle.Oracle(mesh.X, mesh.conn, rng.uniform(2000, 6000, mesh.n_elems), 0.45)
+    Q = _rand_rotation(rng)
+    u = mesh.X @ Q.T - mesh.X + np.array([0.01, -0.02, 0.005])
+    ref = np.abs(o.forces_anp(mesh.X * 0.01)).max()
+    assert np.abs(o.forces_anp(u)).max() <= 1e-10 * ref
