@@ -26,6 +26,9 @@
  *     node 0, then node 1, ...), in the context's precision (float for
  *     DJ_FP32, double for DJ_FP64).
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - A context (and a batch) owns device buffers that every call on it
+ *     uses: calls on one context must not overlap (one host thread at a
+ *     time, one call in flight); separate contexts are independent.
  *   - Return codes: DJ_OK (0), DJ_CONVERGED (1, informational), or a negative
  *     DJ_ERR_*.  djtled_last_error() returns a thread-local message for the
  *     last failing call on the calling thread.
