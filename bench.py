@@ -31,7 +31,7 @@ Further measurements, reported under "extra" (each skippable):
     displacement error from the prediction vs from rest.
 
 Prints one JSON line (see the keys below).  --gpus N > 1 is not supported:
-this build runs on a single GPU.
+the library runs on a single GPU.
 """
 from __future__ import annotations
 
@@ -416,7 +416,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: --gpus {args.gpus} requested; this DJ-TLED build runs on one GPU only "
+        print(f"bench.py: --gpus {args.gpus} requested; this DJ-TLED library runs on one GPU only "
               f"(multi-GPU sharding is a design note, not built).", file=sys.stderr)
         sys.exit(2)
 
