@@ -155,6 +155,20 @@ int djtled_info(const djtled_ctx *ctx, djtled_info_t *out);
  */
 int djtled_forces(djtled_ctx *ctx, const void *u_dev, void *f_dev, void *stream);
 
+/*
+ * djtled_forces_anp -- djtled_forces with the average nodal pressure (the
+ * remedy for volumetric locking of nearly incompressible tissue that Sec. 7
+ * names): the volumetric energy sum_n V_n kappa_n (J_n - 1)^2 / 2 lives on
+ * the nodes, V_n = sum_e 0V_e / n_e and J_n, kappa_n the 0V_e / n_e-weighted
+ * averages of the element volume ratios (Eq. 12) and bulk moduli around n;
+ * each element's pressure kappa (J - 1) in Table 3 is replaced by the mean of
+ * its nodes' kappa_n (J_n - 1).  The nodal averages are formed in FP64 with a
+ * fixed summation order.  DJ_NH / DJ_TI contexts, Jacobian form, variants
+ * 0..3; the first call allocates scratch buffers kept by the context.
+ * Errors: DJ_ERR_ARG, DJ_ERR_UNSUPPORTED, DJ_ERR_HIP.
+ */
+int djtled_forces_anp(djtled_ctx *ctx, const void *u_dev, void *f_dev, void *stream);
+
 /* Loads (host memory): displacement boundary conditions and external forces. */
 typedef struct {
     int32_t n_bc;

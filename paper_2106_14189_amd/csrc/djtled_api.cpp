@@ -430,12 +430,18 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
         const bool okm = (!fib_a || etai[e] >= 0) && (!fib_b || etabi[e] >= 0) && (c.model != DJ_MR || c01i[e] >= 0);
         if (!okm) return fail(DJ_ERR_ARG, "element " + std::to_string(c.elem_perm[e]) + ": negative fibre or C01 modulus");
     }
+    {
+        std::vector<double> kap(E);
+        for (int e = 0; e < E; e++) kap[e] = Ei[e] / (3.0 * (1.0 - 2.0 * nui[e]));
+        DJ_HIP(upload(c, &c.d_kappa64, kap));
+    }
     TempBufs tb;
     double *dX, *dE, *dnu, *ddt;
     int32_t *dconn, *dbad, *dneoff, *dnelist;
     MatDev md{};
     DJ_HIP(tb.up(&dX, Xi));
-    DJ_HIP(tb.up(&dconn, conn));
+    DJ_HIP(upload(c, &dconn, conn));  // kept (element nodes, internal ids)
+    c.d_enode = dconn;
     DJ_HIP(tb.up(&dE, Ei));
     DJ_HIP(tb.up(&dnu, nui));
     md.E = dE;
@@ -466,8 +472,10 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     }
     DJ_HIP(tb.up(&ddt, std::vector<double>(NI, inf)));
     DJ_HIP(tb.up(&dbad, std::vector<int32_t>{0}));
-    DJ_HIP(tb.up(&dneoff, ne_off));
-    DJ_HIP(tb.up(&dnelist, ne_list));
+    DJ_HIP(upload(c, &dneoff, ne_off));  // kept: the average-nodal-pressure forces use them
+    DJ_HIP(upload(c, &dnelist, ne_list));
+    c.d_ne_off = dneoff;
+    c.d_ne_list = dnelist;
     DJ_HIP(launch_precompute(c, dX, dconn, md, dei, ddt, dbad, nullptr));
     int32_t bad = 0;
     std::vector<double> dtc(NI);
@@ -828,6 +836,24 @@ int djtled_forces(djtled_ctx *ctx, const void *u_dev, void *f_dev, void *stream)
     Ctx &c = *reinterpret_cast<Ctx *>(ctx);
     DJ_HIP(hipSetDevice(c.device));
     DJ_HIP(launch_forces(c, u_dev, f_dev, static_cast<hipStream_t>(stream)));
+    return DJ_OK;
+}
+
+int djtled_forces_anp(djtled_ctx *ctx, const void *u_dev, void *f_dev, void *stream) {
+    if (!ctx || !u_dev || !f_dev) return fail(DJ_ERR_ARG, "null argument");
+    Ctx &c = *reinterpret_cast<Ctx *>(ctx);
+    if (c.n_inst > 1) return fail(DJ_ERR_ARG, "batch contexts have no forces entry point");
+    if ((c.model != DJ_NH && c.model != DJ_TI) || c.form != DJ_FORM_JACOBIAN || c.variant >= 4)
+        return fail(DJ_ERR_UNSUPPORTED, "average nodal pressure: DJ_NH / DJ_TI, Jacobian form, variants 0..3");
+    DJ_HIP(hipSetDevice(c.device));
+    if (!c.d_anp_planes) {
+        const size_t ts = c.prec == DJ_FP32 ? sizeof(float) : sizeof(double);
+        DJ_HIP(dalloc(c, reinterpret_cast<char **>(&c.d_anp_planes),
+                      size_t(n_planes(c.ne, c.model)) * c.topo.estride * ts));
+        DJ_HIP(dalloc(c, &c.d_anp_je, size_t(c.n_elems)));
+        DJ_HIP(dalloc(c, &c.d_anp_pn, size_t(c.n_nodes)));
+    }
+    DJ_HIP(launch_forces_anp(c, u_dev, f_dev, static_cast<hipStream_t>(stream)));
     return DJ_OK;
 }
 

@@ -274,7 +274,8 @@ __device__ __forceinline__ T element_force(const T *__restrict__ cst, const T (&
         const T c = dj_cbrt(J);
         const T Jm23 = dj_rcp(c * c);                             // J^-2/3
         const T muV = cst[P::MUV], kaV = cst[P::KAV];
-        T c0 = -(muV * T(1.0 / 3.0)) * Jm23 * I1m3 + kaV * J * Jm1;  // (mu J^-2/3 + p) 0V
+        // (mu J^-2/3 + p) 0V; with ANP the kappa plane holds pbar 0V, pbar = dPsi_vol/dJ
+        T c0 = -(muV * T(1.0 / 3.0)) * Jm23 * I1m3 + ((MODEL & DJ_FORM_ANP) ? J * kaV : kaV * J * Jm1);
         T ciso = muV * Jm23;                                          // the O(1) identity part of c0 - p 0V
         T Q[3][3];
 #pragma unroll

@@ -47,6 +47,9 @@ inline int kind_of(int ne, int model) { return (ne == 8 ? 2 : 0) + (model == DJ_
 // Kernel template MODEL = material model | DJ_FORM_TLED for the classical
 // TLED force (Eq. 4) instead of the Table 3 force; both read the same planes.
 constexpr int DJ_FORM_TLED = 16;
+// MODEL | DJ_FORM_ANP: the kappa 0V plane holds the element's average nodal
+// pressure times 0V, which replaces kappa (J - 1) 0V in the force
+constexpr int DJ_FORM_ANP = 32;
 constexpr int base_model(int model) { return model & 15; }
 
 constexpr int model_planes(int model) {  // planes of the material part, after 0J^-1, mu 0V, kappa 0V
@@ -148,6 +151,12 @@ struct Ctx {
     uint32_t *d_bar = nullptr;
     int32_t *d_status = nullptr;
     double *d_red = nullptr;
+    // average nodal pressure (forces entry point): element nodes, node -> element
+    // lists (internal ids), kappa per element (FP64), scratch planes and pressures
+    int32_t *d_enode = nullptr, *d_ne_off = nullptr, *d_ne_list = nullptr;
+    double *d_kappa64 = nullptr;
+    void *d_anp_planes = nullptr;
+    double *d_anp_je = nullptr, *d_anp_pn = nullptr;
     // several load cases per launch: buffers grown on demand (case capacity rhs_cap)
     int rhs_cap = 0;
     void *d_mubuf[3] = {nullptr, nullptr, nullptr};
@@ -226,5 +235,7 @@ hipError_t launch_forces(Ctx &c, const void *u, void *f, hipStream_t s);
 hipError_t launch_step(Ctx &c, const StepArgs &a, const void *u_cur_in, const void *u_prev_in, hipStream_t s,
                        hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_export(Ctx &c, double *d_V, double *d_dhdX, double *d_mass, hipStream_t s);
+// internal forces with the average nodal pressure (u, f: caller order)
+hipError_t launch_forces_anp(Ctx &c, const void *u, void *f, hipStream_t s);
 
 }  // namespace dj

@@ -733,6 +733,99 @@ hipError_t occupancy_multi(const Ctx &c, int *blocks_per_cu) {
                     [&](auto inst) { return decltype(inst)::occ_multi(blocks_per_cu); });
 }
 
+// ---- average nodal pressure: element J (FP64), nodal pressures, element planes
+template <typename T, int NE>
+__global__ void k_anp_je(const int32_t *__restrict__ enode, const int32_t *__restrict__ nperm, int E,
+                         const T *__restrict__ u, const double *__restrict__ jinv64, double *__restrict__ Je) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    double du[NE][3];
+    int n0 = nperm[enode[int64_t(NE) * e]];
+    for (int a = 0; a < NE; a++) {
+        const int n = nperm[enode[int64_t(NE) * e + a]];
+        for (int k = 0; k < 3; k++) du[a][k] = double(u[3 * int64_t(n) + k]) - double(u[3 * int64_t(n0) + k]);
+    }
+    double dJ[3][3];
+    for (int i = 0; i < 3; i++)
+        for (int k = 0; k < 3; k++) {
+            double s = 0.0;
+            if (NE == 4) {
+                s = du[i + 1][k];
+            } else {
+                for (int a = 1; a < 8; a++) s += h8s(a, i) * du[a][k];
+                s *= 0.125;
+            }
+            dJ[i][k] = s;
+        }
+    const double *Ji = jinv64 + 9 * int64_t(e);
+    double A[3][3];  // I + D, D = 0J^-1 dJ
+    for (int i = 0; i < 3; i++)
+        for (int k = 0; k < 3; k++)
+            A[i][k] = (i == k ? 1.0 : 0.0) + Ji[3 * i] * dJ[0][k] + Ji[3 * i + 1] * dJ[1][k] + Ji[3 * i + 2] * dJ[2][k];
+    Je[e] = det3d(A);  // Eq. 12
+}
+
+// per internal node: V_n, J_n, kappa_n over its elements (ascending), pressure kappa_n (J_n - 1)
+template <int NE>
+__global__ void k_anp_node(const int32_t *__restrict__ off, const int32_t *__restrict__ lst, int N,
+                           const double *__restrict__ V64, const double *__restrict__ Je,
+                           const double *__restrict__ kappa, double *__restrict__ Pn) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    double v = 0.0, vj = 0.0, vk = 0.0;
+    for (int j = off[n]; j < off[n + 1]; j++) {
+        const int e = lst[j];
+        const double w = V64[e] / NE;
+        v += w;
+        vj += w * Je[e];
+        vk += w * kappa[e];
+    }
+    Pn[n] = v > 0.0 ? (vk / v) * (vj / v - 1.0) : 0.0;
+}
+
+// the kappa 0V plane of a copy of the element planes <- mean nodal pressure x 0V
+template <typename T, int NE>
+__global__ void k_anp_plane(const int32_t *__restrict__ enode, int E, const double *__restrict__ Pn,
+                            const double *__restrict__ V64, T *__restrict__ plane) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    double s = 0.0;
+    for (int a = 0; a < NE; a++) s += Pn[enode[int64_t(NE) * e + a]];
+    plane[e] = T(s / NE * V64[e]);
+}
+
+template <typename T, int NE>
+static hipError_t forces_anp_t(Ctx &c, const void *u, void *f, hipStream_t s) {
+    const int B = 256, E = c.n_elems, N = c.n_nodes;
+    hipLaunchKernelGGL((k_anp_je<T, NE>), dim3((E + B - 1) / B), dim3(B), 0, s, c.d_enode, c.d_node_perm, E,
+                       static_cast<const T *>(u), c.d_jinv64, c.d_anp_je);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_anp_node<NE>, dim3((N + B - 1) / B), dim3(B), 0, s, c.d_ne_off, c.d_ne_list, N, c.d_V64,
+                       c.d_anp_je, c.d_kappa64, c.d_anp_pn);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int NP = n_planes(NE, c.model);
+    const size_t bytes = size_t(NP) * c.topo.estride * sizeof(T);
+    if ((e = hipMemcpyAsync(c.d_anp_planes, c.d_elem, bytes, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+    T *kplane = static_cast<T *>(c.d_anp_planes) + int64_t(Planes<NE, DJ_NH>::KAV) * c.topo.estride;
+    hipLaunchKernelGGL((k_anp_plane<T, NE>), dim3((E + B - 1) / B), dim3(B), 0, s, c.d_enode, E, c.d_anp_pn,
+                       c.d_V64, kplane);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // the standard force pass over the modified planes
+    const void *saved = c.topo.elem;
+    c.topo.elem = c.d_anp_planes;
+    auto run = [&](auto inst) { return decltype(inst)::forces(c, u, f, s); };
+    e = c.model == DJ_NH ? with_variant<T, NE, DJ_NH | DJ_FORM_ANP>(c.variant, run)
+                         : with_variant<T, NE, DJ_TI | DJ_FORM_ANP>(c.variant, run);
+    c.topo.elem = saved;
+    return e;
+}
+
+hipError_t launch_forces_anp(Ctx &c, const void *u, void *f, hipStream_t s) {
+    if (c.prec == DJ_FP32) return c.ne == 4 ? forces_anp_t<float, 4>(c, u, f, s) : forces_anp_t<float, 8>(c, u, f, s);
+    return c.ne == 4 ? forces_anp_t<double, 4>(c, u, f, s) : forces_anp_t<double, 8>(c, u, f, s);
+}
+
 hipError_t launch_forces(Ctx &c, const void *u, void *f, hipStream_t s) {
     return dispatch(c.prec, c.ne, c.model, c.form, c.variant,
                     [&](auto inst) { return decltype(inst)::forces(c, u, f, s); });

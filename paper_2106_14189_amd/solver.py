@@ -134,6 +134,16 @@ class Solver:
                                     _stream(stream)), "djtled_forces")
         return out
 
+    def forces_anp(self, u: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Internal forces with the average nodal pressure (djtled_forces_anp)."""
+        self._check_vec(u, "u")
+        if out is None:
+            out = torch.empty_like(u)
+        self._check_vec(out, "out")
+        L.check(L.lib.djtled_forces_anp(self.handle, ctypes.c_void_p(u.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()), _stream(stream)), "djtled_forces_anp")
+        return out
+
     def loadset(self, bc_node=None, bc_mask=None, bc_target=None, ramp=L.DJ_RAMP_NONE, t_ramp=0.0, R=None):
         bn = np.ascontiguousarray(bc_node if bc_node is not None else np.zeros(0), dtype=np.int32)
         bm = np.ascontiguousarray(bc_mask if bc_mask is not None else np.zeros(0), dtype=np.int32)

@@ -145,6 +145,42 @@ def test_classical_form_limits(S):
         _solver(S, mesh, E, nu, W.NH, kw, "fp32", variant=4, formulation="classical")
 
 
+@pytest.mark.parametrize("elem", [W.T4, W.H8])
+@pytest.mark.parametrize("model", [W.NH, W.TI])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("variant,chunk", [(0, 0), (2, 37)])
+def test_forces_anp_parity(S, elem, model, prec, variant, chunk):
+    """Average-nodal-pressure forces against the oracle's, same tolerances as
+    test_forces_parity (the nodal averages are FP64 on both sides)."""
+    say(f"anp elem={elem} model={model} prec={prec} variant={variant} chunk={chunk}")
+    mesh, E, nu, kw, rng = _case(elem, model, n=7, seed=13 + variant)
+    sv = _solver(S, mesh, E, nu, model, kw, prec, variant=variant, chunk_elems=chunk)
+    ora = _oracle(mesh, E, nu, model, kw)
+    for amp in (1e-4, 0.05, 0.2):
+        u = _smooth_u(mesh, rng, amp)
+        if prec == "fp32":
+            u = u.astype(np.float32).astype(np.float64)
+        f = sv.forces_anp(torch.tensor(u, dtype=sv.dtype, device="cuda"))
+        torch.cuda.synchronize()
+        fo = ora.forces_anp(u)
+        err = np.abs(f.double().cpu().numpy() - fo).max() / np.abs(fo).max()
+        tol = 1e-5 if prec == "fp32" else 1e-12 + 1e-15 / amp
+        say(f"  amp={amp} rel max-norm error {err:.3e} (tol {tol})")
+        assert err <= tol
+    # ANP differs from the element pressure for this field, and the context still steps normally
+    assert np.abs(ora.forces(u) - fo).max() > 1e-4 * np.abs(fo).max()
+    f2 = sv.forces(torch.tensor(u, dtype=sv.dtype, device="cuda"))
+    torch.cuda.synchronize()
+    assert np.abs(f2.double().cpu().numpy() - ora.forces(u)).max() <= (1e-5 if prec == "fp32" else 1e-9) * np.abs(fo).max()
+
+
+def test_forces_anp_limits(S):
+    mesh, E, nu, kw, rng = _case(W.T4, W.MR, n=3, seed=1)
+    sv = _solver(S, mesh, E, nu, W.MR, kw, "fp32")
+    with pytest.raises(Exception, match="average nodal pressure"):
+        sv.forces_anp(sv.zeros())
+
+
 @pytest.mark.parametrize("model", [W.OT, W.MR])
 def test_ot_mr_reject_three_wave_variants(S, model):
     mesh, E, nu, kw, rng = _case(W.T4, model, n=3, seed=1)
