@@ -44,3 +44,22 @@ def test_patch_family_windows_and_encoding():
     E = fam.encode(P)
     np.testing.assert_allclose(E[:, 3], P[:, 0])
     np.testing.assert_allclose(E[:, :3], P[:, :1] * P[:, 1:4])
+
+
+def test_uniform_material_model_inputs():
+    """TI/OT fibres are unit vectors, OT's second family is orthogonal to the
+    first, ratios and C01 fall in their stated ranges."""
+    rng = np.random.default_rng(3)
+    E = rng.uniform(2000, 6000, 500)
+    ot = W.uniform_material(500, E, 0.45, model=W.OT, rng=np.random.default_rng(1))
+    np.testing.assert_allclose(np.linalg.norm(ot.fibre, axis=1), 1.0, rtol=1e-12)
+    np.testing.assert_allclose(np.linalg.norm(ot.fibre_b, axis=1), 1.0, rtol=1e-12)
+    assert np.abs(np.sum(ot.fibre * ot.fibre_b, axis=1)).max() < 1e-12
+    assert ot.eta_ratio.min() >= 2.0 and ot.eta_ratio.max() <= 10.0
+    assert ot.eta_b_ratio.min() >= 2.0 and ot.eta_b_ratio.max() <= 10.0
+    mr = W.uniform_material(500, E, 0.45, model=W.MR, rng=np.random.default_rng(2))
+    c10 = E / (2 * 1.45) / 2
+    r = mr.c01 / c10
+    assert r.min() >= 0.2 and r.max() <= 1.0
+    nh = W.uniform_material(500, E, 0.45)
+    assert nh.fibre is None and nh.c01 is None
