@@ -574,10 +574,10 @@ struct Chunk {
                 const int e = min(int(threadIdx.x) + j * BLOCK, ch.elem_count - 1);
                 const T *src = ep + ch.elem_begin + e;
 #pragma unroll
-                for (int q = 0; q < NP; q++) er.cst[j][q] = __builtin_nontemporal_load(src + q * es);
+                for (int q = 0; q < NP; q++) er.cst[j][q] = src[q * es];
                 const uint16_t *w = tp.wpos + ch.elem_begin + e;
 #pragma unroll
-                for (int a = 0; a < NE; a++) er.wp[j][a] = __builtin_nontemporal_load(w + a * es);
+                for (int a = 0; a < NE; a++) er.wp[j][a] = w[a * es];
             }
         }
     }
