@@ -1,34 +1,36 @@
 #!/usr/bin/env python3
 """DJ-TLED time-step benchmark on one MI355X.
 
-Workload (synthetic, seeded): a 0.1 m cube of 64^3 voxels, meshed both as
-1,572,864 linear tetrahedra and as 262,144 one-point hexahedra with hourglass
-control (274,625 nodes each), neo-Hookean with E ~ U[2, 6] kPa per element,
-nu = 0.45, rho = 1000, jittered +-5 %, nodes and elements randomly permuted;
-bottom face fixed, top face compressed to -20 % with a smooth ramp over 1000
-steps; dt = 0.9 x the critical step; FP32.
-
-One benchmark step advances BOTH meshes by one explicit time step (element
-forces -> node reduction -> central difference with damping -> BCs).  The
-timed region runs K steps of each mesh as one persistent kernel launch per
-mesh, with the inputs resident in HBM.
+Headline workload (synthetic, seeded): a batch of 256 independent box
+instances with element counts log-uniform in [5k, 200k] (14.19M elements in
+total), each a fair coin between linear tetrahedra and one-point hexahedra
+with hourglass control and between neo-Hookean and transversely isotropic
+material, E ~ U[2, 6] kPa, nu = 0.45, rho = 1000, jittered +-5 %, permuted;
+bottom face fixed, top face moved by U[5 %, 20 %] of the height in a seeded
+downward direction with a smooth ramp over 500 steps; each instance at 0.9 x
+its own critical step; FP32.  One benchmark step advances every instance by
+one explicit time step (element forces -> node reduction -> central
+difference with damping -> BCs) in one persistent kernel launch replayed
+from a hipGraph, with the inputs resident in HBM.  Setup (pre-computation,
+autotuning, graph capture) precedes the W warmup steps; K steps are timed.
 
 Further measurements, reported under "extra" (each skippable):
-  * batch: 256 box instances (5k-200k elements, T4/H8 x NH/TI, own loads),
-    500 steps in one batched persistent launch from a hipGraph, autotuned;
-    aggregate element-steps/s and per-instance completion p50/p99;
-  * models: the config-1 cubes with each material model of Table 3 (NH,
-    TI, OT, MR): time per step, overhead over NH, and the ratio to the same
-    step with the classical TLED force;
-  * multi: k = 1, 2, 4, 8 compression cases per launch on the config-1
-    cubes (djtled_step_multi): time per step and element-steps/s over cases;
+  * cube64: the 64^3 cube as 1,572,864 tetrahedra and as 262,144 hexahedra
+    (NH, compression, FP32), one persistent launch of K steps per mesh;
+  * models: the 64^3 cubes with each material model of Table 3 (NH, TI, OT,
+    MR): time per step, overhead over NH, and the ratio to the same step with
+    the classical TLED force;
+  * multi: k = 1, 2, 4, 8 compression cases per launch on the 64^3 cubes
+    (djtled_step_multi): time per step and element-steps/s over cases;
   * realtime (--realtime): step time over cube sizes and the model sizes
     for one step per 33.3 ms / 2 ms (Sec. 5.5), checked at the 2 ms size;
   * relaxation: the ~1.2M-tet transversely isotropic ellipsoid relaxed to
     r <= 1e-3 in FP32 and finished to r <= 1e-6 in FP64;
+  * mlp: the full-size surrogate network's training and inference kernels;
   * warm start: surrogate trained on the GPU from relaxation steady states
-    of a ~6000-tet ellipsoid, steps and device time to 1e-3 relative
-    displacement error from the prediction vs from rest.
+    of a ~6000-tet ellipsoid; steps, device and wall time to 1e-3 relative
+    displacement error from the prediction vs from rest with the best of a
+    sweep of ramp lengths.
 
 Prints one JSON line (see the keys below).  --gpus N > 1 is not supported:
 the library runs on a single GPU.
@@ -46,53 +48,117 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-KERNEL_SRC = [os.path.join(ROOT, "paper_2106_14189_amd", "csrc", f) for f in ("djtled_kernels.hip", "djtled_device.h")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "djtled_step_cube64_t4_traffic.json")
+CSRC = os.path.join(ROOT, "paper_2106_14189_amd", "csrc")
+# sources of each measured kernel, and the committed counter summaries taken of it
+KERNELS = {
+    "batch": {"src": ["djtled_batch_kernels.hip", "djtled_device.h"],
+              "traffic": os.path.join(ROOT, "profiles", "djtled_batch_config3_traffic.json")},
+    "step": {"src": ["djtled_kernels.hip", "djtled_device.h"],
+             "traffic": os.path.join(ROOT, "profiles", "djtled_step_cube64_t4_traffic.json")},
+}
 METRIC = "DJ-TLED element-steps/sec + HBM GB/s; warm-start vs plain time-to-1e-3"
 
 
-def _src_sha() -> str:
-    """sha256 of the step kernel's sources (the kernel file and its device header)."""
+def _src_sha(kernel: str) -> str:
+    """sha256 of a kernel's sources (its kernel file and the device header)."""
     h = hashlib.sha256()
-    for f in KERNEL_SRC:
-        h.update(open(f, "rb").read())
+    for f in KERNELS[kernel]["src"]:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
     return h.hexdigest()
 
 
-def _traffic(bytes_scale_steps: int):
-    """HBM bytes per launch from committed rocprofv3 PMC counters (FETCH_SIZE +
-    WRITE_SIZE, calibrated on a plain copy), or None if the kernel changed
-    since they were taken."""
+def _traffic(kernel: str, steps: int):
+    """HBM bytes of `steps` steps from committed rocprofv3 PMC counters
+    (FETCH_SIZE + WRITE_SIZE per step, calibrated on a plain copy), or None if
+    the kernel's sources changed since they were taken."""
     try:
-        t = json.load(open(TRAFFIC_FILE))
+        t = json.load(open(KERNELS[kernel]["traffic"]))
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256") != _src_sha():
+    if t.get("kernel_source_sha256") != _src_sha(kernel):
         return None
-    return (t["fetch_bytes_per_step"] + t["write_bytes_per_step"]) * bytes_scale_steps
+    return (t["fetch_bytes_per_step"] + t["write_bytes_per_step"]) * steps
 
 
-def cpu_baseline(wls, n_steps: int) -> dict:
-    """The FP64 oracle, as it stands, on a bounded sample of the same workload."""
+def host_info() -> dict:
+    """Host CPU model and core counts (as lscpu / nproc would report them)."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    return {"cpu_model": model, "nproc": nproc, "cpu_count": os.cpu_count(),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+
+def _oracle_leg(spec, n_steps: int, omp: bool) -> tuple[int, float]:
+    """(element-steps, seconds) of the FP64 oracle stepping each instance of
+    spec from rest by n_steps steps of its own load (construction untimed)."""
     import numpy as np
 
     import oracle
 
-    total_es, total_t = 0, 0.0
-    for wl in wls:
-        m, mat, ld = wl.mesh, wl.material, wl.loads
-        ora = oracle.Oracle(m.X, m.conn, mat.E, mat.nu, rho=mat.rho, hg_kappa=mat.hg_kappa)
+    es, secs = 0, 0.0
+    for m, mat, ld, alpha in spec:
+        ora = oracle.Oracle(m.X, m.conn, mat.E, mat.nu, model=mat.model, rho=mat.rho, eta_ratio=mat.eta_ratio,
+                            fibre=mat.fibre, hg_kappa=mat.hg_kappa, omp=omp)
         dt = 0.9 * ora.dt_crit
+        t_ramp = -ld.t_ramp * dt if ld.t_ramp < 0 else ld.t_ramp
         u, up = np.zeros((m.n_nodes, 3)), np.zeros((m.n_nodes, 3))
         t0 = time.perf_counter()
-        rc, done, _ = ora.run(u, up, n_steps, dt, wl.alpha, ld.bc_node, ld.bc_mask, ld.bc_target, ramp=ld.ramp,
-                              t_ramp=1000 * dt)
-        total_t += time.perf_counter() - t0
-        assert rc == 0 and done == n_steps
-        total_es += m.n_elems * n_steps
-    return {"value": total_es / total_t, "unit": "element-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_steps} steps of each mesh from rest (single-threaded FP64 C oracle, gcc -O2)",
-            "seconds": round(total_t, 2)}
+        rc, done, _ = ora.run(u, up, n_steps, dt, alpha, ld.bc_node, ld.bc_mask, ld.bc_target, ramp=ld.ramp,
+                              t_ramp=t_ramp)
+        secs += time.perf_counter() - t0
+        assert rc == 0 and done == n_steps, (rc, done)
+        es += m.n_elems * n_steps
+        del ora
+    return es, secs
+
+
+def cpu_baseline(spec, n_steps: int, every: int = 16) -> dict:
+    """The FP64 oracle, as it stands, on a bounded sample of the batch: every
+    `every`-th instance stepped n_steps from rest, single-threaded and with its
+    element loop on all host cores (the OpenMP build of the same source)."""
+    import oracle
+
+    sample = spec[::every]
+    n_el = sum(m.n_elems for m, _, _, _ in sample)
+    es1, s1 = _oracle_leg(sample, n_steps, omp=False)
+    esn, sn = _oracle_leg(sample, n_steps, omp=True)
+    nthr = oracle.threads(omp=True)
+    what = (f"{len(sample)} of the {len(spec)} instances (every {every}th; {n_el} elements) x {n_steps} steps "
+            f"from rest; FP64 C oracle, gcc -O2")
+    return {"value": esn / sn, "unit": "element-steps/s", "cores": nthr, "kind": "oracle",
+            "sample": what + f"; element loop on {nthr} OpenMP threads", "seconds": round(sn, 2),
+            "single_thread": {"value": es1 / s1, "unit": "element-steps/s", "cores": 1, "kind": "oracle",
+                              "sample": what + "; one thread", "seconds": round(s1, 2)},
+            "host": host_info()}
+
+
+def copy_ceiling(nbytes: int = 2 << 30, reps: int = 10) -> dict:
+    """Achievable HBM bandwidth on this GPU in the same run: a device-to-device
+    copy of nbytes (read + write), timed with HIP events."""
+    import torch
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return {"GBps": 2.0 * nbytes / (ms / 1e3) / 1e9, "bytes_copied": nbytes, "ms": ms}
 
 
 def _pct(x, q):
@@ -100,45 +166,48 @@ def _pct(x, q):
     return float(np.percentile(np.asarray(x), q))
 
 
-def bench_batch(log, variant: int = -1) -> dict:
-    """Config-3 batch: 256 instances, 500 steps, autotuned (or a given kernel variant), graph replay."""
-    from paper_2106_14189_amd import solver as S
+def bench_cube64(log, K: int, Wm: int, variant: int = -1, meshes: str = "both") -> dict:
+    """The 64^3 compression cube as 1,572,864 T4 and as 262,144 H8 (NH, FP32,
+    E ~ U[2, 6] kPa, permuted): K steps of each mesh in one persistent launch
+    after Wm warmup steps; per-mesh kernel time (HIP events on the launch
+    stream), algorithmic bytes and, for T4, the committed counter traffic."""
+    import torch
+    from paper_2106_14189_amd import solver
     from paper_2106_14189_amd import workloads as W
-    t0 = time.perf_counter()
-    spec = W.config3()
-    ins = [S.Instance(m.X, m.conn, mat.E, mat.nu, model=mat.model, rho=mat.rho, eta_ratio=mat.eta_ratio,
-                      fibre=mat.fibre, hg_kappa=mat.hg_kappa, bc_node=ld.bc_node, bc_mask=ld.bc_mask,
-                      bc_target=ld.bc_target, ramp=ld.ramp, t_ramp=ld.t_ramp, alpha=al) for m, mat, ld, al in spec]
-    t_gen = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    b = S.Batch(ins, autotune=variant < 0, variant=variant)
-    t_build = time.perf_counter() - t0
-    info = b.info()
-    log(f"batch: {info['n_inst']} instances, {info['n_elems']} elements, variant {info['variant']}, "
-        f"chunk {info['chunk_elems']}, {info['n_items']} chunks on {info['grid_blocks']} workgroups")
-    n = 500
-    st = b.run(n)  # first run captures the graph
-    assert st.code == 0, st
-    b.reset()
-    t0 = time.perf_counter()
-    st = b.run(n)
-    wall = time.perf_counter() - t0
-    assert st.code == 0 and st.steps_done == n, st
-    lat = b.stats()
-    info = b.info()
-    ks = st.kernel_ms / 1e3
-    out = {"workload": "config3_256_boxes_t4h8_nhti_fp32", "instances": info["n_inst"], "elements": info["n_elems"],
-           "nodes": info["n_nodes"], "steps": n, "kernel_ms": st.kernel_ms, "wall_ms": wall * 1e3,
-           "element_steps_per_s": info["n_elems"] * n / ks, "ms_per_step": st.kernel_ms / n,
-           "bytes_per_step": info["bytes_per_step"],
-           "effective_GBps": info["bytes_per_step"] * n / ks / 1e9,
-           "latency_ms_p50": _pct(lat, 50), "latency_ms_p99": _pct(lat, 99),
-           "graph": info["graph"], "autotune": {"variant": info["variant"], "chunk_elems": info["chunk_elems"],
-                                                "steps_per_launch": info["steps_per_launch"],
-                                                "candidates": info["tune_candidates"],
-                                                "tune_ms": info["tune_ms"]},
-           "host_build_s": t_build, "host_gen_s": t_gen}
-    b.close()
+    elems = {"both": [W.T4, W.H8], "t4": [W.T4], "h8": [W.H8]}[meshes]
+    out = {"workload": "cube64_" + "+".join("t4" if e == W.T4 else "h8" for e in elems) + "_nh_fp32_compression",
+           "steps": K, "warmup": Wm}
+    tot_es, tot_s = 0, 0.0
+    for elem in elems:
+        wl = W.config1(elem)
+        tag = "t4" if elem == W.T4 else "h8"
+        kw = {} if variant < 0 else {"variant": variant}
+        sv = solver.from_workload(wl, **kw)
+        i = sv.info()
+        ld = wl.loads
+        ls = sv.loadset(ld.bc_node, ld.bc_mask, ld.bc_target, ld.ramp, 1000 * i["dt"])
+        u, up = sv.zeros(), sv.zeros()
+        st, step = sv.step(u, up, Wm, ls)
+        assert st.code == 0, st
+        st, step = sv.step(u, up, K, ls, step0=step)
+        torch.cuda.synchronize()
+        assert st.code == 0 and st.steps_done == K, st
+        assert bool(torch.isfinite(u).all())
+        km = st.kernel_ms
+        tot_es += i["n_elems"] * K
+        tot_s += km / 1e3
+        out[tag] = {"elems": i["n_elems"], "nodes": i["n_nodes"], "kernel_ms_per_step": km / K,
+                    "element_steps_per_s": i["n_elems"] * K / (km / 1e3), "bytes_per_step": i["bytes_per_step"],
+                    "bytes_per_element_step": i["bytes_per_step"] / i["n_elems"],
+                    "effective_GBps": i["bytes_per_step"] * K / (km / 1e3) / 1e9,
+                    "frac_of_hbm_peak": i["bytes_per_step"] * K / (km / 1e3) / 1e9 / HBM_PEAK_GBPS,
+                    "counter_traffic_bytes_per_step": (_traffic("step", 1) if elem == W.T4 else None),
+                    "dt": i["dt"], "grid": i["grid_blocks"], "chunks": i["n_chunks"],
+                    "chunk_elems": i["chunk_elems"], "variant": i["variant"]}
+        ls.close()
+        sv.close()
+        log(f"cube64 {tag}: {out[tag]}")
+    out["element_steps_per_s_both"] = tot_es / tot_s
     return out
 
 
@@ -292,33 +361,53 @@ def bench_multi(log, steps: int = 300) -> dict:
     return out
 
 
-def bench_relaxation(log) -> dict:
-    """Config 2: FP32 relaxation to 1e-3 (above its rounding floor), FP64 finish to 1e-6."""
+def bench_relaxation(log, ramps=(0.0, 0.05, 0.1, 0.2, 0.4)) -> dict:
+    """The ~1.2M-tet TI ellipsoid: FP32 dynamic relaxation to r <= 1e-3 (above
+    its FP32 rounding floor) for each load-ramp length in `ramps` (0: the load
+    applied at once; residual checks start when the ramp is complete), then
+    the fastest converged run finished in FP64 to r <= 1e-6."""
     import torch
     from paper_2106_14189_amd import solver as S
     from paper_2106_14189_amd import workloads as W
     wl = W.config2()
     ld = wl.loads
-    out = {"workload": wl.name, "elements": wl.mesh.n_elems, "nodes": wl.mesh.n_nodes}
+    ce = wl.extra["check_every"]
+    out = {"workload": wl.name, "elements": wl.mesh.n_elems, "nodes": wl.mesh.n_nodes, "check_every": ce,
+           "fp32_sweep": {}}
     s32 = S.from_workload(wl, precision="fp32")
-    ls = s32.loadset(ld.bc_node, ld.bc_mask, ld.bc_target, ld.ramp, wl.extra["t_ramp"])
-    u, up = s32.zeros(), s32.zeros()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st, step = s32.step(u, up, 400000, ls, relax=True, tol=1e-3, check_every=wl.extra["check_every"])
-    torch.cuda.synchronize()
-    out.update(fp32_steps=st.steps_done, fp32_residual=st.residual, fp32_kernel_ms=st.kernel_ms,
-               fp32_wall_ms=(time.perf_counter() - t0) * 1e3,
-               fp32_element_steps_per_s=wl.mesh.n_elems * st.steps_done / (st.kernel_ms / 1e3))
-    assert st.code == 1, st
+    best = None
+    for tr in ramps:
+        ls = s32.loadset(ld.bc_node, ld.bc_mask, ld.bc_target, ld.ramp, tr)
+        u, up = s32.zeros(), s32.zeros()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, step = s32.step(u, up, 400000, ls, relax=True, tol=1e-3, check_every=ce, raise_on_error=False)
+        torch.cuda.synchronize()
+        ls.close()
+        row = {"code": st.code, "steps": st.steps_done, "residual": st.residual, "kernel_ms": st.kernel_ms,
+               "wall_ms": (time.perf_counter() - t0) * 1e3,
+               "ramp_steps": int(round(tr / s32.info()["dt"])),
+               "element_steps_per_s": wl.mesh.n_elems * st.steps_done / max(st.kernel_ms / 1e3, 1e-12)}
+        out["fp32_sweep"][f"{tr:g}"] = row
+        log(f"relaxation t_ramp {tr:g} s: {row}")
+        if st.code == 1 and (best is None or st.steps_done < best[1]):
+            best = (tr, st.steps_done, u, up, step)
+    assert best is not None, out
+    tr, _, u, up, step = best
+    out.update(t_ramp=tr, fp32_steps=out["fp32_sweep"][f"{tr:g}"]["steps"],
+               fp32_kernel_ms=out["fp32_sweep"][f"{tr:g}"]["kernel_ms"],
+               fp32_element_steps_per_s=out["fp32_sweep"][f"{tr:g}"]["element_steps_per_s"])
     s64 = S.from_workload(wl, precision="fp64")
-    ls64 = s64.loadset(ld.bc_node, ld.bc_mask, ld.bc_target, ld.ramp, wl.extra["t_ramp"])
+    ls64 = s64.loadset(ld.bc_node, ld.bc_mask, ld.bc_target, ld.ramp, tr)
     u64, up64 = u.double(), up.double()
     t0 = time.perf_counter()
-    st64, _ = s64.step(u64, up64, 400000, ls64, step0=step, relax=True, tol=1e-6, check_every=wl.extra["check_every"])
+    st64, _ = s64.step(u64, up64, 400000, ls64, step0=step, relax=True, tol=1e-6, check_every=ce)
     torch.cuda.synchronize()
     out.update(fp64_steps=st64.steps_done, fp64_residual=st64.residual, fp64_kernel_ms=st64.kernel_ms,
                fp64_wall_ms=(time.perf_counter() - t0) * 1e3, converged=st64.code == 1)
+    ls64.close()
+    s32.close()
+    s64.close()
     log(f"relaxation: {out}")
     return out
 
@@ -395,20 +484,22 @@ def bench_warm_start_full(log) -> dict:
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--cpu-steps", type=int, default=50, help="oracle steps per mesh for cpu_baseline (0: skip)")
-    ap.add_argument("--variant", type=int, default=-1, help="kernel variant (-1: per-mesh default)")
-    ap.add_argument("--mesh", choices=["both", "t4", "h8"], default="both")
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=40,
+                    help="oracle steps per sampled instance for cpu_baseline (0: skip)")
+    ap.add_argument("--batch-variant", type=int, default=-1, help="batch kernel variant (-1: autotune)")
+    ap.add_argument("--variant", type=int, default=-1, help="cube64 kernel variant (-1: per-mesh default)")
+    ap.add_argument("--mesh", choices=["both", "t4", "h8"], default="both", help="cube64 meshes")
     ap.add_argument("--copy-calib", action="store_true",
                     help="after the run, copy a 256 MiB buffer 4 times (calibrates rocprofv3 byte counters)")
-    ap.add_argument("--no-batch", action="store_true", help="skip the 256-instance batch measurement")
-    ap.add_argument("--batch-variant", type=int, default=-1, help="batch kernel variant (-1: autotune)")
+    ap.add_argument("--no-cube", action="store_true", help="skip the 64^3 cube measurement")
     ap.add_argument("--no-models", action="store_true", help="skip the four-material-model measurement")
     ap.add_argument("--no-multi", action="store_true", help="skip the several-load-cases measurement")
     ap.add_argument("--no-relax", action="store_true", help="skip the ellipsoid relaxation measurement")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start measurement")
     ap.add_argument("--no-mlp", action="store_true", help="skip the full-size network timing")
+    ap.add_argument("--no-extra", action="store_true", help="skip every measurement under extra")
     ap.add_argument("--realtime", action="store_true",
                     help="also measure step time over cube sizes up to ~60M elements (real-time sizing)")
     ap.add_argument("--warm-full", action="store_true",
@@ -420,64 +511,70 @@ def main():
               f"(multi-GPU sharding is a design note, not built).", file=sys.stderr)
         sys.exit(2)
 
+    import math
+
     import torch
 
-    from paper_2106_14189_amd import solver
+    from paper_2106_14189_amd import solver as S
     from paper_2106_14189_amd import workloads as W
 
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     K, Wm = args.steps, args.warmup
-    elems = {"both": [W.T4, W.H8], "t4": [W.T4], "h8": [W.H8]}[args.mesh]
-    runs = []
-    for elem in elems:
-        wl = W.config1(elem)
-        kw = {} if args.variant < 0 else {"variant": args.variant}
-        sv = solver.from_workload(wl, **kw)
-        info = sv.info()
-        ld = wl.loads
-        ls = sv.loadset(ld.bc_node, ld.bc_mask, ld.bc_target, ld.ramp, 1000 * info["dt"])
-        u, up = sv.zeros(), sv.zeros()
-        st, step = sv.step(u, up, Wm, ls)
-        assert st.code == 0, st
-        runs.append(dict(elem=elem, wl=wl, sv=sv, info=info, ls=ls, u=u, up=up, step=step))
-    torch.cuda.synchronize()
-
     t0 = time.perf_counter()
-    for r in runs:
-        st, r["step"] = r["sv"].step(r["u"], r["up"], K, r["ls"], step0=r["step"])
-        r["status"] = st
+    spec = W.config3()
+    ins = [S.Instance(m.X, m.conn, mat.E, mat.nu, model=mat.model, rho=mat.rho, eta_ratio=mat.eta_ratio,
+                      fibre=mat.fibre, hg_kappa=mat.hg_kappa, bc_node=ld.bc_node, bc_mask=ld.bc_mask,
+                      bc_target=ld.bc_target, ramp=ld.ramp, t_ramp=ld.t_ramp, alpha=al) for m, mat, ld, al in spec]
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    b = S.Batch(ins, autotune=args.batch_variant < 0, variant=args.batch_variant)
+    del ins
+    t_build = time.perf_counter() - t0
+    info = b.info()
+    log(f"batch: {info['n_inst']} instances, {info['n_elems']} elements, variant {info['variant']}, "
+        f"chunk {info['chunk_elems']}, {info['n_items']} chunks on {info['grid_blocks']} workgroups, "
+        f"{info['steps_per_launch']} steps per launch")
+    # setup: capture the K-step and W-step graphs, then start from rest
+    for n in ([K, Wm] if Wm > 0 else [K]):
+        st = b.run(n)
+        assert st.code == 0, st
+    b.reset()
+    if Wm > 0:
+        st = b.run(Wm)
+        assert st.code == 0 and st.steps_done == Wm, st
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = b.run(K)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    for r in runs:
-        assert r["status"].code == 0 and r["status"].steps_done == K, r["status"]
-        assert bool(torch.isfinite(r["u"]).all())
-
-    tot_elems = sum(r["info"]["n_elems"] for r in runs)
-    value = tot_elems * K / wall
-    dom = max(runs, key=lambda r: r["status"].kernel_ms)
-    k_s = dom["status"].kernel_ms / 1000.0
-    achieved = dom["info"]["bytes_per_step"] * K / k_s / 1e9
-    traffic = _traffic(K) if dom["elem"] == W.T4 else None
-    cfg = {"workload": "cube64_" + "+".join("t4" if r["elem"] == W.T4 else "h8" for r in runs) + "_nh_fp32_compression",
-           "nodes": runs[0]["info"]["n_nodes"], "precision": "fp32", "steps_timed": K}
-    for r in runs:
-        tag = "t4" if r["elem"] == W.T4 else "h8"
-        i = r["info"]
-        km = r["status"].kernel_ms
-        cfg[f"{tag}_elems"] = i["n_elems"]
-        cfg[f"{tag}_kernel_ms_per_step"] = km / K
-        cfg[f"{tag}_element_steps_per_s"] = i["n_elems"] * K / (km / 1000.0)
-        cfg[f"{tag}_bytes_per_step"] = i["bytes_per_step"]
-        cfg[f"{tag}_bytes_per_element_step"] = i["bytes_per_step"] / i["n_elems"]
-        cfg[f"{tag}_effective_GBps"] = i["bytes_per_step"] * K / (km / 1000.0) / 1e9
-        cfg[f"{tag}_dt"] = i["dt"]
-        cfg[f"{tag}_grid"] = i["grid_blocks"]
-        cfg[f"{tag}_chunks"] = i["n_chunks"]
-        cfg[f"{tag}_chunk_elems"] = i["chunk_elems"]
-        cfg[f"{tag}_variant"] = i["variant"]
+    assert st.code == 0 and st.steps_done == K and st.kernel_ms > 0, st
+    info = b.info()
+    lat = b.stats()
+    bps = info["bytes_per_step"]
+    spl = info["steps_per_launch"] if info["steps_per_launch"] > 0 else K
+    launches = math.ceil(K / spl)
+    # HIP events on the launch stream around the replayed graph: the
+    # persistent launches of the run and their flag-reset kernels
+    k_s = st.kernel_ms / 1e3
+    achieved = bps * K / k_s / 1e9
+    traffic = _traffic("batch", K)
+    ceiling = copy_ceiling()
+    cfg = {"workload": "batch256_boxes_5k-200k_t4h8_nhti_fp32", "instances": info["n_inst"],
+           "elements": info["n_elems"], "nodes": info["n_nodes"], "precision": "fp32", "steps_timed": K,
+           "kernel_ms": st.kernel_ms, "kernel_ms_per_step": st.kernel_ms / K,
+           "element_steps_per_s_kernel": info["n_elems"] * K / k_s,
+           "bytes_per_step": bps, "bytes_per_element_step": bps / info["n_elems"],
+           "instance_latency_ms_p50": _pct(lat, 50), "instance_latency_ms_p99": _pct(lat, 99),
+           "graph": info["graph"],
+           "autotune": {"variant": info["variant"], "chunk_elems": info["chunk_elems"],
+                        "steps_per_launch": info["steps_per_launch"], "candidates": info["tune_candidates"],
+                        "tune_ms": info["tune_ms"]},
+           "grid": info["grid_blocks"], "block": info["block_threads"], "chunks": info["n_items"],
+           "host_build_s": t_build, "host_gen_s": t_gen}
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": info["n_elems"] * K / wall,
         "unit": "element-steps/s",
         "n_gpus": 1,
         "steps": K,
@@ -490,11 +587,15 @@ def main():
         "data": "synthetic",
         "config": cfg,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "kernel": "k_step (persistent fused DJ-TLED step), " + ("T4" if dom["elem"] == W.T4 else "H8"),
-                     "bytes_per_launch": dom["info"]["bytes_per_step"] * K,
-                     "launch_ms": dom["status"].kernel_ms},
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None if traffic is None else traffic / launches,
+                     "kernel": "k_batch_step (persistent fused DJ-TLED step of the whole batch)",
+                     "bytes_per_step": bps, "steps_per_launch": min(spl, K), "launches": launches,
+                     "bytes_per_launch": bps * min(spl, K), "launch_ms_avg": st.kernel_ms / launches,
+                     "copy_ceiling_GBps": ceiling["GBps"], "frac_of_copy_ceiling": achieved / ceiling["GBps"]},
     }
+    b.close()
+    del b
+    torch.cuda.synchronize()
     if args.copy_calib:
         x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")  # 256 MiB
         y = torch.empty_like(x)
@@ -502,30 +603,27 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         out["copy_calib_bytes"] = x.numel() * 4
-    if args.cpu_steps > 0:
-        out["cpu_baseline"] = cpu_baseline([r["wl"] for r in runs], args.cpu_steps)
-    else:
-        out["cpu_baseline"] = None
-    for r in runs:
-        r["sv"].close()
-    del runs
-    log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+        del x, y
+    out["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps) if args.cpu_steps > 0 else None
+    del spec
     extra = {}
-    for name, skip, fn in (("batch", args.no_batch, lambda lg: bench_batch(lg, args.batch_variant)),
+    for name, skip, fn in (("cube64", args.no_cube, lambda lg: bench_cube64(lg, K, Wm, args.variant, args.mesh)),
                            ("models", args.no_models, bench_models),
                            ("multi", args.no_multi, bench_multi),
                            ("realtime", not args.realtime, bench_realtime),
                            ("relaxation", args.no_relax, bench_relaxation),
                            ("mlp", args.no_mlp, bench_mlp), ("warm_start", args.no_warm, bench_warm_start),
                            ("warm_start_full", not args.warm_full, bench_warm_start_full)):
-        if skip:
+        if skip or (args.no_extra and name not in ("realtime", "warm_start_full")):
             continue
         try:
             extra[name] = fn(log)
         except Exception as e:  # reported, not hidden: the main line stays valid
             extra[name] = {"error": f"{type(e).__name__}: {e}"}
+        torch.cuda.synchronize()
         log(f"{name}: {json.dumps(extra[name])[:400]}")
     out["extra"] = extra
+    torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 

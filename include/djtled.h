@@ -218,7 +218,11 @@ typedef struct {
  * |(F - R)_free|_2 / |F_constrained|_2 of u^n is evaluated and the run stops
  * without advancing when it is <= tol (code DJ_CONVERGED).
  * On return state->u_cur / u_prev / step hold the last completed step; on
- * DJ_ERR_INVERTED that is the step before the failing one.  loads may be NULL
+ * DJ_ERR_INVERTED, and on DJ_ERR_NONFINITE found in an element, that is the
+ * step before the failing one.  A non-finite displacement produced at a node
+ * shared by several workgroup tiles is found only after the step that made
+ * it: that step then counts as done, the state holds the non-finite value and
+ * error_step names the step that produced it.  loads may be NULL
  * (free body, no external force).  Synchronises `stream` to read the status.
  */
 int djtled_step(djtled_ctx *ctx, djtled_state *state, const djtled_loadset *loads, int32_t n_steps,

@@ -21,30 +21,39 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "djtled_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# the same source built with OpenMP (all host cores; timing only, never parity)
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 NH, TI, OT, MR = 0, 1, 2, 3
 RAMP_NONE, RAMP_LINEAR, RAMP_SMOOTH = 0, 1, 2
 OK, CONVERGED, ERR_INVERTED, ERR_NONFINITE = 0, 1, -3, -4
 
 
+def _build_one(path: str, extra: list, force: bool) -> None:
+    if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        tmp = path + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", *extra, "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, path)
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, single thread)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+    """Compile the oracle with gcc: plain -O2, single thread (liboracle.so, the
+    one the tests use), and the same source with -fopenmp (liboracle_omp.so,
+    all host cores, for the CPU timing baseline only)."""
+    _build_one(_LIB, [], force)
+    _build_one(_LIB_OMP, ["-fopenmp"], force)
     return _LIB
 
 
-_lib = None
+_libs = {}
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+def _load(omp: bool = False):
+    path = _LIB_OMP if omp else _LIB
+    if path not in _libs:
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
             build(force=True)
-        lib = ctypes.CDLL(_LIB)
+        lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         D = ctypes.c_double
         I = ctypes.c_int
@@ -67,11 +76,13 @@ def _load():
         lib.ora_jacobian_invariants.argtypes = [dp, dp, dp, dp]
         lib.ora_lame.argtypes = [D, D, dp, dp]
         lib.ora_run.restype = I
-        lib.ora_run.argtypes = [P, dp, dp, dp, I, ip, ip, dp, I, D, D, D, ctypes.c_long, I, I, D, I, dp, ip]
+        lib.ora_run.argtypes = [P, dp, dp, dp, I, ip, ip, dp, I, D, D, D, ctypes.c_long, I, I, D, I, dp, ip, I]
+        lib.ora_threads.restype = I
+        lib.ora_threads.argtypes = []
         lib.ora_residual.restype = D
         lib.ora_residual.argtypes = [P, dp, dp, I, ip, ip]
-        _lib = lib
-    return _lib
+        _libs[path] = lib
+    return _libs[path]
 
 
 def _dp(a):
@@ -87,6 +98,11 @@ def _f64(a, shape=None):
     if shape is not None:
         a = a.reshape(shape)
     return a
+
+
+def threads(omp: bool = False) -> int:
+    """Threads the oracle's element loop uses in the given build."""
+    return _load(omp).ora_threads()
 
 
 def lame(E: float, nu: float):
@@ -110,8 +126,9 @@ class Oracle:
     """One mesh + material with Algorithm 1's pre-computation done in FP64."""
 
     def __init__(self, X, conn, E, nu, model=NH, eta_ratio=None, fibre=None, rho=1000.0, hg_kappa=0.1,
-                 eta_b_ratio=None, fibre_b=None, c01=None):
-        lib = _load()
+                 eta_b_ratio=None, fibre_b=None, c01=None, omp: bool = False):
+        """omp=True loads the all-cores build (same results; CPU timing baseline only)."""
+        lib = _load(omp)
         self.X = _f64(X)
         self.conn = np.ascontiguousarray(conn, dtype=np.int32)
         self.ne = self.conn.shape[1]
@@ -211,8 +228,9 @@ class Oracle:
         return self._lib.ora_energy(self._ctx, _dp(_f64(u, (self.n_nodes, 3))))
 
     def run(self, u_cur, u_prev, n_steps, dt, alpha, bc_node=None, bc_mask=None, bc_target=None, R=None,
-            ramp=RAMP_SMOOTH, t_ramp=0.0, step0=0, relax=False, tol=0.0, check_every=1):
-        """Advance (u_cur, u_prev) in place; returns (rc, steps_done, last_residual)."""
+            ramp=RAMP_SMOOTH, t_ramp=0.0, step0=0, relax=False, tol=0.0, check_every=1, anp=False):
+        """Advance (u_cur, u_prev) in place; returns (rc, steps_done, last_residual).
+        anp=True steps with the average-nodal-pressure force (forces_anp)."""
         assert u_cur.dtype == np.float64 and u_cur.flags.c_contiguous
         assert u_prev.dtype == np.float64 and u_prev.flags.c_contiguous
         if bc_node is None:
@@ -228,7 +246,7 @@ class Oracle:
         rc = self._lib.ora_run(self._ctx, _dp(u_cur), _dp(u_prev), Rp, len(bn), _ip(bn), _ip(bm), _dp(bt),
                                int(ramp), float(t_ramp), float(dt), float(alpha), int(step0), int(n_steps),
                                int(bool(relax)), float(tol), int(check_every), ctypes.byref(res),
-                               ctypes.byref(done))
+                               ctypes.byref(done), int(bool(anp)))
         return rc, done.value, res.value
 
     def residual(self, u, bc_node, bc_mask, R=None) -> float:

@@ -51,6 +51,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORA_NH 0
 #define ORA_TI 1
@@ -154,6 +157,10 @@ typedef struct {
     double *gam, *khg;        /* hourglass shape vectors (4 x 8) and stiffness */
     double *mass;             /* lumped nodal mass */
     double dt_crit;
+    /* all-cores timing build only: node -> (element, local node) incidences in
+       ascending element order, and a per-incidence force array */
+    int *inc_off, *inc;
+    double *fe;
 } ora_ctx;
 
 void ora_destroy(ora_ctx *c) {
@@ -162,6 +169,7 @@ void ora_destroy(ora_ctx *c) {
     free(c->eta_b); free(c->fibre_b); free(c->c01); free(c->m6); free(c->M2); free(c->I6m); free(c->I2m);
     free(c->J0); free(c->detJ0); free(c->V); free(c->G); free(c->m1); free(c->m4);
     free(c->I1m); free(c->I4m); free(c->dhdX); free(c->gam); free(c->khg); free(c->mass);
+    free(c->inc_off); free(c->inc); free(c->fe);
     free(c);
 }
 
@@ -417,7 +425,30 @@ ora_ctx *ora_create(int ne, int n_nodes, int n_elems, const double *X, const int
         if (L / cw < dtc) dtc = L / cw;
     }
     c->dt_crit = dtc;
+#ifdef _OPENMP
+    /* incidence lists for the all-cores assembly (see ora_forces) */
+    c->inc_off = (int *)calloc((size_t)c->n_nodes + 1, sizeof(int));
+    c->inc = (int *)malloc(sizeof(int) * E_ * ne);
+    c->fe = (double *)malloc(sizeof(double) * 3 * E_ * ne);
+    for (size_t q = 0; q < E_ * (size_t)ne; q++) c->inc_off[c->conn[q] + 1]++;
+    for (int n = 0; n < c->n_nodes; n++) c->inc_off[n + 1] += c->inc_off[n];
+    {
+        int *fill = (int *)malloc(sizeof(int) * ((size_t)c->n_nodes + 1));
+        memcpy(fill, c->inc_off, sizeof(int) * ((size_t)c->n_nodes + 1));
+        for (size_t q = 0; q < E_ * (size_t)ne; q++) c->inc[fill[c->conn[q]]++] = (int)q;
+        free(fill);
+    }
+#endif
     return c;
+}
+
+/* Threads the element loop uses (1 unless built with OpenMP). */
+int ora_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 double ora_dt_crit(const ora_ctx *c) { return c->dt_crit; }
@@ -593,6 +624,40 @@ static double force_djtled(const ora_ctx *c, int e, const double Ue[8][3], doubl
  * Returns 0, or -3 if some element has J <= 0 (its index in *bad_elem).
  */
 int ora_forces(const ora_ctx *c, const double *u, double *f, int route, int *bad_elem) {
+#ifdef _OPENMP
+    /* All-cores timing build (never used for parity): the element forces are
+       formed in parallel, then every node adds its incidences in ascending
+       element order -- the order of the loop below -- from zero, so the sums
+       are the serial ones bit for bit. */
+    {
+        const int ne = c->ne;
+        int first_bad = c->n_elems;
+#pragma omp parallel for schedule(static) reduction(min : first_bad)
+        for (int e = 0; e < c->n_elems; e++) {
+            double Ue[8][3], Fe[8][3];
+            gather_u(c, e, u, Ue);
+            double J = (route == 0) ? force_djtled(c, e, Ue, Fe) : force_tled(c, e, Ue, Fe);
+            if (!(J > 0.0) && e < first_bad) first_bad = e;
+            for (int a = 0; a < ne; a++)
+                for (int k = 0; k < 3; k++) c->fe[3 * ((size_t)e * ne + a) + k] = Fe[a][k];
+        }
+#pragma omp parallel for schedule(static)
+        for (int n = 0; n < c->n_nodes; n++) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+            for (int q = c->inc_off[n]; q < c->inc_off[n + 1]; q++) {
+                const double *g = c->fe + 3 * (size_t)c->inc[q];
+                s0 += g[0];
+                s1 += g[1];
+                s2 += g[2];
+            }
+            f[3 * n] = s0;
+            f[3 * n + 1] = s1;
+            f[3 * n + 2] = s2;
+        }
+        if (bad_elem) *bad_elem = first_bad < c->n_elems ? first_bad : -1;
+        return first_bad < c->n_elems ? -3 : 0;
+    }
+#endif
     memset(f, 0, sizeof(double) * 3 * (size_t)c->n_nodes);
     int rc = 0;
     if (bad_elem) *bad_elem = -1;
@@ -806,12 +871,13 @@ static double residual_of(const ora_ctx *c, const double *f, const double *R, co
  * bc_mask[j] (bit k) of constrained node bc_node[j].
  * relax != 0: every check_every steps once the ramp is complete, the residual of
  * u^n is evaluated first and the run stops, without advancing, if it is <= tol.
+ * anp != 0: F is the average-nodal-pressure internal force (ora_forces_anp).
  * Returns 0 (all steps done), 1 (converged), -3 (element inverted), -4 (non-finite).
  */
 int ora_run(const ora_ctx *c, double *u_cur, double *u_prev, const double *R, int n_bc, const int *bc_node,
             const int *bc_mask, const double *bc_target, int ramp, double t_ramp, double dt, double alpha,
             long step0, int n_steps, int relax, double tol, int check_every, double *residual_out,
-            int *steps_done) {
+            int *steps_done, int anp) {
     const int N3 = 3 * c->n_nodes;
     double *f = (double *)malloc(sizeof(double) * N3);
     double *un = (double *)malloc(sizeof(double) * N3);
@@ -827,7 +893,7 @@ int ora_run(const ora_ctx *c, double *u_cur, double *u_prev, const double *R, in
     for (s = 0; s < n_steps; s++) {
         long n = step0 + s;
         int bad;
-        if (ora_forces(c, u_cur, f, 0, &bad) != 0) { rc = -3; break; }
+        if ((anp ? ora_forces_anp(c, u_cur, f, &bad) : ora_forces(c, u_cur, f, 0, &bad)) != 0) { rc = -3; break; }
         if (relax && (s % check_every) == 0 && ramp_value(ramp, (double)n * dt, t_ramp) >= 1.0) {
             double r = residual_of(c, f, R, cmask);
             if (residual_out) *residual_out = r;

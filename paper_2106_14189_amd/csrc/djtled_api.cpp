@@ -716,6 +716,9 @@ int step_cases(djtled_ctx *ctx, int nrhs, djtled_state *st, const djtled_loadset
     DJ_HIP(hipStreamSynchronize(s));
     djtled_status r;
     r.code = c.h_status[4] ? DJ_ERR_BARRIER : c.h_status[0];
+    // an error of the last step's shared-node phase is left in a parity word
+    // (that step counts as done; the returned state holds the bad value)
+    if (r.code == DJ_OK) r.code = c.h_status[5] != 0 ? c.h_status[5] : c.h_status[6];
     r.steps_done = c.h_status[1];
     r.error_step = -1;
     r.error_elem = -1;

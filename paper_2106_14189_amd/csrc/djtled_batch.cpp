@@ -41,10 +41,15 @@ struct Batch {
     void *d_stage[4][2] = {};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipStream_t own = nullptr;   // runs of callers on the null stream (graphs need a real stream)
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
-    int g_steps = -1;
-    hipStream_t g_stream = nullptr;
+    // captured runs, one per (steps, stream), the most recent last
+    struct Graph {
+        int steps;
+        hipStream_t stream;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    static constexpr size_t MAX_GRAPHS = 4;
+    std::vector<Graph> graphs;
     int graph_used = 0;
     int64_t step = 0;
     int cur = 0;
@@ -58,8 +63,10 @@ void destroy_batch(Batch *b) {
     if (!b) return;
     hipSetDevice(b->device);
     hipDeviceSynchronize();
-    if (b->gexec) hipGraphExecDestroy(b->gexec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    for (auto &g : b->graphs) {
+        hipGraphExecDestroy(g.exec);
+        hipGraphDestroy(g.graph);
+    }
     for (int k = 0; k < 4; k++) {
         if (b->kc[k]) free_all(b->kc[k]);  // frees the kind's load sets too
         for (int j = 0; j < 2; j++)
@@ -341,31 +348,30 @@ int run_batch(Batch &b, int n_steps, djtled_status *out, hipStream_t s) {
     }
     b.error_inst = -1;
     if (n_steps > 0) {
-        bool replay = false;
+        hipGraphExec_t exec = nullptr;
         if (b.use_graph) {
-            if (b.gexec && b.g_steps == n_steps && b.g_stream == s) {
-                replay = true;
-            } else {
-                if (b.gexec) hipGraphExecDestroy(b.gexec);
-                if (b.graph) hipGraphDestroy(b.graph);
-                b.gexec = nullptr;
-                b.graph = nullptr;
-                b.g_steps = -1;
+            for (const auto &g : b.graphs)
+                if (g.steps == n_steps && g.stream == s) exec = g.exec;
+            if (!exec) {
+                if (b.graphs.size() >= Batch::MAX_GRAPHS) {  // drop the oldest capture
+                    DJ_HIP(hipStreamSynchronize(b.graphs.front().stream));
+                    hipGraphExecDestroy(b.graphs.front().exec);
+                    hipGraphDestroy(b.graphs.front().graph);
+                    b.graphs.erase(b.graphs.begin());
+                }
                 // capture; a runtime that cannot record cooperative launches
                 // leaves the batch on direct launches
                 if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
                     const hipError_t ec = enqueue_run(b, n_steps, s);
                     hipGraph_t g = nullptr;
                     const hipError_t ee = hipStreamEndCapture(s, &g);
+                    hipGraphExec_t x = nullptr;
                     if (ec == hipSuccess && ee == hipSuccess && g &&
-                        hipGraphInstantiate(&b.gexec, g, nullptr, nullptr, 0) == hipSuccess) {
-                        b.graph = g;
-                        b.g_steps = n_steps;
-                        b.g_stream = s;
-                        replay = true;
+                        hipGraphInstantiate(&x, g, nullptr, nullptr, 0) == hipSuccess) {
+                        b.graphs.push_back(Batch::Graph{n_steps, s, g, x});
+                        exec = x;
                     } else {
                         if (g) hipGraphDestroy(g);
-                        b.gexec = nullptr;
                         (void)hipGetLastError();
                         b.use_graph = 0;
                     }
@@ -375,9 +381,10 @@ int run_batch(Batch &b, int n_steps, djtled_status *out, hipStream_t s) {
                 }
             }
         }
+        const bool replay = exec != nullptr;
         DJ_HIP(hipEventRecord(b.ev0, s));
         if (replay) {
-            DJ_HIP(hipGraphLaunch(b.gexec, s));
+            DJ_HIP(hipGraphLaunch(exec, s));
         } else {
             DJ_HIP(enqueue_run(b, n_steps, s));
         }
@@ -392,6 +399,8 @@ int run_batch(Batch &b, int n_steps, djtled_status *out, hipStream_t s) {
         float ms = 0.0f;
         r.kernel_ms = hipEventElapsedTime(&ms, b.ev0, b.ev1) == hipSuccess ? double(ms) : -1.0;
         r.code = b.h_status[4] ? DJ_ERR_BARRIER : b.h_status[0];
+        // an error of the last step's shared-node phase is left in a parity word
+        if (r.code == DJ_OK) r.code = b.h_status[5] != 0 ? b.h_status[5] : b.h_status[6];
         r.steps_done = int32_t(b.h_clock[0] - b.step);
         // per-instance completion: latest end stamp of its workgroups after the earliest start
         uint64_t t0 = std::numeric_limits<uint64_t>::max();
@@ -405,7 +414,7 @@ int run_batch(Batch &b, int n_steps, djtled_status *out, hipStream_t s) {
     if (r.code == DJ_ERR_BARRIER) {
         g_err = "batch kernel grid barrier timed out";
     } else if (r.code == DJ_ERR_INVERTED || r.code == DJ_ERR_NONFINITE) {
-        r.error_step = b.step + r.steps_done;
+        r.error_step = b.h_status[3];  // absolute step index of the failing step
         const int w = b.h_status[2];
         if (w >= 0) {
             const int k = w >> 28;

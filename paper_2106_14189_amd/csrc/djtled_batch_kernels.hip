@@ -157,7 +157,7 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK)) k_batch_step(BatchDev bd
                 // kind << 28 | element, or kind << 28 | 1 << 27 | copy for a node-level error
                 bd.status[2] = po.bad_elem >= 0 ? ((bad_kind << 28) | po.bad_elem)
                              : po.bad_elem <= -2 ? ((bad_kind << 28) | (1 << 27) | (-2 - po.bad_elem)) : -1;
-                bd.status[3] = s;
+                bd.status[3] = int32_t(n);  // absolute step index
             }
         }
         if (!grid_barrier(bd.bar, G, epoch, bd.status)) {
@@ -178,6 +178,7 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK)) k_batch_step(BatchDev bd
                 CS::template shared_finish<1, KB>(bd.k[KC].tp, sr, sp, po);
                 CS::template shared_batch<1, KB>(bd.k[KC].tp, s_ch, nb0, 1, sp, po);
             });
+        int late_kind = po.bad ? kind0 : -1;
         for (int k0 = nb0; k0 < nmine;) {
             const int nb = batch_len(k0);
             const int kind = __builtin_amdgcn_readfirstlane(s_kind[k0]);
@@ -186,8 +187,12 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK)) k_batch_step(BatchDev bd
                 const StepPtrs<T> sp = kind_ptrs<T>(bd.k[KC], cur, prv, nxt, s, n);
                 CS::template shared_batch<1, KB>(bd.k[KC].tp, s_ch + k0, nb, 0, sp, po);
             });
+            if (po.bad && late_kind < 0) late_kind = kind;
             k0 += nb;
         }
+        // a node-level error of the shared-node phase stops the run at the next barrier
+        if (po.bad && po.bad_elem <= -2)
+            publish_late_error(bd.status, s, po.bad, (late_kind << 28) | (1 << 27) | (-2 - po.bad_elem), int32_t(n));
         __syncthreads();  // shared copies written above are read by other threads next step
         cur = nxt;
     }
@@ -210,9 +215,16 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK)) k_batch_step(BatchDev bd
 __global__ void k_batch_reset(uint32_t *sync, int n_sync, int32_t *status, int clear_status) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_sync; i += gridDim.x * blockDim.x) sync[i] = 0u;
     // a run starts with a clear status; later launches of the run keep the
-    // code, error and abort words and clear only the per-parity error words
+    // code, error and abort words and clear only the per-parity error words,
+    // after making an error that the previous launch found in its last step's
+    // shared-node phase (left in a parity word) the run's code
     if (clear_status && blockIdx.x == 0 && threadIdx.x < 8) status[threadIdx.x] = threadIdx.x == 2 ? -1 : 0;
-    if (!clear_status && blockIdx.x == 0 && (threadIdx.x == 5 || threadIdx.x == 6)) status[threadIdx.x] = 0;
+    if (!clear_status && blockIdx.x == 0 && threadIdx.x == 0) {
+        const int32_t late = status[5] != 0 ? status[5] : status[6];
+        if (status[0] == 0 && late != 0) status[0] = late;
+        status[5] = 0;
+        status[6] = 0;
+    }
 }
 
 // canonical copies -> caller-order arrays of the kind's instances

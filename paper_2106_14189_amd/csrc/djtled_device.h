@@ -856,6 +856,22 @@ struct Chunk {
     }
 };
 
+// A node-level error raised in the shared-node phase of step s (a non-finite
+// u^{n+1} at a copy of a node shared by several chunks) is found after that
+// step's grid barrier, when the other workgroups have moved on.  It goes to
+// the error word of parity s + 1: every workgroup reads that word after the
+// next barrier and stops there with step s counted as done (its state holds
+// the non-finite value); after a launch's last step the host reads the word.
+// No workgroup reads parity s + 1 between the two barriers, so the word is free.
+__device__ __forceinline__ void publish_late_error(int32_t *status, int s, int code, int32_t where, int32_t step_word,
+                                                   int32_t case_word = -1) {
+    if (atomicCAS(&status[5 + ((s + 1) & 1)], 0, code) == 0) {
+        status[2] = where;
+        status[3] = step_word;
+        if (case_word >= 0) status[7] = case_word;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // block-wide sum of two doubles in a fixed order (result valid in thread 0)
 // ---------------------------------------------------------------------------

@@ -118,6 +118,7 @@ __global__ void __launch_bounds__(BLOCK, WPE) k_step(DevTopo tp, StepArgs a) {
         C::template shared_finish<1, KB>(tp, sr, sp, po);
         for (int k0 = 0; k0 < nmine; k0 += KB)
             C::template shared_batch<1, KB>(tp, s_ch + k0, min(KB, nmine - k0), k0 == 0 ? 1 : 0, sp, po);
+        if (po.bad) publish_late_error(a.status, s, po.bad, po.bad_elem, s);
         if (check) {
             double x = po.num, y = po.den;
             block_sum2<BLOCK>(x, y, sred);
@@ -323,6 +324,7 @@ __global__ void __launch_bounds__(BLOCK, WPE) k_step_multi(DevTopo tp, StepArgs 
                 C::template shared_batch<1, KB>(tp, s_ch + k0, min(KB, nmine - k0), 0, sp, po);
             after_case(r);
         }
+        if (po.bad) publish_late_error(a.status, s, po.bad, po.bad_elem, s, max(bad_rhs, 0));
         if (check) {
             // per workgroup and case: (|F - R|^2 over free, |F|^2 over constrained) components
             double *red = a.red + size_t(s & 1) * 2 * G * R;

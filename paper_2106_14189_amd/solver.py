@@ -7,6 +7,7 @@ libdjtled.so.
 from __future__ import annotations
 
 import ctypes
+import sys
 from dataclasses import dataclass
 
 import numpy as np
@@ -106,6 +107,10 @@ class Solver:
             self.handle = None
 
     def __del__(self):
+        # nothing is released while the interpreter shuts down: the HIP
+        # runtime may already be torn down by then (close() explicitly)
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -313,6 +318,10 @@ class Batch:
             self.handle = None
 
     def __del__(self):
+        # nothing is released while the interpreter shuts down: the HIP
+        # runtime may already be torn down by then (close() explicitly)
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -61,9 +61,10 @@ def _instances(S, spec):
     return ins
 
 
-def _oracle_run(mesh, mat, ld, alpha, dt, n_steps):
+def _oracle_run(mesh, mat, ld, alpha, dt, n_steps, omp=False):
+    # omp: the all-cores build, equal to the serial oracle bit for bit (pinned on the CPU)
     ora = oracle.Oracle(mesh.X, mesh.conn, mat.E, mat.nu, model=mat.model, rho=mat.rho, eta_ratio=mat.eta_ratio,
-                        fibre=mat.fibre, hg_kappa=mat.hg_kappa)
+                        fibre=mat.fibre, hg_kappa=mat.hg_kappa, omp=omp)
     np.testing.assert_allclose(dt, 0.9 * ora.dt_crit, rtol=1e-12)
     u, up = np.zeros((mesh.n_nodes, 3)), np.zeros((mesh.n_nodes, 3))
     t_ramp = ld.t_ramp if ld.t_ramp >= 0 else -ld.t_ramp * dt
@@ -180,8 +181,10 @@ def test_batch_autotune_picks_a_candidate(S):
 def test_full_size_config3_sampled_against_oracle(S):
     """Config 3 at full size (256 instances, ~14.2M elements, 500 steps) in
     the launch configuration the benchmark times (autotuned, graph replay):
-    every instance finite, and the three smallest instances against the
-    oracle (<= 1e-4)."""
+    every instance finite, and against the oracle (<= 1e-4) the three
+    smallest instances and the largest instance of each element kind
+    (T4 / H8 x NH / TI, up to 200k elements with many chunks and shared-node
+    groups each)."""
     spec = W.config3()
     say(f"config3: {len(spec)} instances, {sum(m.n_elems for m, _, _, _ in spec)} elements")
     b = S.Batch(_instances(S, spec), autotune=True)
@@ -192,10 +195,15 @@ def test_full_size_config3_sampled_against_oracle(S):
     assert b.info()["graph"] == 1
     for i in range(len(spec)):
         assert torch.isfinite(b.read(i)).all(), i
-    order = np.argsort([m.n_elems for m, _, _, _ in spec])[:3]
+    sizes = np.array([m.n_elems for m, _, _, _ in spec])
+    order = list(np.argsort(sizes)[:3])
+    for ne_, model in ((4, W.NH), (4, W.TI), (8, W.NH), (8, W.TI)):
+        kind = [i for i, (m, mat, _, _) in enumerate(spec) if m.ne == ne_ and mat.model == model]
+        order.append(max(kind, key=lambda i: sizes[i]))
     for i in order:
         mesh, mat, ld, alpha = spec[i]
-        uo = _oracle_run(mesh, mat, ld, alpha, b.instance(int(i))["dt"], 500)
+        say(f"  oracle: instance {i} ({mesh.n_elems} elements)")
+        uo = _oracle_run(mesh, mat, ld, alpha, b.instance(int(i))["dt"], 500, omp=True)
         err = np.abs(b.read(int(i)).double().cpu().numpy() - uo).max() / np.abs(uo).max()
         say(f"  instance {i} ({mesh.ne}-node, model {mat.model}, {mesh.n_elems} el): rel error {err:.2e}")
         assert err <= 1e-4

@@ -388,3 +388,39 @@ def test_full_size_config1_forces_and_steps(S, elem):
     err = np.abs(fg - fo).max() / np.abs(fo).max()
     say(f"  rel max-norm force error {err:.3e}")
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("tag", ["t4", "h8"])
+def test_full_size_config1_full_run_against_oracle(S, tag):
+    """Config 1 at full size for its whole run (1000 steps of the 64^3
+    compression cube, 1,572,864 T4 / 262,144 H8), as ONE persistent launch in
+    the configuration the benchmark times (automatic kernel variant): the final
+    displacement against the FP64 oracle's at 8192 sampled nodes, relative to
+    the oracle's max-norm over the whole field, <= 1e-4; the field's max-norm
+    and 2-norm within 1e-4.  The oracle's values were written by
+    tests/golden/make_cube64_reference.py (oracle only)."""
+    import importlib.util
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_cube64_reference", os.path.join(here, "make_cube64_reference.py"))
+    ref_mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(ref_mod)
+    ref = np.load(ref_mod.path_for(tag))
+    wl = W.config1(W.T4 if tag == "t4" else W.H8)
+    assert str(ref["fingerprint"]) == ref_mod.fingerprint(wl), "inputs differ from the stored oracle run"
+    n = int(ref["steps"])
+    sv = S.from_workload(wl)
+    dt = sv.info()["dt"]
+    assert abs(dt - float(ref["dt"])) <= 1e-12 * dt
+    wl.loads.t_ramp = n * float(ref["dt"])
+    say(f"config1 {tag}: gpu {n} steps in one launch (variant {sv.info()['variant']})")
+    u, _ = _run_gpu(sv, wl, n)
+    ug = u.double().cpu().numpy()
+    sv.close()
+    umax, unorm = float(ref["umax"]), float(ref["unorm"])
+    err = np.abs(ug[ref["nodes"]] - ref["u"]).max() / umax
+    say(f"  sampled rel max-norm error {err:.3e}; max-norm {np.abs(ug).max():.6e} vs {umax:.6e}; "
+        f"2-norm {np.linalg.norm(ug):.6e} vs {unorm:.6e}")
+    assert err <= 1e-4
+    assert abs(np.abs(ug).max() - umax) <= 1e-4 * umax
+    assert abs(np.linalg.norm(ug) - unorm) <= 1e-4 * unorm

@@ -434,8 +434,12 @@ def _uniaxial_case(elem, model):
     return mesh, o, np.array(nodes), np.array(masks), np.array(tg, float), E, nu, eta_r, a
 
 
-@pytest.mark.parametrize("elem,model", [(W.T4, W.NH), (W.H8, W.NH), (W.T4, W.TI)])
-def test_dynamic_relaxation_reaches_homogeneous_uniaxial_state(elem, model):
+@pytest.mark.parametrize("elem,model,anp", [(W.T4, W.NH, False), (W.H8, W.NH, False), (W.T4, W.TI, False),
+                                            (W.T4, W.NH, True), (W.H8, W.TI, True)])
+def test_dynamic_relaxation_reaches_homogeneous_uniaxial_state(elem, model, anp):
+    """Roller-supported cube relaxed under 20 % compression reaches the
+    homogeneous uniaxial state.  With the average nodal pressure (anp) every
+    J_e is equal at that state, so ANP stepping must reach it as well."""
     mesh, o, bn, bm, bt, E, nu, eta_r, a = _uniaxial_case(elem, model)
     mu, ka = _lame(E, nu)
     eta = eta_r * mu
@@ -460,7 +464,7 @@ def test_dynamic_relaxation_reaches_homogeneous_uniaxial_state(elem, model):
     alpha = 40.0
     u, up = np.zeros((mesh.n_nodes, 3)), np.zeros((mesh.n_nodes, 3))
     rc, done, res = o.run(u, up, 200000, dt, alpha, bc_node=bn, bc_mask=bm, bc_target=bt,
-                          ramp=W.RAMP_SMOOTH, t_ramp=200 * dt, relax=True, tol=1e-9, check_every=10)
+                          ramp=W.RAMP_SMOOTH, t_ramp=200 * dt, relax=True, tol=1e-9, check_every=10, anp=anp)
     assert rc == oracle.CONVERGED, (rc, done, res)
     exact = mesh.X * lam - mesh.X
     assert np.abs(u - exact).max() <= 1e-7 * np.abs(exact).max()
@@ -514,3 +518,24 @@ def test_anp_rigid_motion_gives_zero_force():
     u = mesh.X @ Q.T - mesh.X + np.array([0.01, -0.02, 0.005])
     ref = np.abs(o.forces_anp(mesh.X * 0.01)).max()
     assert np.abs(o.forces_anp(u)).max() <= 1e-10 * ref
+
+
+@pytest.mark.parametrize("elem,model", [(W.T4, W.NH), (W.H8, W.TI)])
+def test_all_cores_build_equals_serial_build_bitwise(elem, model):
+    """The OpenMP build (CPU timing baseline, reference generation) forms the
+    same node sums in the same order as the serial oracle: forces and a
+    30-step run agree bit for bit."""
+    mesh, o1, E, nu, kw, rng = _small_case(elem, model, n=5, seed=3)
+    o2 = oracle.Oracle(mesh.X, mesh.conn, E, nu, model=model, omp=True, **kw)
+    u = rng.normal(size=(mesh.n_nodes, 3)) * 1e-3
+    assert np.array_equal(o1.forces(u), o2.forces(u))
+    ld = W.compression_loads(mesh, -0.1, W.RAMP_SMOOTH, 30 * 0.9 * o1.dt_crit)
+    st = []
+    for o in (o1, o2):
+        uc, up = np.zeros((mesh.n_nodes, 3)), np.zeros((mesh.n_nodes, 3))
+        rc, done, _ = o.run(uc, up, 30, 0.9 * o1.dt_crit, 20.0, ld.bc_node, ld.bc_mask, ld.bc_target, ramp=ld.ramp,
+                            t_ramp=ld.t_ramp)
+        assert rc == 0 and done == 30
+        st.append((uc, up))
+    assert np.array_equal(st[0][0], st[1][0]) and np.array_equal(st[0][1], st[1][1])
+    assert np.abs(st[0][0]).max() > 0
