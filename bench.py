@@ -334,11 +334,12 @@ def bench_multi(log, steps: int = 300) -> dict:
     from paper_2106_14189_amd import solver as S
     from paper_2106_14189_amd import workloads as W
     out = {"workload": "cube64_t4+h8_nh_fp32_compression_k_cases", "steps": steps}
-    for elem in (W.T4, W.H8):
+    for elem, variant in ((W.T4, -1), (W.T4, 2), (W.H8, -1)):
         wl = W.config1(elem)
-        tag = "t4" if elem == W.T4 else "h8"
-        sv = S.from_workload(wl)
+        sv = S.from_workload(wl, variant=variant)
         info = sv.info()
+        tag = ("t4" if elem == W.T4 else "h8") + ("" if variant < 0 else f"_v{variant}")
+        out[f"{tag}_variant"] = info["variant"]
         per = {}
         for k in (1, 2, 4, 8):
             lss = []
@@ -356,6 +357,8 @@ def bench_multi(log, steps: int = 300) -> dict:
             out[f"{tag}_k{k}_element_steps_per_s"] = k * info["n_elems"] / (us * 1e-6)
             for ls in lss:
                 ls.close()
+        for k in (2, 4, 8):
+            out[f"{tag}_k{k}_per_case_over_k1"] = per[k] / k / per[1]
         log(f"multi {tag}: " + ", ".join(f"k={k} {v:.1f} us ({v / k:.1f} per case)" for k, v in per.items()))
         sv.close()
     return out

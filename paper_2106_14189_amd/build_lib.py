@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdjtled.so")
 SOURCES = ["djtled_api.cpp", "djtled_batch.cpp", "djtled_kernels.hip", "djtled_batch_kernels.hip",
-           "djtled_mlp.hip"]
+           "djtled_mlp.hip"] + [f"djtled_inst_{t}.hip" for t in ("f4", "f8", "d4", "d8", "c4", "c8")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # packed-FP32 instructions are disabled for every HIP translation unit

@@ -79,6 +79,11 @@ __host__ __device__ constexpr int hgG(int al, int a) {
 static_assert(h8s(0, 0) == -1 && h8s(1, 0) == 1 && h8s(2, 0) == 1 && h8s(3, 0) == -1, "H8 order");
 static_assert(h8s(2, 1) == 1 && h8s(3, 1) == 1 && h8s(4, 1) == -1 && h8s(7, 2) == 1, "H8 order");
 
+__device__ __forceinline__ double det3d(const double m[3][3]) {
+    return m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) - m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+           m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+}
+
 __device__ __forceinline__ double ramp_value(int ramp, double t, double t_ramp) {
     if (ramp == DJ_RAMP_NONE || t_ramp <= 0.0) return 1.0;
     double tau = t / t_ramp;

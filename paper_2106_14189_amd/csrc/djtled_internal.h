@@ -238,4 +238,28 @@ hipError_t launch_export(Ctx &c, double *d_V, double *d_dhdX, double *d_mass, hi
 // internal forces with the average nodal pressure (u, f: caller order)
 hipError_t launch_forces_anp(Ctx &c, const void *u, void *f, hipStream_t s);
 
+// One launcher operation for one (precision, element type, form), dispatched
+// over (model, variant) by the instantiating unit inst_<p><ne> (f: FP32,
+// d: FP64, c: FP32 classical TLED form).
+enum class Op { OCC, OCC_MULTI, FORCES, STEP, FORCES_ANP };
+struct OpArgs {
+    Op op = Op::OCC;
+    Ctx *c = nullptr;
+    int model = DJ_NH, variant = 0;
+    int *bpc = nullptr;          // OCC, OCC_MULTI: workgroups per CU
+    size_t *lds = nullptr;       // OCC: dynamic LDS bytes
+    const void *u = nullptr;     // FORCES, FORCES_ANP: caller-order u and f
+    void *f = nullptr;
+    hipStream_t s = nullptr;
+    const StepArgs *a = nullptr;  // STEP
+    const void *u_cur_in = nullptr, *u_prev_in = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+hipError_t inst_f4(const OpArgs &o);
+hipError_t inst_f8(const OpArgs &o);
+hipError_t inst_d4(const OpArgs &o);
+hipError_t inst_d8(const OpArgs &o);
+hipError_t inst_c4(const OpArgs &o);
+hipError_t inst_c8(const OpArgs &o);
+
 }  // namespace dj
