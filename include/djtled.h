@@ -36,6 +36,7 @@
 #ifndef DJTLED_H
 #define DJTLED_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -154,6 +155,28 @@ int djtled_info(const djtled_ctx *ctx, djtled_info_t *out);
  * Errors: DJ_ERR_ARG, DJ_ERR_HIP.
  */
 int djtled_forces(djtled_ctx *ctx, const void *u_dev, void *f_dev, void *stream);
+
+/*
+ * djtled_forces_noalloc -- djtled_forces for callers that cannot allocate
+ * device memory at call time (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments, kernels and
+ * result (bit for bit) as djtled_forces, but the per-call scratch -- the
+ * node-copy displacement planes and the shared-node partial sums --
+ * lives in one fixed device array of DJTLED_NOALLOC_SCRATCH_BYTES per GPU,
+ * owned by the library and held until the process ends; the call itself
+ * makes no allocation.  The array's address on the context's GPU is looked
+ * up when the context is created (djtled_precompute).  The scratch needed is
+ * 3 x (copies + max(shared-node partial entries, 1)) values of the context's
+ * precision (the node copies are at most n_elems x elem_type); a context
+ * needing more is refused with DJ_ERR_UNSUPPORTED and a message giving both
+ * sizes.  No part of the array needs clearing: every entry a call reads was
+ * written earlier in the same call.  All calls on one GPU share the array:
+ * calls that overlap in time on one GPU (any contexts, any streams) race and
+ * must be ordered by the caller.
+ * Errors: DJ_ERR_ARG, DJ_ERR_UNSUPPORTED, DJ_ERR_HIP.
+ */
+#define DJTLED_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int djtled_forces_noalloc(djtled_ctx *ctx, const void *u_dev, void *f_dev, void *stream);
 
 /*
  * djtled_forces_anp -- djtled_forces with the average nodal pressure (the

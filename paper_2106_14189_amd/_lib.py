@@ -118,6 +118,7 @@ EXPORTS = {
     "djtled_info": (ctypes.c_int, [_vp, ctypes.POINTER(djtled_info_t)]),
     "djtled_forces": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "djtled_forces_anp": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "djtled_forces_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "djtled_loadset_create": (ctypes.c_int, [_vp, ctypes.POINTER(djtled_loads), ctypes.POINTER(_vp)]),
     "djtled_loadset_destroy": (ctypes.c_int, [_vp]),
     "djtled_step": (ctypes.c_int, [_vp, ctypes.POINTER(djtled_state), _vp, ctypes.c_int32,

@@ -793,6 +793,11 @@ int djtled_precompute(const djtled_mesh *mesh, const djtled_material *mat, const
         return fail(DJ_ERR_HIP, "hipSetDevice failed");
     }
     int rc = build(*c, mesh, mat, prm);
+    // set-up of the allocation-free entry point on this GPU (once per device):
+    // the device address of its fixed scratch array
+    void *scr = nullptr;
+    if (rc == DJ_OK && noalloc_scratch(dev, &scr) != hipSuccess)
+        rc = fail(DJ_ERR_HIP, "hipGetSymbolAddress of the fixed scratch array failed");
     if (rc != DJ_OK) {
         std::string msg = g_err;
         free_all(c);
@@ -839,6 +844,25 @@ int djtled_forces(djtled_ctx *ctx, const void *u_dev, void *f_dev, void *stream)
     Ctx &c = *reinterpret_cast<Ctx *>(ctx);
     DJ_HIP(hipSetDevice(c.device));
     DJ_HIP(launch_forces(c, u_dev, f_dev, static_cast<hipStream_t>(stream)));
+    return DJ_OK;
+}
+
+int djtled_forces_noalloc(djtled_ctx *ctx, const void *u_dev, void *f_dev, void *stream) {
+    if (!ctx || !u_dev || !f_dev) return fail(DJ_ERR_ARG, "null argument");
+    Ctx &c = *reinterpret_cast<Ctx *>(ctx);
+    if (c.n_inst > 1) return fail(DJ_ERR_ARG, "batch contexts have no forces entry point");
+    const size_t ts = c.prec == DJ_FP32 ? sizeof(float) : sizeof(double);
+    const size_t ubytes = (size_t(3) * c.topo.n_copies * ts + 255) & ~size_t(255);
+    const size_t need = ubytes + size_t(3) * std::max(c.topo.n_part, 1) * ts;
+    if (need > noalloc_scratch_bytes())
+        return fail(DJ_ERR_UNSUPPORTED, "djtled_forces_noalloc: this context needs " + std::to_string(need) +
+                                            " bytes of scratch; the fixed scratch holds " +
+                                            std::to_string(noalloc_scratch_bytes()));
+    DJ_HIP(hipSetDevice(c.device));
+    void *base = nullptr;
+    DJ_HIP(noalloc_scratch(c.device, &base));  // looked up at precompute; a table read here
+    DJ_HIP(launch_forces_in(c, u_dev, f_dev, base, static_cast<char *>(base) + ubytes,
+                            static_cast<hipStream_t>(stream)));
     return DJ_OK;
 }
 

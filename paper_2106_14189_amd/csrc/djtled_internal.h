@@ -232,6 +232,12 @@ hipError_t launch_precompute(Ctx &c, const double *dX, const int32_t *dconn, con
 hipError_t launch_mass_acoef(Ctx &c, const int32_t *d_ne_off, const int32_t *d_ne_list, const double *d_c2,
                              const double *d_bp, hipStream_t s);
 hipError_t launch_forces(Ctx &c, const void *u, void *f, hipStream_t s);
+// the same in caller-given device buffers: 3 x n_copies u planes, 3 x max(n_part, 1) partials
+hipError_t launch_forces_in(Ctx &c, const void *u, void *f, void *ubuf0, void *part, hipStream_t s);
+// device address of the fixed scratch array of the allocation-free entry points
+// on the current device (looked up once per device); its size in bytes
+hipError_t noalloc_scratch(int device, void **ptr);
+size_t noalloc_scratch_bytes();
 hipError_t launch_step(Ctx &c, const StepArgs &a, const void *u_cur_in, const void *u_prev_in, hipStream_t s,
                        hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_export(Ctx &c, double *d_V, double *d_dhdX, double *d_mass, hipStream_t s);
@@ -254,6 +260,8 @@ struct OpArgs {
     const StepArgs *a = nullptr;  // STEP
     const void *u_cur_in = nullptr, *u_prev_in = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    void *ubuf0 = nullptr;        // FORCES: node-copy u planes and partial sums to use instead of
+    void *part = nullptr;         //   the context's (both or neither)
 };
 hipError_t inst_f4(const OpArgs &o);
 hipError_t inst_f8(const OpArgs &o);

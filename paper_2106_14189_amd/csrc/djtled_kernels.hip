@@ -2,6 +2,8 @@
 // pre-computation and the launchers.  The step and force kernels are
 // templates in djtled_step.h, instantiated per (precision, element type,
 // form) in the djtled_inst_*.hip translation units.
+#include <mutex>
+
 #include "djtled_device.h"
 
 namespace dj {
@@ -236,6 +238,56 @@ hipError_t launch_forces(Ctx &c, const void *u, void *f, hipStream_t s) {
     o.f = f;
     o.s = s;
     return dispatch_op(c.prec, c.ne, c.form, o);
+}
+
+hipError_t launch_forces_in(Ctx &c, const void *u, void *f, void *ubuf0, void *part, hipStream_t s) {
+    OpArgs o;
+    o.op = Op::FORCES;
+    o.c = &c;
+    o.model = c.model;
+    o.variant = c.variant;
+    o.u = u;
+    o.f = f;
+    o.s = s;
+    o.ubuf0 = ubuf0;
+    o.part = part;
+    return dispatch_op(c.prec, c.ne, c.form, o);
+}
+
+// ---------------------------------------------------------------------------
+// Fixed scratch of the allocation-free entry point (djtled_forces_noalloc):
+// the node-copy u planes and shared-node partial sums of one force
+// evaluation live in this file-scope device array, one per GPU, held until
+// the process ends.  In host code the array's name is only a stand-in: its
+// device address on each GPU is looked up once, with that GPU current, and
+// only that address is ever passed to kernels.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[DJTLED_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+size_t noalloc_scratch_bytes() { return DJTLED_NOALLOC_SCRATCH_BYTES; }
+
+hipError_t noalloc_scratch(int device, void **ptr) {
+    *ptr = nullptr;
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;  // the caller makes `device` current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
 }
 
 hipError_t launch_step(Ctx &c, const StepArgs &a, const void *u_cur_in, const void *u_prev_in, hipStream_t s,

@@ -436,15 +436,16 @@ struct Inst {
         }
         return hipSuccess;
     }
-    static hipError_t forces(Ctx &c, const void *u, void *f, hipStream_t s) {
+    // ubuf0: 3 x n_copies u planes, part: 3 x max(n_part, 1) partial sums
+    static hipError_t forces(Ctx &c, const void *u, void *f, void *ubuf0, void *part_buf, hipStream_t s) {
         const int L = c.topo.n_copies, B = 256;
-        T *u0 = static_cast<T *>(c.d_ubuf[0]);
+        T *u0 = static_cast<T *>(ubuf0);
         hipLaunchKernelGGL(k_scatter_in<T>, dim3((L + B - 1) / B), dim3(B), 0, s, c.topo.cnode, L,
                            static_cast<const T *>(u), static_cast<const T *>(nullptr), u0, static_cast<T *>(nullptr));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         StepPtrs<T> sp{};
-        T *part = static_cast<T *>(c.d_part);
+        T *part = static_cast<T *>(part_buf);
         for (int k = 0; k < 3; k++) {
             sp.uc[k] = u0 + int64_t(k) * L;
             sp.up[k] = nullptr;
@@ -618,7 +619,7 @@ static hipError_t forces_anp_t(Ctx &c, const void *u, void *f, hipStream_t s) {
     // the standard force pass over the modified planes
     const void *saved = c.topo.elem;
     c.topo.elem = c.d_anp_planes;
-    auto run = [&](auto inst) { return decltype(inst)::forces(c, u, f, s); };
+    auto run = [&](auto inst) { return decltype(inst)::forces(c, u, f, c.d_ubuf[0], c.d_part, s); };
     e = c.model == DJ_NH ? with_variant<T, NE, DJ_NH | DJ_FORM_ANP>(c.variant, run)
                          : with_variant<T, NE, DJ_TI | DJ_FORM_ANP>(c.variant, run);
     c.topo.elem = saved;
@@ -638,7 +639,9 @@ hipError_t run_ops(const OpArgs &o) {
         switch (o.op) {
             case Op::OCC: return I::occ(o.bpc, o.lds);
             case Op::OCC_MULTI: return I::occ_multi(o.bpc);
-            case Op::FORCES: return I::forces(*o.c, o.u, o.f, o.s);
+            case Op::FORCES:
+                return o.ubuf0 ? I::forces(*o.c, o.u, o.f, o.ubuf0, o.part, o.s)
+                               : I::forces(*o.c, o.u, o.f, o.c->d_ubuf[0], o.c->d_part, o.s);
             case Op::STEP: return I::step(*o.c, *o.a, o.u_cur_in, o.u_prev_in, o.s, o.ev0, o.ev1);
             default: return hipErrorInvalidValue;
         }
