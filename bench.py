@@ -22,6 +22,8 @@ Further measurements, reported under "extra" (each skippable):
     the classical TLED force;
   * multi: k = 1, 2, 4, 8 compression cases per launch on the 64^3 cubes
     (djtled_step_multi): time per step and element-steps/s over cases;
+  * anp: the average-nodal-pressure step (Sec. 7) on the 64^3 cubes next to
+    the element-pressure step;
   * realtime (--realtime): step time over cube sizes and the model sizes
     for one step per 33.3 ms / 2 ms (Sec. 5.5), checked at the 2 ms size;
   * relaxation: the ~1.2M-tet transversely isotropic ellipsoid relaxed to
@@ -364,6 +366,39 @@ def bench_multi(log, steps: int = 300) -> dict:
     return out
 
 
+def bench_anp(log, steps: int = 300) -> dict:
+    """The average-nodal-pressure step (Sec. 7; formulation nodal_pressure)
+    on the 64^3 compression cubes, T4 and H8, NH, FP32: kernel time per step
+    next to the element-pressure step of the same mesh (the ANP step makes a
+    second element pass and a second grid barrier per step)."""
+    import torch
+    from paper_2106_14189_amd import solver as S
+    from paper_2106_14189_amd import workloads as W
+    out = {"workload": "cube64_t4+h8_nh_fp32_compression_nodal_pressure", "steps": steps}
+    for elem in (W.T4, W.H8):
+        wl = W.config1(elem)
+        tag = "t4" if elem == W.T4 else "h8"
+        for form in ("jacobian", "nodal_pressure"):
+            sv = S.from_workload(wl, formulation=form)
+            info = sv.info()
+            ld = wl.loads
+            ls = sv.loadset(ld.bc_node, ld.bc_mask, ld.bc_target, ld.ramp, 1000 * info["dt"])
+            u, up = sv.zeros(), sv.zeros()
+            st, step = sv.step(u, up, 20, ls)
+            st, step = sv.step(u, up, steps, ls, step0=step)
+            torch.cuda.synchronize()
+            assert st.code == 0 and st.steps_done == steps, st
+            out[f"{tag}_{form}_us_per_step"] = st.kernel_ms / steps * 1e3
+            out[f"{tag}_{form}_bytes_per_step"] = info["bytes_per_step"]
+            out[f"{tag}_{form}_effective_GBps"] = info["bytes_per_step"] * steps / (st.kernel_ms / 1e3) / 1e9
+            ls.close()
+            sv.close()
+        out[f"{tag}_anp_over_standard"] = out[f"{tag}_nodal_pressure_us_per_step"] / out[f"{tag}_jacobian_us_per_step"]
+        log(f"anp {tag}: {out[f'{tag}_jacobian_us_per_step']:.1f} us standard, "
+            f"{out[f'{tag}_nodal_pressure_us_per_step']:.1f} us nodal pressure")
+    return out
+
+
 def bench_relaxation(log, ramps=(0.0, 0.05, 0.1, 0.2, 0.4)) -> dict:
     """The ~1.2M-tet TI ellipsoid: FP32 dynamic relaxation to r <= 1e-3 (above
     its FP32 rounding floor) for each load-ramp length in `ramps` (0: the load
@@ -499,6 +534,7 @@ def main():
     ap.add_argument("--no-cube", action="store_true", help="skip the 64^3 cube measurement")
     ap.add_argument("--no-models", action="store_true", help="skip the four-material-model measurement")
     ap.add_argument("--no-multi", action="store_true", help="skip the several-load-cases measurement")
+    ap.add_argument("--no-anp", action="store_true", help="skip the average-nodal-pressure step measurement")
     ap.add_argument("--no-relax", action="store_true", help="skip the ellipsoid relaxation measurement")
     ap.add_argument("--no-warm", action="store_true", help="skip the warm-start measurement")
     ap.add_argument("--no-mlp", action="store_true", help="skip the full-size network timing")
@@ -613,6 +649,7 @@ def main():
     for name, skip, fn in (("cube64", args.no_cube, lambda lg: bench_cube64(lg, K, Wm, args.variant, args.mesh)),
                            ("models", args.no_models, bench_models),
                            ("multi", args.no_multi, bench_multi),
+                           ("anp", args.no_anp, bench_anp),
                            ("realtime", not args.realtime, bench_realtime),
                            ("relaxation", args.no_relax, bench_relaxation),
                            ("mlp", args.no_mlp, bench_mlp), ("warm_start", args.no_warm, bench_warm_start),

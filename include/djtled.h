@@ -60,8 +60,13 @@ enum { DJ_NH = 0, DJ_TI = 1, DJ_OT = 2, DJ_MR = 3 };  /* Table 3 rows: neo-Hooke
 enum { DJ_FP32 = 0, DJ_FP64 = 1 };
 /* Element force: the Jacobian form of Table 3 (the method), or the classical
    TLED form of Eq. 4 (deformation gradient, C^-1 and the second Piola-Kirchhoff
-   stress of the same strain energy), kept as a comparison path (FP32 only). */
-enum { DJ_FORM_JACOBIAN = 0, DJ_FORM_CLASSICAL = 1 };
+   stress of the same strain energy), kept as a comparison path (FP32 only), or
+   the Jacobian form with the average nodal pressure that Sec. 7 names against
+   volumetric locking (DJ_NH / DJ_TI, variants 0..3; see djtled_forces_anp for
+   the pressure): every time step then makes a J pass over the elements, a grid
+   barrier, and the force pass with each element's pressure the mean of its
+   nodes' pressures, and djtled_forces returns these forces. */
+enum { DJ_FORM_JACOBIAN = 0, DJ_FORM_CLASSICAL = 1, DJ_FORM_NODAL_PRESSURE = 2 };
 enum { DJ_RAMP_NONE = 0, DJ_RAMP_LINEAR = 1, DJ_RAMP_SMOOTH = 2 };
 enum { DJ_MODE_FIXED = 0, DJ_MODE_RELAX = 1 };
 
@@ -108,7 +113,8 @@ typedef struct {
     int32_t variant;        /* step kernel variant 0..5 (threads, elements per thread, register budget);
                                -1: automatic (FP32 H8: 2, otherwise 0) */
     int32_t device;         /* HIP device ordinal; < 0 -> current device */
-    int32_t formulation;    /* DJ_FORM_JACOBIAN (0) or DJ_FORM_CLASSICAL; batches take 0 only */
+    int32_t formulation;    /* DJ_FORM_JACOBIAN (0), DJ_FORM_CLASSICAL or DJ_FORM_NODAL_PRESSURE;
+                               batches take 0 only */
 } djtled_params;
 
 typedef struct djtled_ctx djtled_ctx;

@@ -24,7 +24,7 @@ DJ_ERR_UNSUPPORTED, DJ_ERR_UNSTABLE_DT, DJ_ERR_HIP, DJ_ERR_BARRIER = -5, -6, -7,
 DJ_T4, DJ_H8 = 4, 8
 DJ_NH, DJ_TI, DJ_OT, DJ_MR = 0, 1, 2, 3
 DJ_FP32, DJ_FP64 = 0, 1
-DJ_FORM_JACOBIAN, DJ_FORM_CLASSICAL = 0, 1
+DJ_FORM_JACOBIAN, DJ_FORM_CLASSICAL, DJ_FORM_NODAL_PRESSURE = 0, 1, 2
 DJ_RAMP_NONE, DJ_RAMP_LINEAR, DJ_RAMP_SMOOTH = 0, 1, 2
 DJ_MODE_FIXED, DJ_MODE_RELAX = 0, 1
 

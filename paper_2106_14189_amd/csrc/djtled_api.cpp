@@ -514,6 +514,17 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
         c.topo.bpc = pb;
     }
     DJ_HIP(launch_mass_acoef(c, dneoff, dnelist, dc2, dbpn, nullptr));
+    if (c.form == DJ_FORM_NODAL_PRESSURE) {
+        unsigned char *q;
+        DJ_HIP(dalloc(c, &q, size_t(L) * ts));
+        c.d_anps_c = q;
+        DJ_HIP(dalloc(c, &q, size_t(L) * ts));
+        c.d_anps_p = q;
+        DJ_HIP(hipMemset(c.d_anps_p, 0, size_t(L) * ts));
+        DJ_HIP(dalloc(c, &q, size_t(std::max(c.topo.n_part, 1)) * ts));
+        c.d_anps_j = q;
+        DJ_HIP(launch_anps_setup(c, nullptr));
+    }
     std::vector<double> m(N);
     DJ_HIP(hipMemcpy(m.data(), c.d_mass64, N * sizeof(double), hipMemcpyDeviceToHost));
     c.mass_total = std::accumulate(m.begin(), m.end(), 0.0);
@@ -537,6 +548,22 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
         }
     }
     c.bytes_per_step = eb * E + interior + shared + double(nch) * sizeof(ChunkDesc);
+    if (c.form == DJ_FORM_NODAL_PRESSURE) {
+        // the J pass: element data again; per copy slot range, flags, u^n, and
+        // c_n + p_n (interior) or the J partial (shared); the shared copies'
+        // flags, partial index, group of J partials, c_n and p_n; the force
+        // pass reads p_n of every copy
+        double jp = eb * E;
+        for (int64_t l = 0; l < L; l++) {
+            if (flags[l] & FLAG_SHARED) {
+                const int k = (flags[l] >> FLAG_NCOPY_SHIFT) & 255;
+                jp += (4 + 4 + 4 + 3 * ts) + ts + (4 + 4 + k * ts + 2 * ts) + ts;
+            } else {
+                jp += 4 + 4 + 3 * ts + 2 * ts + ts;
+            }
+        }
+        c.bytes_per_step += jp + double(nch) * sizeof(ChunkDesc);
+    }
     c.elem_bytes = eb;
     return DJ_OK;
 }
@@ -647,6 +674,9 @@ int step_cases(djtled_ctx *ctx, int nrhs, djtled_state *st, const djtled_loadset
     const LoadSet *l0 = has_loads ? reinterpret_cast<const LoadSet *>(lsp[0]) : nullptr;
     a.ramp = l0 ? l0->ramp : DJ_RAMP_NONE;
     a.t_ramp = l0 ? l0->t_ramp : 0.0;
+    a.anp_c = c.d_anps_c;
+    a.anp_p = c.d_anps_p;
+    a.anp_jpart = c.d_anps_j;
     if (nrhs == 1) {
         for (int b = 0; b < 3; b++) a.ubuf[b] = c.d_ubuf[b];
         a.part = c.d_part;
@@ -768,8 +798,11 @@ int djtled_precompute(const djtled_mesh *mesh, const djtled_material *mat, const
     if (mat->model == DJ_OT && !mat->fibre_b) return fail(DJ_ERR_ARG, "DJ_OT needs second fibre directions");
     if ((mat->model == DJ_OT || mat->model == DJ_MR) && prm->variant >= 4)
         return fail(DJ_ERR_UNSUPPORTED, "variants 4 and 5 are built for DJ_NH and DJ_TI only");
-    if (prm->formulation != DJ_FORM_JACOBIAN && prm->formulation != DJ_FORM_CLASSICAL)
-        return fail(DJ_ERR_ARG, "formulation must be DJ_FORM_JACOBIAN or DJ_FORM_CLASSICAL");
+    if (prm->formulation != DJ_FORM_JACOBIAN && prm->formulation != DJ_FORM_CLASSICAL &&
+        prm->formulation != DJ_FORM_NODAL_PRESSURE)
+        return fail(DJ_ERR_ARG, "formulation must be DJ_FORM_JACOBIAN, DJ_FORM_CLASSICAL or DJ_FORM_NODAL_PRESSURE");
+    if (prm->formulation == DJ_FORM_NODAL_PRESSURE && ((mat->model != DJ_NH && mat->model != DJ_TI) || prm->variant >= 4))
+        return fail(DJ_ERR_UNSUPPORTED, "the average-nodal-pressure form: DJ_NH / DJ_TI, variants 0..3");
     if (prm->formulation == DJ_FORM_CLASSICAL && (prm->precision != DJ_FP32 || prm->variant >= 4))
         return fail(DJ_ERR_UNSUPPORTED, "the classical TLED form is built for FP32 and variants 0..3");
     if (!(prm->alpha >= 0) || !(prm->dt >= 0)) return fail(DJ_ERR_ARG, "alpha and dt must be >= 0");
@@ -842,6 +875,7 @@ int djtled_info(const djtled_ctx *ctx, djtled_info_t *o) {
 int djtled_forces(djtled_ctx *ctx, const void *u_dev, void *f_dev, void *stream) {
     if (!ctx || !u_dev || !f_dev) return fail(DJ_ERR_ARG, "null argument");
     Ctx &c = *reinterpret_cast<Ctx *>(ctx);
+    if (c.form == DJ_FORM_NODAL_PRESSURE) return djtled_forces_anp(ctx, u_dev, f_dev, stream);
     DJ_HIP(hipSetDevice(c.device));
     DJ_HIP(launch_forces(c, u_dev, f_dev, static_cast<hipStream_t>(stream)));
     return DJ_OK;
@@ -851,6 +885,8 @@ int djtled_forces_noalloc(djtled_ctx *ctx, const void *u_dev, void *f_dev, void 
     if (!ctx || !u_dev || !f_dev) return fail(DJ_ERR_ARG, "null argument");
     Ctx &c = *reinterpret_cast<Ctx *>(ctx);
     if (c.n_inst > 1) return fail(DJ_ERR_ARG, "batch contexts have no forces entry point");
+    if (c.form == DJ_FORM_NODAL_PRESSURE)
+        return fail(DJ_ERR_UNSUPPORTED, "djtled_forces_noalloc: not for average-nodal-pressure contexts");
     const size_t ts = c.prec == DJ_FP32 ? sizeof(float) : sizeof(double);
     const size_t ubytes = (size_t(3) * c.topo.n_copies * ts + 255) & ~size_t(255);
     const size_t need = ubytes + size_t(3) * std::max(c.topo.n_part, 1) * ts;
@@ -870,7 +906,7 @@ int djtled_forces_anp(djtled_ctx *ctx, const void *u_dev, void *f_dev, void *str
     if (!ctx || !u_dev || !f_dev) return fail(DJ_ERR_ARG, "null argument");
     Ctx &c = *reinterpret_cast<Ctx *>(ctx);
     if (c.n_inst > 1) return fail(DJ_ERR_ARG, "batch contexts have no forces entry point");
-    if ((c.model != DJ_NH && c.model != DJ_TI) || c.form != DJ_FORM_JACOBIAN || c.variant >= 4)
+    if ((c.model != DJ_NH && c.model != DJ_TI) || c.form == DJ_FORM_CLASSICAL || c.variant >= 4)
         return fail(DJ_ERR_UNSUPPORTED, "average nodal pressure: DJ_NH / DJ_TI, Jacobian form, variants 0..3");
     DJ_HIP(hipSetDevice(c.device));
     if (!c.d_anp_planes) {

@@ -75,6 +75,7 @@ __device__ __forceinline__ StepPtrs<T> kind_ptrs(const BatchKind &kd, int cur, i
     sp.bpc = static_cast<const T *>(kd.tp.bpc);
     sp.rrate = static_cast<const T *>(kd.rate);
     sp.n1 = T(n + 1);
+    sp.pn = nullptr;
     return sp;
 }
 

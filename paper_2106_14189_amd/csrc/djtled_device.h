@@ -221,6 +221,42 @@ __device__ __forceinline__ T tled_stress_m(const T *__restrict__ cst, const T (&
     return J;
 }
 
+// J - 1 of an element at displacement u (Eq. 12 in the increment form used by
+// element_force: D = 0J^-1 H_xi Ue, J - 1 = tr D + (tr^2 D - tr D^2) / 2 + det D)
+template <typename T, int NE, int MODEL>
+__device__ __forceinline__ T element_jm1(const T *__restrict__ cst, const T (&u)[NE][3]) {
+    using P = Planes<NE, MODEL>;
+    T dJ[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) {
+            if constexpr (NE == 4) {
+                dJ[i][k] = u[i + 1][k] - u[0][k];
+            } else {
+                T s = 0;
+#pragma unroll
+                for (int a = 1; a < 8; a++) s += (h8s(a, i) > 0) ? (u[a][k] - u[0][k]) : -(u[a][k] - u[0][k]);
+                dJ[i][k] = s * T(0.125);
+            }
+        }
+    const T *Ji = cst + P::JINV;
+    T D[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int k = 0; k < 3; k++) D[i][k] = Ji[3 * i] * dJ[0][k] + Ji[3 * i + 1] * dJ[1][k] + Ji[3 * i + 2] * dJ[2][k];
+    const T trD = D[0][0] + D[1][1] + D[2][2];
+    T trD2 = 0;
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) trD2 += D[i][j] * D[j][i];
+    const T detD = D[0][0] * (D[1][1] * D[2][2] - D[1][2] * D[2][1]) - D[0][1] * (D[1][0] * D[2][2] - D[1][2] * D[2][0]) +
+                   D[0][2] * (D[1][0] * D[2][1] - D[1][1] * D[2][0]);
+    return trD + T(0.5) * (trD * trD - trD2) + detD;
+}
+
 template <typename T, int NE, int MODEL>
 __device__ __forceinline__ T element_force(const T *__restrict__ cst, const T (&u)[NE][3], T (&F)[NE][3]) {
     using P = Planes<NE, MODEL>;
@@ -432,6 +468,8 @@ struct StepPtrs {
     const T *bpc;
     const T *rrate;
     T n1;             // n + 1
+    // average nodal pressure step: per-copy nodal pressure p_n (force pass; null otherwise)
+    const T *pn;
 };
 
 struct PhaseOut {
@@ -565,7 +603,11 @@ struct Chunk {
         uint32_t cr[MC], fl[MC];
         int pb[MC];
         T ux[MC][3], upv[MC][3], A[MC], Bp[MC], rr[MC], rv[MC][3];
+        T pn[MC];  // average-nodal-pressure step: the copy's nodal pressure
     };
+    static constexpr bool ANPM = (MODEL & DJ_FORM_ANP) != 0;
+    // LDS of the average-nodal-pressure step: a fourth slot plane carries p_n
+    static constexpr size_t LDS_ANP = LDS + size_t(NE) * CMAX * sizeof(T);
 
     // Element planes and slot positions (register path).  Lanes past the
     // chunk's end load its last element again: the loads are unconditional, so
@@ -601,6 +643,7 @@ struct Chunk {
             c.fl[m] = sp.flags[l];
 #pragma unroll
             for (int k = 0; k < 3; k++) c.ux[m][k] = sp.uc[k][l];
+            if constexpr (ANPM) c.pn[m] = sp.pn ? sp.pn[l] : T(0);
             if (i < ch.copy_count) {
                 if (i >= ch.n_interior) {
                     c.pb[m] = tp.pidx[l];
@@ -667,6 +710,9 @@ struct Chunk {
                     ly[q] = cin.ux[m][1];
                     lz[q] = cin.ux[m][2];
                 }
+                if constexpr (ANPM)
+                    if (sp.pn)
+                        for (int q = b; q < b + n; q++) lz[NE * CMAX + q] = cin.pn[m];
             }
         }
         if constexpr (RV) load_rv<MODE>(ch, sp, cin);
@@ -698,7 +744,24 @@ struct Chunk {
                     u[a][1] = ly[er.wp[j][a]];
                     u[a][2] = lz[er.wp[j][a]];
                 }
-                const T J = element_force<T, NE, MODEL>(er.cst[j], u, F);
+                T J;
+                if constexpr (ANPM) {
+                    // average nodal pressure: with sp.pn the kappa plane holds 0V and the
+                    // element pressure is the mean of its nodes' pressures; without it
+                    // the plane already holds that mean times 0V
+                    T cst[NP];
+#pragma unroll
+                    for (int q = 0; q < NP; q++) cst[q] = er.cst[j][q];
+                    if (sp.pn) {
+                        T pb = 0;
+#pragma unroll
+                        for (int a = 0; a < NE; a++) pb += lz[NE * CMAX + er.wp[j][a]];
+                        cst[Planes<NE, MODEL>::KAV] *= pb * T(1.0 / NE);
+                    }
+                    J = element_force<T, NE, MODEL>(cst, u, F);
+                } else {
+                    J = element_force<T, NE, MODEL>(er.cst[j], u, F);
+                }
                 // an inverted (or non-finite) element stops the run; its force is
                 // left out so that the error is reported at the element itself
                 const bool ok = J > T(0);
@@ -843,6 +906,82 @@ struct Chunk {
                     node_update<T>(l, r.fl[kb], f, r.uc[kb], r.up[kb], r.A[kb], sp.bprime, sp.sval, r.rv[kb], sp,
                                    po);
             }
+        }
+    }
+
+    // Average-nodal-pressure J pass over one chunk: every element adds
+    // 0V / n_e (J_e - 1) (the kappa plane holds 0V) to its nodes' slots; each
+    // copy sums its range into S.  Interior copies finish the nodal pressure
+    // p_n = c_n S_n at once, with c_n = kappa_n / V_n per copy; shared copies
+    // publish S into their node's group (one plane).  Errors are left to the
+    // force pass, which evaluates the same elements at the same u.
+    __device__ static void anp_j_phase(const DevTopo &tp, const ChunkDesc &ch, const StepPtrs<T> &sp, T *jpart,
+                                       const T *cn, T *pn, unsigned char *smem) {
+        const int tid = threadIdx.x;
+        ElemRegs er;
+        CopyRegs cp;
+        load_elems(tp, ch, er);
+        load_copies<0>(tp, ch, sp, cp);
+        T *lx = reinterpret_cast<T *>(smem);
+        T *ly = lx + NE * CMAX;
+        T *lz = lx + 2 * NE * CMAX;
+#pragma unroll
+        for (int m = 0; m < MC; m++) {
+            const int i = tid + m * BLOCK;
+            if (i < ch.copy_count) {
+                const int b = cp.cr[m] & 0xffffu, n = cp.cr[m] >> 16;
+                for (int q = b; q < b + n; q++) {
+                    lx[q] = cp.ux[m][0];
+                    ly[q] = cp.ux[m][1];
+                    lz[q] = cp.ux[m][2];
+                }
+            }
+        }
+        __syncthreads();
+        // each element reads and then overwrites only its own incidence slots
+#pragma unroll
+        for (int j = 0; j < EPT; j++) {
+            const int e = tid + j * BLOCK;
+            if (e < ch.elem_count) {
+                T u[NE][3];
+#pragma unroll
+                for (int a = 0; a < NE; a++) {
+                    u[a][0] = lx[er.wp[j][a]];
+                    u[a][1] = ly[er.wp[j][a]];
+                    u[a][2] = lz[er.wp[j][a]];
+                }
+                const T jw = er.cst[j][Planes<NE, MODEL>::KAV] * T(1.0 / NE) * element_jm1<T, NE, MODEL>(er.cst[j], u);
+#pragma unroll
+                for (int a = 0; a < NE; a++) lx[er.wp[j][a]] = jw;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < MC; m++) {
+            const int i = tid + m * BLOCK;
+            if (i < ch.copy_count) {
+                const int b = cp.cr[m] & 0xffffu, n = cp.cr[m] >> 16;
+                T S = T(0);
+                for (int q = b; q < b + n; q++) S += lx[q];
+                const int l = ch.copy_begin + i;
+                if (i >= ch.n_interior) st_dev(&jpart[cp.pb[m] + int((cp.fl[m] >> FLAG_RANK_SHIFT) & 255u)], S);
+                else pn[l] = cn[l] * S;
+            }
+        }
+        __syncthreads();  // LDS is reused by the next chunk
+    }
+
+    // After the J barrier: the nodal pressure of every shared copy of one
+    // chunk from its node's group of J sums (summed in rank order).
+    __device__ static void anp_j_shared(const DevTopo &tp, const ChunkDesc &ch, const StepPtrs<T> &sp,
+                                        const T *jpart, const T *cn, T *pn) {
+        for (int i = ch.n_interior + threadIdx.x; i < ch.copy_count; i += BLOCK) {
+            const int l = ch.copy_begin + i;
+            const uint32_t fl = sp.flags[l];
+            const int cnt = (fl >> FLAG_NCOPY_SHIFT) & 255u, q0 = tp.pidx[l];
+            T S = T(0);
+            for (int q = 0; q < cnt; q++) S += ld_dev(&jpart[q0 + q]);
+            pn[l] = cn[l] * S;
         }
     }
 

@@ -131,6 +131,11 @@ struct StepArgs {
                                 // [4] barrier abort [5..6] per-parity error words [7] case of the error
     double *red = nullptr;      // residual partials: 2 parities x grid x nrhs x 2
     double *res_out = nullptr;  // last residual per case
+    // average-nodal-pressure step: per copy c_n = kappa_n / V_n and nodal
+    // pressure p_n, and the J partial sums of shared copies (one plane)
+    const void *anp_c = nullptr;
+    void *anp_p = nullptr;
+    void *anp_jpart = nullptr;
 };
 
 struct Ctx {
@@ -157,6 +162,9 @@ struct Ctx {
     double *d_kappa64 = nullptr;
     void *d_anp_planes = nullptr;
     double *d_anp_je = nullptr, *d_anp_pn = nullptr;
+    // average-nodal-pressure step (formulation DJ_FORM_NODAL_PRESSURE): per copy
+    // c_n and p_n, J partials (context precision)
+    void *d_anps_c = nullptr, *d_anps_p = nullptr, *d_anps_j = nullptr;
     // several load cases per launch: buffers grown on demand (case capacity rhs_cap)
     int rhs_cap = 0;
     void *d_mubuf[3] = {nullptr, nullptr, nullptr};
@@ -243,6 +251,8 @@ hipError_t launch_step(Ctx &c, const StepArgs &a, const void *u_cur_in, const vo
 hipError_t launch_export(Ctx &c, double *d_V, double *d_dhdX, double *d_mass, hipStream_t s);
 // internal forces with the average nodal pressure (u, f: caller order)
 hipError_t launch_forces_anp(Ctx &c, const void *u, void *f, hipStream_t s);
+// average-nodal-pressure step contexts: kappa plane <- 0V, per-copy c_n
+hipError_t launch_anps_setup(Ctx &c, hipStream_t s);
 
 // One launcher operation for one (precision, element type, form), dispatched
 // over (model, variant) by the instantiating unit inst_<p><ne> (f: FP32,
@@ -262,6 +272,7 @@ struct OpArgs {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     void *ubuf0 = nullptr;        // FORCES: node-copy u planes and partial sums to use instead of
     void *part = nullptr;         //   the context's (both or neither)
+    int anp = 0;                  // OCC, STEP: the average-nodal-pressure step kernel
 };
 hipError_t inst_f4(const OpArgs &o);
 hipError_t inst_f8(const OpArgs &o);

@@ -181,11 +181,12 @@ __global__ void k_export_mass(const double *__restrict__ mass, const int32_t *__
 // each dispatches over (model, variant).  The classical TLED form is built in
 // FP32 only (a comparison path).
 // ---------------------------------------------------------------------------
-static hipError_t dispatch_op(int prec, int ne, int form, const OpArgs &o) {
+static hipError_t dispatch_op(int prec, int ne, int form, OpArgs o) {
     if (form == DJ_FORM_CLASSICAL) {
         if (prec != DJ_FP32) return hipErrorInvalidValue;
         return ne == 4 ? inst_c4(o) : inst_c8(o);
     }
+    if (form == DJ_FORM_NODAL_PRESSURE) o.anp = 1;  // the Jacobian units hold the ANP step kernels
     if (prec == DJ_FP32) return ne == 4 ? inst_f4(o) : inst_f8(o);
     return ne == 4 ? inst_d4(o) : inst_d8(o);
 }
@@ -354,6 +355,49 @@ hipError_t launch_mass_acoef(Ctx &c, const int32_t *d_ne_off, const int32_t *d_n
     else
         hipLaunchKernelGGL(k_acoef<double>, dim3(G), dim3(B), 0, s, c.d_inode, c.topo.n_copies, c.d_mass64, c2, d_c2,
                            d_bp, static_cast<double *>(c.d_acoef), static_cast<double *>(c.d_bpc));
+    return hipGetLastError();
+}
+
+// ---- average-nodal-pressure step set-up: the kappa plane holds 0V, and every
+// copy gets c_n = kappa_n / V_n of its node (V_n = sum_e 0V_e / n_e, kappa_n
+// the 0V_e / n_e-weighted mean of kappa_e), summed in ascending element order
+template <typename T>
+__global__ void k_anps_vplane(int E, const double *__restrict__ V64, T *__restrict__ plane) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < E) plane[e] = T(V64[e]);
+}
+
+template <typename T>
+__global__ void k_anps_c(const int32_t *__restrict__ inode, int L, const int32_t *__restrict__ off,
+                         const int32_t *__restrict__ lst, int ne, const double *__restrict__ V64,
+                         const double *__restrict__ kappa, T *__restrict__ cn) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= L) return;
+    const int n = inode[l];
+    double v = 0.0, vk = 0.0;
+    for (int j = off[n]; j < off[n + 1]; j++) {
+        const int e = lst[j];
+        const double w = V64[e] / ne;
+        v += w;
+        vk += w * kappa[e];
+    }
+    cn[l] = T(v > 0.0 ? vk / (v * v) : 0.0);
+}
+
+hipError_t launch_anps_setup(Ctx &c, hipStream_t s) {
+    const int B = 256, E = c.n_elems, L = c.topo.n_copies;
+    const int64_t kav = int64_t(Planes<4, DJ_NH>::KAV) * c.topo.estride;
+    if (c.prec == DJ_FP32) {
+        hipLaunchKernelGGL(k_anps_vplane<float>, dim3((E + B - 1) / B), dim3(B), 0, s, E, c.d_V64,
+                           static_cast<float *>(c.d_elem) + kav);
+        hipLaunchKernelGGL(k_anps_c<float>, dim3((L + B - 1) / B), dim3(B), 0, s, c.d_inode, L, c.d_ne_off,
+                           c.d_ne_list, c.ne, c.d_V64, c.d_kappa64, static_cast<float *>(c.d_anps_c));
+    } else {
+        hipLaunchKernelGGL(k_anps_vplane<double>, dim3((E + B - 1) / B), dim3(B), 0, s, E, c.d_V64,
+                           static_cast<double *>(c.d_elem) + kav);
+        hipLaunchKernelGGL(k_anps_c<double>, dim3((L + B - 1) / B), dim3(B), 0, s, c.d_inode, L, c.d_ne_off,
+                           c.d_ne_list, c.ne, c.d_V64, c.d_kappa64, static_cast<double *>(c.d_anps_c));
+    }
     return hipGetLastError();
 }
 

@@ -78,7 +78,26 @@ __global__ void __launch_bounds__(BLOCK, WPE) k_step(DevTopo tp, StepArgs a) {
         sp.bpc = nullptr;
         sp.rrate = nullptr;
         sp.n1 = T(n + 1);
+        sp.pn = nullptr;
         PhaseOut po{0.0, 0.0, 0, -1};
+        if constexpr (C::ANPM) {
+            // Average nodal pressure (Sec. 7): a J pass over every chunk, its own
+            // grid barrier, the nodal pressures of the shared copies, then the
+            // force pass below with each element's pressure the mean of its
+            // nodes' pressures.  The J partial sums are single-buffered: they
+            // are read before the force barrier and written after it.
+            T *jpart = static_cast<T *>(a.anp_jpart);
+            const T *cn = static_cast<const T *>(a.anp_c);
+            T *pnb = static_cast<T *>(a.anp_p);
+            for (int k = 0; k < nmine; k++) C::anp_j_phase(tp, s_ch[k], sp, jpart, cn, pnb, smem);
+            if (!grid_barrier(a.bar, G, epoch, a.status)) {
+                code = DJ_ERR_BARRIER;
+                break;
+            }
+            for (int k = 0; k < nmine; k++) C::anp_j_shared(tp, s_ch[k], sp, jpart, cn, pnb);
+            __syncthreads();  // pressures written above by one thread are scattered by another
+            sp.pn = pnb;
+        }
         // The copy data of chunk k + 1 is loaded while chunk k is summed and
         // updated; the element data of chunk k is in flight during its
         // scatter.  (Element data loaded one chunk ahead, or across the step
@@ -245,6 +264,7 @@ __global__ void __launch_bounds__(BLOCK, WPE) k_step_multi(DevTopo tp, StepArgs 
             sp.bpc = nullptr;
             sp.rrate = nullptr;
             sp.n1 = T(n + 1);
+            sp.pn = nullptr;
             return sp;
         };
         PhaseOut po{0.0, 0.0, 0, -1};
@@ -419,10 +439,18 @@ template <typename T, int NE, int MODEL, int BLOCK, int EPT, int MC, int WPE>
 struct Inst {
     using C = Chunk<T, NE, MODEL, BLOCK, EPT, MC>;
     // several load cases per launch: FP32, Jacobian form, two-wave variants
-    static constexpr bool has_multi() { return sizeof(T) == 4 && (MODEL & DJ_FORM_TLED) == 0 && WPE < 3; }
+    static constexpr bool has_multi() {
+        return sizeof(T) == 4 && (MODEL & (DJ_FORM_TLED | DJ_FORM_ANP)) == 0 && WPE < 3;
+    }
+    // dynamic LDS of the step kernel (a fourth slot plane for the average nodal pressure)
+    static constexpr size_t STEP_LDS = C::ANPM ? C::LDS_ANP : C::LDS;
     static hipError_t occ(int *bpc, size_t *lds) {
-        *lds = C::LDS;
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, k_step<T, NE, MODEL, BLOCK, EPT, MC, WPE>, BLOCK, C::LDS);
+        *lds = STEP_LDS;
+        const void *kern = reinterpret_cast<const void *>(&k_step<T, NE, MODEL, BLOCK, EPT, MC, WPE>);
+        hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(STEP_LDS));
+        if (e != hipSuccess) return e;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, k_step<T, NE, MODEL, BLOCK, EPT, MC, WPE>, BLOCK,
+                                                            STEP_LDS);
     }
     // workgroups per CU of the several-cases kernel; 0: not built
     static hipError_t occ_multi(int *bpc) {
@@ -495,10 +523,11 @@ struct Inst {
             if constexpr (has_multi()) kern = reinterpret_cast<const void *>(&k_step_multi<T, NE, MODEL, BLOCK, EPT, MC, WPE>);
             else return hipErrorInvalidValue;
         }
-        e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(C::LDS));
+        const size_t lds = a.nrhs > 1 ? C::LDS : STEP_LDS;
+        e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
         if (e != hipSuccess) return e;
         if (ev0 && (e = hipEventRecord(ev0, s)) != hipSuccess) return e;
-        e = hipLaunchCooperativeKernel(kern, dim3(c.grid), dim3(BLOCK), args, C::LDS, s);
+        e = hipLaunchCooperativeKernel(kern, dim3(c.grid), dim3(BLOCK), args, lds, s);
         if (e != hipSuccess) return e;
         if (ev1) e = hipEventRecord(ev1, s);
         return e;
@@ -634,7 +663,7 @@ hipError_t run_ops(const OpArgs &o) {
         if constexpr (FORM == 0) return forces_anp_t<T, NE>(*o.c, o.u, o.f, o.s);
         return hipErrorInvalidValue;
     }
-    return with_model<T, NE, FORM>(o.model, o.variant, [&](auto inst) -> hipError_t {
+    auto run = [&](auto inst) -> hipError_t {
         using I = decltype(inst);
         switch (o.op) {
             case Op::OCC: return I::occ(o.bpc, o.lds);
@@ -645,7 +674,17 @@ hipError_t run_ops(const OpArgs &o) {
             case Op::STEP: return I::step(*o.c, *o.a, o.u_cur_in, o.u_prev_in, o.s, o.ev0, o.ev1);
             default: return hipErrorInvalidValue;
         }
-    });
+    };
+    if constexpr (FORM == 0) {
+        // the average-nodal-pressure step (neo-Hookean and transversely isotropic)
+        if (o.anp) {
+            if (o.op == Op::FORCES || o.op == Op::OCC_MULTI) return hipErrorInvalidValue;
+            if (o.model == DJ_NH) return with_variant<T, NE, DJ_NH | DJ_FORM_ANP>(o.variant, run);
+            if (o.model == DJ_TI) return with_variant<T, NE, DJ_TI | DJ_FORM_ANP>(o.variant, run);
+            return hipErrorInvalidValue;
+        }
+    }
+    return with_model<T, NE, FORM>(o.model, o.variant, run);
 }
 
 }  // namespace dj

@@ -91,7 +91,8 @@ class Solver:
             mat.c01 = _dptr(cc)
         self.precision = L.DJ_FP64 if precision in ("fp64", L.DJ_FP64) else L.DJ_FP32
         self.dtype = torch.float64 if self.precision == L.DJ_FP64 else torch.float32
-        form = {"jacobian": L.DJ_FORM_JACOBIAN, "classical": L.DJ_FORM_CLASSICAL}.get(formulation, formulation)
+        form = {"jacobian": L.DJ_FORM_JACOBIAN, "classical": L.DJ_FORM_CLASSICAL,
+                "nodal_pressure": L.DJ_FORM_NODAL_PRESSURE}.get(formulation, formulation)
         prm = L.djtled_params(self.precision, float(dt), float(dt_factor), float(alpha), int(allow_unstable_dt),
                               int(chunk_elems), int(variant), int(device), int(form))
         self.device = torch.device("cuda", device)

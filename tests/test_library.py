@@ -64,7 +64,11 @@ def test_host_validation_errors():
     assert _call_precompute(m, precision=7) == L.DJ_ERR_UNSUPPORTED
     assert _call_precompute(m, rho=-1.0) == L.DJ_ERR_ARG
     assert _call_precompute(m, variant=-2) == L.DJ_ERR_ARG
-    assert _call_precompute(m, formulation=2) == L.DJ_ERR_ARG
+    assert _call_precompute(m, formulation=3) == L.DJ_ERR_ARG
+    # the average-nodal-pressure form: neo-Hookean / transversely isotropic, variants 0..3
+    assert _call_precompute(m, formulation=L.DJ_FORM_NODAL_PRESSURE, variant=4) == L.DJ_ERR_UNSUPPORTED
+    assert "average-nodal-pressure form" in L.lib.djtled_last_error().decode()
+    assert _call_precompute(m, formulation=L.DJ_FORM_NODAL_PRESSURE, model=L.DJ_MR) == L.DJ_ERR_UNSUPPORTED
     assert _call_precompute(m, formulation=L.DJ_FORM_CLASSICAL, precision=L.DJ_FP64) == L.DJ_ERR_UNSUPPORTED
     assert "classical TLED form" in L.lib.djtled_last_error().decode()
     assert _call_precompute(m, model=L.DJ_OT) == L.DJ_ERR_ARG  # OT needs both fibre families
