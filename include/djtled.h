@@ -308,8 +308,9 @@ typedef struct djtled_batch djtled_batch;
 typedef struct {
     int32_t autotune;          /* nonzero: choose variant, chunk size and steps per launch by timing
                                   candidates on a sample of the instances */
-    int32_t variant;           /* batch kernel variant when not tuning (FP32: 0..7, 4..7 stage element data
-                                  in LDS by prefetch; FP64: 0); <0 -> default */
+    int32_t variant;           /* batch kernel variant when not tuning (FP32: 0..8, 4..7 stage element data
+                                  in LDS by prefetch, 8 runs two workgroups per compute unit;
+                                  FP64: 0); <0 -> default */
     int32_t chunk_elems;       /* elements per workgroup tile when not tuning; 0 -> kernel capacity */
     int32_t steps_per_launch;  /* persistent-launch length inside a run; 0 -> the whole run */
     int32_t use_graph;         /* nonzero: each run replays a captured hipGraph */

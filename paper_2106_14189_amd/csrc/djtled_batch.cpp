@@ -201,7 +201,7 @@ int build_batch(Batch &b, const std::vector<int> &sel, const djtled_mesh *meshes
             umat.fibre = fib.data();
         }
         djtled_params kp = *prm;
-        kp.variant = variant & 3;  // the chunk geometry of the batch kernel's variant (4..7: 0..3 + prefetch)
+        kp.variant = batch_geometry(variant);  // the chunk geometry of the batch kernel's variant
         kp.chunk_elems = chunk_elems;
         kp.dt = 0.0;
         MultiInst mi;
@@ -285,7 +285,12 @@ int build_batch(Batch &b, const std::vector<int> &sel, const djtled_mesh *meshes
     DJ_HIP(hipMemset(b.d_status, 0, 8 * sizeof(int32_t)));
     DJ_HIP(balloc(b, &b.d_clock, 2));
     DJ_HIP(hipMemset(b.d_clock, 0, 2 * sizeof(int64_t)));
+#ifdef DJ_INSTR
+    DJ_HIP(balloc(b, &b.d_ts, size_t(18) * b.grid));  // + 16 sub-phase counters per workgroup
+    DJ_HIP(hipMemset(b.d_ts, 0, size_t(18) * b.grid * sizeof(uint64_t)));
+#else
     DJ_HIP(balloc(b, &b.d_ts, size_t(2) * b.grid));
+#endif
     DJ_HIP(hipHostMalloc(reinterpret_cast<void **>(&b.h_status), 8 * sizeof(int32_t), hipHostMallocDefault));
     DJ_HIP(hipHostMalloc(reinterpret_cast<void **>(&b.h_clock), 2 * sizeof(int64_t), hipHostMallocDefault));
     DJ_HIP(hipHostMalloc(reinterpret_cast<void **>(&b.h_ts), size_t(2) * b.grid * sizeof(uint64_t),
@@ -505,7 +510,7 @@ int djtled_batch_create(int32_t n, const djtled_mesh *meshes, const djtled_mater
         const int m = std::max(1, std::min(8, n / 16));
         std::vector<int> sub;
         for (int i = 0; i < n; i += m) sub.push_back(i);
-        std::vector<int> vs = prec == DJ_FP32 ? std::vector<int>{1, 2, 5, 6, 0, 3, 4, 7} : std::vector<int>{0};
+        std::vector<int> vs = prec == DJ_FP32 ? std::vector<int>{1, 2, 5, 6, 0, 3, 4, 7, 8} : std::vector<int>{0};
         std::vector<std::pair<double, std::pair<int, int>>> ranked;  // time per element-step, (variant, chunk)
         for (int v : vs)
             for (int cf : {0, 2}) {
@@ -654,6 +659,18 @@ int djtled_batch_run(djtled_batch *p, int32_t n_steps, djtled_status *out, void 
     DJ_HIP(hipSetDevice(b.device));
     return run_batch(b, n_steps, out, static_cast<hipStream_t>(stream));
 }
+
+#ifdef DJ_INSTR
+// instrumented build only: per-workgroup sub-phase counters (16 each)
+int djtled_batch_instr(djtled_batch *p, uint64_t *out, int clear) {
+    Batch &b = *reinterpret_cast<Batch *>(p);
+    DJ_HIP(hipDeviceSynchronize());
+    DJ_HIP(instr_set(b.d_ts + 2 * size_t(b.grid)));
+    DJ_HIP(hipMemcpy(out, b.d_ts + 2 * size_t(b.grid), size_t(16) * b.grid * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    if (clear) DJ_HIP(hipMemset(b.d_ts + 2 * size_t(b.grid), 0, size_t(16) * b.grid * sizeof(uint64_t)));
+    return b.grid;
+}
+#endif
 
 int djtled_batch_stats(const djtled_batch *p, double *inst_ms) {
     if (!p || !inst_ms) return fail(DJ_ERR_ARG, "null argument");

@@ -32,6 +32,10 @@ struct BatchDev {
 };
 
 bool batch_variant_ok(int prec, int v);
+int batch_geometry(int v);  // the step-kernel variant whose chunk geometry batch variant v uses
+#ifdef DJ_INSTR
+hipError_t instr_set(uint64_t *p);  // instrumented build: the sub-phase counter array
+#endif
 hipError_t batch_occupancy(int prec, int v, int *blocks_per_cu, size_t *lds, int *block);
 hipError_t launch_batch_step(const BatchDev &bd, int prec, int v, int grid, hipStream_t s);
 hipError_t launch_batch_reset(uint32_t *bar, int n_sync, int32_t *status, bool clear_status, hipStream_t s);

@@ -22,10 +22,15 @@ namespace {
 
 // Batch variant V: 0..3 use the step-kernel tables' variants 0..3 for every
 // kind; V + 4 is the same with the element data staged in LDS by prefetch.
+// 8 trades registers for occupancy: the chunk geometry of variant 2 (512
+// threads) compiled for 4 waves per SIMD, i.e. two workgroups per compute
+// unit (its registers spill), with the element phase in plain order.
 template <typename T, int V>
 struct Kinds {
-    static constexpr int VB = V & 3;
-    static constexpr bool PF = V >= 4;
+    static constexpr int VB = V < 8 ? (V & 3) : 2;
+    static constexpr bool PF = V >= 4 && V < 8;
+    static constexpr int WPE = V < 8 ? 1 : 4;                 // minimum waves per SIMD
+    static constexpr bool PIPE = sizeof(T) == 4 && V < 8;     // software-pipelined element phase
     static constexpr Variant v4 = var_table<T, 4>()[VB];
     static constexpr Variant v8 = var_table<T, 8>()[VB];
     static_assert(v4.block == v8.block, "one block size for all element kinds");
@@ -64,7 +69,6 @@ __device__ __forceinline__ StepPtrs<T> kind_ptrs(const BatchKind &kd, int cur, i
         sp.un[k] = un + k * L;
         sp.ru[k] = ru ? ru + k * L : nullptr;
     }
-#pragma unroll
     for (int k = 0; k < 3; k++) sp.pp[k] = static_cast<T *>(kd.part) + ((s & 1) * 3 + k) * int64_t(kd.tp.n_part);
     sp.flags = kd.flags;
     sp.acoef = static_cast<const T *>(kd.tp.acoef);
@@ -80,7 +84,7 @@ __device__ __forceinline__ StepPtrs<T> kind_ptrs(const BatchKind &kd, int cur, i
 }
 
 template <typename T, int V>
-__global__ void __launch_bounds__((Kinds<T, V>::BLOCK)) k_batch_step(BatchDev bd) {
+__global__ void __launch_bounds__((Kinds<T, V>::BLOCK), (Kinds<T, V>::WPE)) k_batch_step(BatchDev bd) {
     using K = Kinds<T, V>;
     constexpr int BLOCK = K::BLOCK;
     constexpr int KB = 4;  // chunks per shared-phase batch
@@ -124,19 +128,52 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK)) k_batch_step(BatchDev bd
     for (s = 0; s < bd.n_steps; s++) {
         const int nxt = (cur + 1) % 3, prv = (cur + 2) % 3;
         const int64_t n = step0 + s;
+        INSTR_T(t0);
         PhaseOut po{0.0, 0.0, 0, -1};
         int bad_kind = -1;
-        for (int k = 0; k < nmine; k++) {
-            const int kind = __builtin_amdgcn_readfirstlane(s_kind[k]);
-            const int kn = k + 1 < nmine ? k + 1 : 0;
+        // FP32: runs of consecutive chunks of one kind, software-pipelined as in
+        // the single-mesh kernel: the copy data of chunk k + 1 is loaded while
+        // chunk k is summed and updated, the element data of a chunk is in
+        // flight during its scatter, and its load values are fetched after it.
+        // FP64 and the occupancy variants keep the plain order (their
+        // registers do not hold the pipeline).
+        if constexpr (!K::PIPE) {
+            for (int k = 0; k < nmine; k++) {
+                const int kind = __builtin_amdgcn_readfirstlane(s_kind[k]);
+                const int kn = k + 1 < nmine ? k + 1 : 0;
+                on_kind(kind, [&](auto kc) {
+                    constexpr int KC = decltype(kc)::value;
+                    const StepPtrs<T> sp = kind_ptrs<T>(bd.k[KC], cur, prv, nxt, s, n);
+                    K::template C<KC>::template element_phase<1>(bd.k[KC].tp, s_ch[k], sp, smem, po,
+                                                                  [&]() { prefetch(kn); });
+                });
+                if (po.bad && bad_kind < 0) bad_kind = kind;
+            }
+        } else
+        for (int k0 = 0; k0 < nmine;) {
+            const int kind = __builtin_amdgcn_readfirstlane(s_kind[k0]);
+            int k1 = k0 + 1;
+            while (k1 < nmine && s_kind[k1] == kind) k1++;
             on_kind(kind, [&](auto kc) {
                 constexpr int KC = decltype(kc)::value;
+                using CK = typename K::template C<KC>;
                 const StepPtrs<T> sp = kind_ptrs<T>(bd.k[KC], cur, prv, nxt, s, n);
-                K::template C<KC>::template element_phase<1>(bd.k[KC].tp, s_ch[k], sp, smem, po,
-                                                              [&]() { prefetch(kn); });
+                typename CK::CopyRegs cp;
+                CK::template load_copies<1>(bd.k[KC].tp, s_ch[k0], sp, cp);
+                for (int k = k0; k < k1; k++) {
+                    const int kn = k + 1 < nmine ? k + 1 : 0;
+                    typename CK::ElemRegs er;
+                    CK::load_elems(bd.k[KC].tp, s_ch[k], er);
+                    CK::template process<1, true>(bd.k[KC].tp, s_ch[k], sp, smem, po, er, cp, [&]() {
+                        prefetch(kn);
+                        if (k + 1 < k1) CK::template load_copies<1>(bd.k[KC].tp, s_ch[k + 1], sp, cp);
+                    });
+                }
             });
             if (po.bad && bad_kind < 0) bad_kind = kind;
+            k0 = k1;
         }
+        INSTR_T(t1);
         // shared-node batches: up to KB consecutive chunks of one kind
         auto batch_len = [&](int k0) {
             int nb = 1;
@@ -161,10 +198,12 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK)) k_batch_step(BatchDev bd
                 bd.status[3] = int32_t(n);  // absolute step index
             }
         }
+        INSTR_T(t2);
         if (!grid_barrier(bd.bar, G, epoch, bd.status)) {
             code = DJ_ERR_BARRIER;
             break;
         }
+        INSTR_T(t3);
         if (threadIdx.x == 0) s_flag = ld_dev(errw);
         __syncthreads();
         if (s_flag != 0) {
@@ -195,6 +234,14 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK)) k_batch_step(BatchDev bd
         if (po.bad && po.bad_elem <= -2)
             publish_late_error(bd.status, s, po.bad, (late_kind << 28) | (1 << 27) | (-2 - po.bad_elem), int32_t(n));
         __syncthreads();  // shared copies written above are read by other threads next step
+#ifdef DJ_INSTR
+        INSTR_T(t4);
+        instr_add(0, t1 - t0);
+        instr_add(1, t2 - t1);
+        instr_add(2, t3 - t2);
+        instr_add(7, t4 - t3);
+        instr_add(8, 1);
+#endif
         cur = nxt;
     }
     __builtin_amdgcn_s_waitcnt(0);  // no staged load outlives the workgroup
@@ -273,6 +320,7 @@ hipError_t batch_dispatch(int prec, int v, F &&f) {
             case 5: return f(std::integral_constant<int, 5>(), float());
             case 6: return f(std::integral_constant<int, 6>(), float());
             case 7: return f(std::integral_constant<int, 7>(), float());
+            case 8: return f(std::integral_constant<int, 8>(), float());
             default: return hipErrorInvalidValue;
         }
     }
@@ -282,7 +330,16 @@ hipError_t batch_dispatch(int prec, int v, F &&f) {
 
 }  // namespace
 
-bool batch_variant_ok(int prec, int v) { return prec == DJ_FP32 ? (v >= 0 && v < 8) : v == 0; }
+#ifdef DJ_INSTR
+hipError_t instr_set(uint64_t *p) {
+    unsigned long long *q = reinterpret_cast<unsigned long long *>(p);
+    return hipMemcpyToSymbol(HIP_SYMBOL(dj_instr_buf), &q, sizeof(q));
+}
+#endif
+
+bool batch_variant_ok(int prec, int v) { return prec == DJ_FP32 ? (v >= 0 && v < 9) : v == 0; }
+
+int batch_geometry(int v) { return v < 8 ? (v & 3) : 2; }
 
 hipError_t batch_occupancy(int prec, int v, int *bpc, size_t *lds, int *block) {
     return batch_dispatch(prec, v, [&](auto vc, auto t) {

@@ -42,6 +42,19 @@
 
 namespace dj {
 
+// Sub-phase timers of the step kernels, compiled only into a separate
+// instrumented build (-DDJ_INSTR): thread 0 of each workgroup adds wall-clock
+// ticks (100 MHz) of each phase into its 16 counters.
+#ifdef DJ_INSTR
+static __device__ unsigned long long *dj_instr_buf;
+__device__ __forceinline__ void instr_add(int k, unsigned long long v) {
+    if (threadIdx.x == 0 && dj_instr_buf) dj_instr_buf[blockIdx.x * 16 + k] += v;
+}
+#define INSTR_T(x) const unsigned long long x = wall_clock64()
+#else
+#define INSTR_T(x)
+#endif
+
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
@@ -108,7 +121,8 @@ __device__ __forceinline__ T ld_dev(const T *p) {
 // Partial node forces: three planes (x, y, z) over the partial entries of
 // one step parity; each component is published and read with a device-scope
 // access.  Entries of neighbouring nodes are adjacent in each plane, so a
-// wave's stores of one component fall on few cache lines.
+// wave's stores of one component fall on few cache lines.  (One 16-byte entry
+// per partial, read as two 64-bit words, measured no faster.)
 template <typename T>
 __device__ __forceinline__ void put_partial(T *const (&pp)[3], int q, const T (&f)[3]) {
 #pragma unroll
@@ -696,6 +710,7 @@ struct Chunk {
     __device__ static void process(const DevTopo &tp, const ChunkDesc &ch, const StepPtrs<T> &sp, unsigned char *smem,
                                    PhaseOut &po, ElemRegs &er, CopyRegs &cin, After after) {
         const int tid = threadIdx.x;
+        INSTR_T(i0);
         T *lx = reinterpret_cast<T *>(smem);
         T *ly = lx + NE * CMAX;
         T *lz = lx + 2 * NE * CMAX;
@@ -718,6 +733,7 @@ struct Chunk {
         if constexpr (RV) load_rv<MODE>(ch, sp, cin);
         if constexpr (PF) __builtin_amdgcn_s_waitcnt(0);  // this thread's staged loads have landed
         __syncthreads();
+        INSTR_T(i1);
         if constexpr (PF) {
             const T *stage = reinterpret_cast<const T *>(smem + SLOTS);
             const uint16_t *wstage = reinterpret_cast<const uint16_t *>(smem + SLOTS) + 2 * NP * PDW + (ch.elem_begin & 1);
@@ -781,6 +797,7 @@ struct Chunk {
             }
         }
         __syncthreads();
+        INSTR_T(i2);
         const CopyRegs c = cin;
         after();
         // ---- node sums over each copy's range, in fixed order
@@ -817,6 +834,13 @@ struct Chunk {
             }
         }
         __syncthreads();  // LDS is reused by the next chunk
+#ifdef DJ_INSTR
+        INSTR_T(i3);
+        instr_add(3, i1 - i0);
+        instr_add(4, i2 - i1);
+        instr_add(5, i3 - i2);
+        instr_add(6, 1);
+#endif
     }
 
     // Round A for the shared copies of up to KB chunks (one per thread per

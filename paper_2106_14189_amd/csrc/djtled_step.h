@@ -253,8 +253,8 @@ __global__ void __launch_bounds__(BLOCK, WPE) k_step_multi(DevTopo tp, StepArgs 
                 sp.up[k] = ub(prv) + uo + k * L;
                 sp.un[k] = ub(nxt) + uo + k * L;
                 sp.ru[k] = ru ? ru + k * L : nullptr;
-                sp.pp[k] = part + ((int64_t(r) * 2 + (s & 1)) * 3 + k) * NPART;
             }
+            for (int k = 0; k < 3; k++) sp.pp[k] = part + ((int64_t(r) * 2 + (s & 1)) * 3 + k) * NPART;
             sp.flags = a.flags + int64_t(r) * L;
             sp.acoef = static_cast<const T *>(tp.acoef);
             sp.bprime = T(a.bprime);

@@ -107,10 +107,10 @@ class Solver:
             L.lib.djtled_destroy(self.handle)
             self.handle = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # nothing is released while the interpreter shuts down: the HIP
         # runtime may already be torn down by then (close() explicitly)
-        if sys.is_finalizing():
+        if _finalizing():
             return
         try:
             self.close()
@@ -318,10 +318,10 @@ class Batch:
             L.lib.djtled_batch_destroy(self.handle)
             self.handle = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # nothing is released while the interpreter shuts down: the HIP
         # runtime may already be torn down by then (close() explicitly)
-        if sys.is_finalizing():
+        if _finalizing():
             return
         try:
             self.close()

@@ -75,7 +75,8 @@ def _oracle_run(mesh, mat, ld, alpha, dt, n_steps, omp=False):
 
 
 @pytest.mark.parametrize("prec,variant", [("fp32", 1), ("fp32", 0), ("fp32", 2), ("fp32", 3), ("fp32", 4), ("fp32", 5),
-                                          ("fp32", 6), ("fp32", 7), ("fp64", 0)])
+                                          ("fp32", 6), ("fp32", 7), ("fp32", 8),
+                                          ("fp64", 0)])
 def test_batch_matches_oracle_per_instance(S, prec, variant):
     n_steps = 160
     spec = _mixed(n_steps)
