@@ -245,7 +245,8 @@ typedef struct {
  * then prescribed components are set to s(t_{n+1}) * target.
  * RELAX: every check_every steps, once the ramp is complete, the residual
  * |(F - R)_free|_2 / |F_constrained|_2 of u^n is evaluated and the run stops
- * without advancing when it is <= tol (code DJ_CONVERGED).
+ * without advancing when it is <= tol (code DJ_CONVERGED); with no reaction force the residual is taken as
+ * infinite (it is relative to the reaction), so a run never stops there.
  * On return state->u_cur / u_prev / step hold the last completed step; on
  * DJ_ERR_INVERTED, and on DJ_ERR_NONFINITE found in an element, that is the
  * step before the failing one.  A non-finite displacement produced at a node

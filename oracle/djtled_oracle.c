@@ -851,7 +851,10 @@ static double ramp_value(int ramp, double t, double t_ramp) {
     return tau * tau * tau * (10.0 - 15.0 * tau + 6.0 * tau * tau);
 }
 
-/* Dynamic relaxation residual |(F - R)_free|_2 / |F_constrained|_2. */
+/* Dynamic relaxation residual |(F - R)_free|_2 / |F_constrained|_2.  It is
+   relative to the reaction at the constrained components; with no reaction
+   (for instance at a start from rest before any prescribed value is applied)
+   it is undefined and taken as infinite, so a relaxation never stops there. */
 static double residual_of(const ora_ctx *c, const double *f, const double *R, const unsigned char *cmask) {
     double num = 0.0, den = 0.0;
     for (int i = 0; i < 3 * c->n_nodes; i++) {
@@ -859,7 +862,7 @@ static double residual_of(const ora_ctx *c, const double *f, const double *R, co
         if (cmask[i]) den += f[i] * f[i]; else num += r * r;
     }
     if (den > 0.0) return sqrt(num) / sqrt(den);
-    return num > 0.0 ? INFINITY : 0.0;
+    return INFINITY;
 }
 
 /*

@@ -163,7 +163,8 @@ __global__ void __launch_bounds__(BLOCK, WPE) k_step(DevTopo tp, StepArgs a) {
             }
             block_sum2<BLOCK>(sx, sy, sred);
             if (threadIdx.x == 0) {
-                const double r = sy > 0.0 ? sqrt(sx) / sqrt(sy) : (sx > 0.0 ? INFINITY : 0.0);
+                // no reaction force (e.g. prescribed values not yet applied): undefined, not converged
+                const double r = sy > 0.0 ? sqrt(sx) / sqrt(sy) : INFINITY;
                 s_flag = (r <= a.tol) ? 1 : 0;
                 if (blockIdx.x == 0) *a.res_out = r;
             }
@@ -377,7 +378,7 @@ __global__ void __launch_bounds__(BLOCK, WPE) k_step_multi(DevTopo tp, StepArgs 
                 }
                 block_sum2<BLOCK>(sx, sy, sred);
                 if (threadIdx.x == 0) {
-                    const double res = sy > 0.0 ? sqrt(sx) / sqrt(sy) : (sx > 0.0 ? INFINITY : 0.0);
+                    const double res = sy > 0.0 ? sqrt(sx) / sqrt(sy) : INFINITY;
                     conv &= (res <= a.tol) ? 1 : 0;
                     if (blockIdx.x == 0) a.res_out[r] = res;
                 }
