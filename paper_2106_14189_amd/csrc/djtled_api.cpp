@@ -246,9 +246,7 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     if (nch > E) nch = E;
     c.chunk_elems = int((E + nch - 1) / nch);
     c.grid = int(std::min<int64_t>(nch, gmax));
-    if (!in_batch && (nch + c.grid - 1) / c.grid > KMAX)
-        return fail(DJ_ERR_UNSUPPORTED, "mesh needs more than " + std::to_string(KMAX) +
-                                            " chunks per workgroup; use a variant with more workgroups");
+    // (a workgroup with more than KMAX chunks reads its chunk list in windows)
     chunks.assign(nch, ChunkDesc{});
     crange.clear();
     wpos.assign(size_t(NE) * estride, 0);
@@ -643,6 +641,9 @@ int step_cases(djtled_ctx *ctx, int nrhs, djtled_state *st, const djtled_loadset
     if (c.n_inst > 1) return fail(DJ_ERR_ARG, "batch contexts step through djtled_batch_run");
     if (nrhs > 1 && (c.prec != DJ_FP32 || c.form != DJ_FORM_JACOBIAN || c.variant >= 4))
         return fail(DJ_ERR_UNSUPPORTED, "several load cases per launch: FP32, Jacobian form, variants 0..3");
+    if (nrhs > 1 && (c.topo.n_chunks + c.grid - 1) / c.grid > KMAX)
+        return fail(DJ_ERR_UNSUPPORTED, "several load cases per launch: at most " + std::to_string(KMAX) +
+                                            " chunks per workgroup");
     // load sets: all absent, or one per case with a common ramp
     const bool has_loads = lsp && lsp[0];
     for (int r = 0; r < nrhs; r++) {

@@ -255,9 +255,10 @@ int build_batch(Batch &b, const std::vector<int> &sel, const djtled_mesh *meshes
     if (bpc < 1) return fail(DJ_ERR_UNSUPPORTED, "batch kernel variant does not fit on a compute unit");
     b.block = blk;
     b.grid = std::min(bpc * prop.multiProcessorCount, b.n_items);
-    if ((b.n_items + b.grid - 1) / b.grid > KMAXB)
+    // the prefetch variants keep every work item of a workgroup in its LDS list
+    if (variant >= 4 && variant < 8 && (b.n_items + b.grid - 1) / b.grid > KMAXB)
         return fail(DJ_ERR_UNSUPPORTED, "batch needs more than " + std::to_string(KMAXB) +
-                                            " chunks per workgroup; use larger chunks");
+                                            " chunks per workgroup for the prefetch variants 4..7");
     // workgroups holding each instance's chunks (for per-instance completion times)
     b.inst_wgs.assign(b.n_inst, {});
     for (int j = 0; j < b.n_items; j++) {

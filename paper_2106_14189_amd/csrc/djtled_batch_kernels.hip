@@ -95,16 +95,31 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK), (Kinds<T, V>::WPE)) k_ba
     __shared__ int s_flag;
     const uint32_t G = gridDim.x;
     const int nmine = int(blockIdx.x) < bd.n_items ? (bd.n_items - int(blockIdx.x) + int(G) - 1) / int(G) : 0;
-    for (int k = threadIdx.x; k < nmine; k += BLOCK) {
-        const int w = bd.work[blockIdx.x + k * G];
-        const int kind = w >> 28, idx = w & 0x0fffffff;
-        const ChunkDesc *cp = kind == 0 ? bd.k[0].tp.chunks
-                            : kind == 1 ? bd.k[1].tp.chunks
-                            : kind == 2 ? bd.k[2].tp.chunks
-                                        : bd.k[3].tp.chunks;
-        s_ch[k] = cp[idx];
-        s_kind[k] = kind;
-    }
+    // the workgroup's work items (kind, chunk descriptor) from w0 on: all in
+    // LDS when they fit, otherwise in windows of KMAXB refilled as the loops
+    // advance (batches too large for one list; not the prefetch variants)
+    auto fill = [&](int w0, int wn) {
+        for (int k = threadIdx.x; k < wn; k += BLOCK) {
+            const int w = bd.work[blockIdx.x + (w0 + k) * G];
+            const int kind = w >> 28, idx = w & 0x0fffffff;
+            const ChunkDesc *cp = kind == 0 ? bd.k[0].tp.chunks
+                                : kind == 1 ? bd.k[1].tp.chunks
+                                : kind == 2 ? bd.k[2].tp.chunks
+                                            : bd.k[3].tp.chunks;
+            s_ch[k] = cp[idx];
+            s_kind[k] = kind;
+        }
+    };
+    auto window = [&](int w0) {
+        const int wn = min(KMAXB, nmine - w0);
+        if (nmine > KMAXB) {
+            __syncthreads();  // no thread still reads the previous window
+            fill(w0, wn);
+            __syncthreads();
+        }
+        return wn;
+    };
+    fill(0, min(nmine, KMAXB));
     if (threadIdx.x == 0) s_flag = bd.status[0];
     __syncthreads();
     if (s_flag != 0) return;  // an earlier launch of this run stopped on an error
@@ -137,10 +152,12 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK), (Kinds<T, V>::WPE)) k_ba
         // flight during its scatter, and its load values are fetched after it.
         // FP64 and the occupancy variants keep the plain order (their
         // registers do not hold the pipeline).
+        for (int w0 = 0; w0 < nmine; w0 += KMAXB) {
+        const int wn = window(w0);
         if constexpr (!K::PIPE) {
-            for (int k = 0; k < nmine; k++) {
+            for (int k = 0; k < wn; k++) {
                 const int kind = __builtin_amdgcn_readfirstlane(s_kind[k]);
-                const int kn = k + 1 < nmine ? k + 1 : 0;
+                const int kn = k + 1 < wn ? k + 1 : 0;
                 on_kind(kind, [&](auto kc) {
                     constexpr int KC = decltype(kc)::value;
                     const StepPtrs<T> sp = kind_ptrs<T>(bd.k[KC], cur, prv, nxt, s, n);
@@ -150,10 +167,10 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK), (Kinds<T, V>::WPE)) k_ba
                 if (po.bad && bad_kind < 0) bad_kind = kind;
             }
         } else
-        for (int k0 = 0; k0 < nmine;) {
+        for (int k0 = 0; k0 < wn;) {
             const int kind = __builtin_amdgcn_readfirstlane(s_kind[k0]);
             int k1 = k0 + 1;
-            while (k1 < nmine && s_kind[k1] == kind) k1++;
+            while (k1 < wn && s_kind[k1] == kind) k1++;
             on_kind(kind, [&](auto kc) {
                 constexpr int KC = decltype(kc)::value;
                 using CK = typename K::template C<KC>;
@@ -161,7 +178,7 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK), (Kinds<T, V>::WPE)) k_ba
                 typename CK::CopyRegs cp;
                 CK::template load_copies<1>(bd.k[KC].tp, s_ch[k0], sp, cp);
                 for (int k = k0; k < k1; k++) {
-                    const int kn = k + 1 < nmine ? k + 1 : 0;
+                    const int kn = k + 1 < wn ? k + 1 : 0;
                     typename CK::ElemRegs er;
                     CK::load_elems(bd.k[KC].tp, s_ch[k], er);
                     CK::template process<1, true>(bd.k[KC].tp, s_ch[k], sp, smem, po, er, cp, [&]() {
@@ -173,15 +190,17 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK), (Kinds<T, V>::WPE)) k_ba
             if (po.bad && bad_kind < 0) bad_kind = kind;
             k0 = k1;
         }
+        }
         INSTR_T(t1);
-        // shared-node batches: up to KB consecutive chunks of one kind
-        auto batch_len = [&](int k0) {
+        // shared-node batches: up to KB consecutive chunks of one kind (window wn)
+        auto batch_len = [&](int k0, int wn) {
             int nb = 1;
-            while (nb < KB && k0 + nb < nmine && s_kind[k0 + nb] == s_kind[k0]) nb++;
+            while (nb < KB && k0 + nb < wn && s_kind[k0 + nb] == s_kind[k0]) nb++;
             return nb;
         };
+        const int wn0 = nmine > 0 ? window(0) : 0;
         SharedRegs<T, KB> sr;
-        const int nb0 = nmine > 0 ? batch_len(0) : 0;
+        const int nb0 = nmine > 0 ? batch_len(0, wn0) : 0;
         const int kind0 = nmine > 0 ? __builtin_amdgcn_readfirstlane(s_kind[0]) : 0;
         if (nmine > 0)
             on_kind(kind0, [&](auto kc) {
@@ -219,16 +238,19 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK), (Kinds<T, V>::WPE)) k_ba
                 CS::template shared_batch<1, KB>(bd.k[KC].tp, s_ch, nb0, 1, sp, po);
             });
         int late_kind = po.bad ? kind0 : -1;
-        for (int k0 = nb0; k0 < nmine;) {
-            const int nb = batch_len(k0);
-            const int kind = __builtin_amdgcn_readfirstlane(s_kind[k0]);
-            on_kind(kind, [&](auto kc) {
-                constexpr int KC = decltype(kc)::value;
-                const StepPtrs<T> sp = kind_ptrs<T>(bd.k[KC], cur, prv, nxt, s, n);
-                CS::template shared_batch<1, KB>(bd.k[KC].tp, s_ch + k0, nb, 0, sp, po);
-            });
-            if (po.bad && late_kind < 0) late_kind = kind;
-            k0 += nb;
+        for (int w0 = 0; w0 < nmine; w0 += KMAXB) {
+            const int wn = w0 == 0 ? wn0 : window(w0);
+            for (int k0 = w0 == 0 ? nb0 : 0; k0 < wn;) {
+                const int nb = batch_len(k0, wn);
+                const int kind = __builtin_amdgcn_readfirstlane(s_kind[k0]);
+                on_kind(kind, [&](auto kc) {
+                    constexpr int KC = decltype(kc)::value;
+                    const StepPtrs<T> sp = kind_ptrs<T>(bd.k[KC], cur, prv, nxt, s, n);
+                    CS::template shared_batch<1, KB>(bd.k[KC].tp, s_ch + k0, nb, 0, sp, po);
+                });
+                if (po.bad && late_kind < 0) late_kind = kind;
+                k0 += nb;
+            }
         }
         // a node-level error of the shared-node phase stops the run at the next barrier
         if (po.bad && po.bad_elem <= -2)

@@ -44,8 +44,19 @@ __global__ void __launch_bounds__(BLOCK, WPE) k_step(DevTopo tp, StepArgs a) {
     const int64_t NPART = tp.n_part;
     const uint32_t G = gridDim.x;
     const int nmine = int(blockIdx.x) < tp.n_chunks ? (tp.n_chunks - int(blockIdx.x) + int(G) - 1) / int(G) : 0;
-    for (int k = threadIdx.x; k < nmine; k += BLOCK) s_ch[k] = tp.chunks[blockIdx.x + k * G];
+    for (int k = threadIdx.x; k < min(nmine, KMAX); k += BLOCK) s_ch[k] = tp.chunks[blockIdx.x + k * G];
     __syncthreads();
+    // The workgroup's chunk descriptors: all in LDS when they fit, otherwise
+    // in windows of KMAX refilled as the loops below advance (large meshes).
+    auto window = [&](int w0) {
+        const int wn = min(KMAX, nmine - w0);
+        if (nmine > KMAX) {
+            __syncthreads();  // no thread still reads the previous window
+            for (int k = threadIdx.x; k < wn; k += BLOCK) s_ch[k] = tp.chunks[blockIdx.x + (w0 + k) * G];
+            __syncthreads();
+        }
+        return wn;
+    };
     uint32_t epoch = 0;  // the flags are cleared before every launch
     T *const ub0 = static_cast<T *>(a.ubuf[0]), *const ub1 = static_cast<T *>(a.ubuf[1]),
             *const ub2 = static_cast<T *>(a.ubuf[2]);
@@ -89,12 +100,18 @@ __global__ void __launch_bounds__(BLOCK, WPE) k_step(DevTopo tp, StepArgs a) {
             T *jpart = static_cast<T *>(a.anp_jpart);
             const T *cn = static_cast<const T *>(a.anp_c);
             T *pnb = static_cast<T *>(a.anp_p);
-            for (int k = 0; k < nmine; k++) C::anp_j_phase(tp, s_ch[k], sp, jpart, cn, pnb, smem);
+            for (int w0 = 0; w0 < nmine; w0 += KMAX) {
+                const int wn = window(w0);
+                for (int k = 0; k < wn; k++) C::anp_j_phase(tp, s_ch[k], sp, jpart, cn, pnb, smem);
+            }
             if (!grid_barrier(a.bar, G, epoch, a.status)) {
                 code = DJ_ERR_BARRIER;
                 break;
             }
-            for (int k = 0; k < nmine; k++) C::anp_j_shared(tp, s_ch[k], sp, jpart, cn, pnb);
+            for (int w0 = 0; w0 < nmine; w0 += KMAX) {
+                const int wn = window(w0);
+                for (int k = 0; k < wn; k++) C::anp_j_shared(tp, s_ch[k], sp, jpart, cn, pnb);
+            }
             __syncthreads();  // pressures written above by one thread are scattered by another
             sp.pn = pnb;
         }
@@ -104,22 +121,26 @@ __global__ void __launch_bounds__(BLOCK, WPE) k_step(DevTopo tp, StepArgs a) {
         // boundary, measured slower: it does not fit the register budget of
         // two waves per SIMD, or it competes with the shared phase's loads.)
         // Variants built for three waves per SIMD keep the plain order.
-        if constexpr (WPE >= 3) {
-            for (int k = 0; k < nmine; k++) C::template element_phase<1>(tp, s_ch[k], sp, smem, po);
-        } else {
-            typename C::CopyRegs cp;
-            if (nmine > 0) C::template load_copies<1>(tp, s_ch[0], sp, cp);
-            for (int k = 0; k < nmine; k++) {
-                typename C::ElemRegs er;
-                C::load_elems(tp, s_ch[k], er);
-                C::template process<1, true>(tp, s_ch[k], sp, smem, po, er, cp, [&]() {
-                    if (k + 1 < nmine) C::template load_copies<1>(tp, s_ch[k + 1], sp, cp);
-                });
+        for (int w0 = 0; w0 < nmine; w0 += KMAX) {
+            const int wn = window(w0);
+            if constexpr (WPE >= 3) {
+                for (int k = 0; k < wn; k++) C::template element_phase<1>(tp, s_ch[k], sp, smem, po);
+            } else {
+                typename C::CopyRegs cp;
+                C::template load_copies<1>(tp, s_ch[0], sp, cp);
+                for (int k = 0; k < wn; k++) {
+                    typename C::ElemRegs er;
+                    C::load_elems(tp, s_ch[k], er);
+                    C::template process<1, true>(tp, s_ch[k], sp, smem, po, er, cp, [&]() {
+                        if (k + 1 < wn) C::template load_copies<1>(tp, s_ch[k + 1], sp, cp);
+                    });
+                }
             }
         }
         // round A of the first batch of shared copies, in flight during the barrier
+        const int wn0 = nmine > 0 ? window(0) : 0;
         SharedRegs<T, KB> sr;
-        C::template shared_load<1, KB>(tp, s_ch, min(KB, nmine), 0, sp, sr);
+        C::template shared_load<1, KB>(tp, s_ch, min(KB, wn0), 0, sp, sr);
         // Errors of step s go to the error word of parity s & 1, which nobody
         // writes again before every workgroup has read it after this barrier.
         int32_t *errw = &a.status[5 + (s & 1)];
@@ -140,8 +161,11 @@ __global__ void __launch_bounds__(BLOCK, WPE) k_step(DevTopo tp, StepArgs a) {
             break;
         }
         C::template shared_finish<1, KB>(tp, sr, sp, po);
-        for (int k0 = 0; k0 < nmine; k0 += KB)
-            C::template shared_batch<1, KB>(tp, s_ch + k0, min(KB, nmine - k0), k0 == 0 ? 1 : 0, sp, po);
+        for (int w0 = 0; w0 < nmine; w0 += KMAX) {
+            const int wn = w0 == 0 ? wn0 : window(w0);
+            for (int k0 = 0; k0 < wn; k0 += KB)
+                C::template shared_batch<1, KB>(tp, s_ch + k0, min(KB, wn - k0), (w0 == 0 && k0 == 0) ? 1 : 0, sp, po);
+        }
         if (po.bad) publish_late_error(a.status, s, po.bad, po.bad_elem, s);
         if (check) {
             double x = po.num, y = po.den;
@@ -191,16 +215,19 @@ __global__ void __launch_bounds__(BLOCK, WPE) k_step(DevTopo tp, StepArgs a) {
     const int prv = (cur + 2) % 3;
     T *oc = static_cast<T *>(a.u_out_cur);
     T *op = static_cast<T *>(a.u_out_prev);
-    for (int k = 0; k < nmine; k++) {
-        const ChunkDesc ch = s_ch[k];
-        for (int i = threadIdx.x; i < ch.copy_count; i += BLOCK) {
-            const int l = ch.copy_begin + i;
-            if (!(tp.flags[l] & FLAG_CANON)) continue;
-            const int nd = tp.cnode[l];
+    for (int w0 = 0; w0 < nmine; w0 += KMAX) {
+        const int wn = window(w0);
+        for (int k = 0; k < wn; k++) {
+            const ChunkDesc ch = s_ch[k];
+            for (int i = threadIdx.x; i < ch.copy_count; i += BLOCK) {
+                const int l = ch.copy_begin + i;
+                if (!(tp.flags[l] & FLAG_CANON)) continue;
+                const int nd = tp.cnode[l];
 #pragma unroll
-            for (int c3 = 0; c3 < 3; c3++) {
-                oc[3 * nd + c3] = ub(cur)[c3 * L + l];
-                op[3 * nd + c3] = ub(prv)[c3 * L + l];
+                for (int c3 = 0; c3 < 3; c3++) {
+                    oc[3 * nd + c3] = ub(cur)[c3 * L + l];
+                    op[3 * nd + c3] = ub(prv)[c3 * L + l];
+                }
             }
         }
     }

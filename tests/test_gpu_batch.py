@@ -209,3 +209,32 @@ def test_full_size_config3_sampled_against_oracle(S):
         say(f"  instance {i} ({mesh.ne}-node, model {mat.model}, {mesh.n_elems} el): rel error {err:.2e}")
         assert err <= 1e-4
     b.close()
+
+
+def test_batch_twice_config3_reads_work_lists_in_windows(S):
+    """A batch twice the size of config 3 (512 instances, ~28M elements) on
+    the 512-thread variant: about 160 chunks per workgroup, beyond the 128 the
+    LDS work list holds, so each workgroup reads its list in windows.  100
+    steps; every instance finite; the largest instance of each kind against
+    the oracle (<= 1e-4)."""
+    spec = W.config3(n_inst=512)  # loads ramped over 500 steps, as in config 3; 100 of them run
+    b = S.Batch(_instances(S, spec), variant=2)
+    inf = b.info()
+    per_wg = -(-inf["n_items"] // inf["grid_blocks"])
+    say(f"2x config3: {inf['n_inst']} instances, {inf['n_elems']} elements, {inf['n_items']} chunks, "
+        f"{per_wg} per workgroup")
+    assert per_wg > 128
+    st = b.run(100)
+    assert st.code == 0 and st.steps_done == 100, st
+    for i in range(len(spec)):
+        assert torch.isfinite(b.read(i)).all(), i
+    sizes = np.array([m.n_elems for m, _, _, _ in spec])
+    for ne_, model in ((4, W.NH), (4, W.TI), (8, W.NH), (8, W.TI)):
+        i = max([i for i, (m, mat, _, _) in enumerate(spec) if m.ne == ne_ and mat.model == model],
+                key=lambda i: sizes[i])
+        mesh, mat, ld, alpha = spec[i]
+        uo = _oracle_run(mesh, mat, ld, alpha, b.instance(int(i))["dt"], 100, omp=True)
+        err = np.abs(b.read(int(i)).double().cpu().numpy() - uo).max() / np.abs(uo).max()
+        say(f"  instance {i} ({mesh.n_elems} el): rel error {err:.2e}")
+        assert err <= 1e-4
+    b.close()

@@ -424,3 +424,32 @@ def test_full_size_config1_full_run_against_oracle(S, tag):
     assert err <= 1e-4
     assert abs(np.abs(ug).max() - umax) <= 1e-4 * umax
     assert abs(np.linalg.norm(ug) - unorm) <= 1e-4 * unorm
+
+
+def test_many_chunks_per_workgroup_read_in_windows(S):
+    """The 64^3 T4 cube cut into 16-element chunks (98,304 chunks, about 190
+    per workgroup, beyond the 128 the LDS list holds): the kernel reads each
+    workgroup's chunk list in windows; the full 1000-step run still matches
+    the FP64 oracle's stored state (as test_full_size_config1_full_run)."""
+    import importlib.util
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_cube64_reference", os.path.join(here, "make_cube64_reference.py"))
+    ref_mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(ref_mod)
+    ref = np.load(ref_mod.path_for("t4"))
+    wl = W.config1(W.T4)
+    assert str(ref["fingerprint"]) == ref_mod.fingerprint(wl)
+    sv = S.from_workload(wl, chunk_elems=16)
+    info = sv.info()
+    per_wg = -(-info["n_chunks"] // info["grid_blocks"])
+    say(f"windows: {info['n_chunks']} chunks on {info['grid_blocks']} workgroups ({per_wg} per workgroup)")
+    assert per_wg > 128
+    n = int(ref["steps"])
+    wl.loads.t_ramp = n * float(ref["dt"])
+    u, _ = _run_gpu(sv, wl, n)
+    ug = u.double().cpu().numpy()
+    sv.close()
+    err = np.abs(ug[ref["nodes"]] - ref["u"]).max() / float(ref["umax"])
+    say(f"  sampled rel max-norm error {err:.3e}")
+    assert err <= 1e-4

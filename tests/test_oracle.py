@@ -539,3 +539,18 @@ def test_all_cores_build_equals_serial_build_bitwise(elem, model):
         st.append((uc, up))
     assert np.array_equal(st[0][0], st[1][0]) and np.array_equal(st[0][1], st[1][1])
     assert np.abs(st[0][0]).max() > 0
+
+
+def test_relaxation_does_not_stop_before_any_reaction():
+    """The relaxation residual is relative to the reaction at the constrained
+    components: from rest with the load applied at once (no ramp) the
+    reaction is zero before the first update, and the run must not stop
+    there (0/0 is not convergence)."""
+    mesh, o, bn, bm, bt, E, nu, eta_r, a = _uniaxial_case(W.T4, W.NH)
+    u, up = np.zeros((mesh.n_nodes, 3)), np.zeros((mesh.n_nodes, 3))
+    dt = 0.9 * o.dt_crit
+    rc, done, res = o.run(u, up, 50, dt, 40.0, bc_node=bn, bc_mask=bm, bc_target=bt, ramp=W.RAMP_NONE,
+                          relax=True, tol=1e-3, check_every=1)
+    assert rc == 0 and done == 50
+    assert np.isfinite(res) and res > 1e-3
+    assert o.residual(np.zeros((mesh.n_nodes, 3)), bn, bm) == np.inf
