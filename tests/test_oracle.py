@@ -553,4 +553,5 @@ def test_relaxation_does_not_stop_before_any_reaction():
                           relax=True, tol=1e-3, check_every=1)
     assert rc == 0 and done == 50
     assert np.isfinite(res) and res > 1e-3
-    assert o.residual(np.zeros((mesh.n_nodes, 3)), bn, bm) == np.inf
+    # at rest the literal Table 3 forces are rounding noise (or exactly zero): never converged
+    assert not (o.residual(np.zeros((mesh.n_nodes, 3)), bn, bm) <= 1e-3)
