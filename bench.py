@@ -82,6 +82,19 @@ def _traffic(kernel: str, steps: int):
     return (t["fetch_bytes_per_step"] + t["write_bytes_per_step"]) * steps
 
 
+def _copy_calib(torch) -> int:
+    """Copies a 256 MiB buffer 4 times: a plain copy kernel of known size whose
+    rocprofv3 FETCH_SIZE / WRITE_SIZE readings calibrate the byte counters."""
+    x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(4):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    n = x.numel() * 4
+    del x, y
+    return n
+
+
 def host_info() -> dict:
     """Host CPU model and core counts (as lscpu / nproc would report them)."""
     model = None
@@ -480,6 +493,15 @@ def bench_mlp(log) -> dict:
     e1.record()
     torch.cuda.synchronize()
     adam_ms = e0.elapsed_time(e1) / reps
+    Y = torch.empty((B, net.ld_out), device="cuda")
+    net.forward(P, out=Y)
+    e0.record()
+    for _ in range(reps):
+        net.forward(P, out=Y)
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / reps
+    del Y
     P1 = P[:1].contiguous()
     net.forward(P1)
     e0.record()
@@ -489,7 +511,8 @@ def bench_mlp(log) -> dict:
     torch.cuda.synchronize()
     inf_ms = e0.elapsed_time(e1) / reps
     fwd = 2.0 * B * (16 * H + H * H + H * n_out)
-    out = {"n_out": n_out, "batch": B, "loss_grad_ms": lg_ms, "adam_ms": adam_ms, "inference_ms_batch1": inf_ms,
+    out = {"n_out": n_out, "batch": B, "loss_grad_ms": lg_ms, "adam_ms": adam_ms, "forward_ms": fwd_ms,
+           "inference_ms_batch1": inf_ms, "forward_GBps_W3": 2.0 * H * net.ld_out / (fwd_ms / 1e3) / 1e9,
            "train_products_TFLOPs": 3 * fwd / (lg_ms / 1e3) / 1e12,
            "inference_GBps_W3": 2.0 * H * net.ld_out / (inf_ms / 1e3) / 1e9}
     log(f"mlp: {out}")
@@ -547,6 +570,9 @@ def main():
                     help="also measure step time over cube sizes up to ~60M elements (real-time sizing)")
     ap.add_argument("--warm-full", action="store_true",
                     help="also run the warm-start pipeline on the full ellipsoid (several GPU-minutes)")
+    ap.add_argument("--only", choices=["cube64", "models", "multi", "anp", "realtime", "relaxation", "mlp",
+                                       "warm_start", "warm_start_full"],
+                    help="run this one measurement alone (no headline line; for profiling)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -564,6 +590,22 @@ def main():
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     K, Wm = args.steps, args.warmup
+    extras = (("cube64", args.no_cube, lambda lg: bench_cube64(lg, K, Wm, args.variant, args.mesh)),
+              ("models", args.no_models, bench_models),
+              ("multi", args.no_multi, bench_multi),
+              ("anp", args.no_anp, bench_anp),
+              ("realtime", not args.realtime, bench_realtime),
+              ("relaxation", args.no_relax, bench_relaxation),
+              ("mlp", args.no_mlp, bench_mlp), ("warm_start", args.no_warm, bench_warm_start),
+              ("warm_start_full", not args.warm_full, bench_warm_start_full))
+    if args.only:
+        r = dict((n, f) for n, _, f in extras)[args.only](log)
+        torch.cuda.synchronize()
+        out = {"only": args.only, args.only: r}
+        if args.copy_calib:
+            out["copy_calib_bytes"] = _copy_calib(torch)
+        print(json.dumps(out), flush=True)
+        return
     t0 = time.perf_counter()
     spec = W.config3()
     ins = [S.Instance(m.X, m.conn, mat.E, mat.nu, model=mat.model, rho=mat.rho, eta_ratio=mat.eta_ratio,
@@ -640,24 +682,11 @@ def main():
     del b
     torch.cuda.synchronize()
     if args.copy_calib:
-        x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")  # 256 MiB
-        y = torch.empty_like(x)
-        for _ in range(4):
-            y.copy_(x)
-        torch.cuda.synchronize()
-        out["copy_calib_bytes"] = x.numel() * 4
-        del x, y
+        out["copy_calib_bytes"] = _copy_calib(torch)
     out["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps) if args.cpu_steps > 0 else None
     del spec
     extra = {}
-    for name, skip, fn in (("cube64", args.no_cube, lambda lg: bench_cube64(lg, K, Wm, args.variant, args.mesh)),
-                           ("models", args.no_models, bench_models),
-                           ("multi", args.no_multi, bench_multi),
-                           ("anp", args.no_anp, bench_anp),
-                           ("realtime", not args.realtime, bench_realtime),
-                           ("relaxation", args.no_relax, bench_relaxation),
-                           ("mlp", args.no_mlp, bench_mlp), ("warm_start", args.no_warm, bench_warm_start),
-                           ("warm_start_full", not args.warm_full, bench_warm_start_full)):
+    for name, skip, fn in extras:
         if skip or (args.no_extra and name not in ("realtime", "warm_start_full")):
             continue
         try:

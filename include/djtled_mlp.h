@@ -38,7 +38,9 @@ typedef struct {
     int32_t n_in;             /* input width, 1..32 */
     int32_t n_hidden;         /* hidden width, multiple of 8 */
     int32_t n_out;            /* output width */
-    int32_t ld_out;           /* padded output width (>= n_out, multiple of 8): row length of W3^T rows, b3, Y, U */
+    int32_t ld_out;           /* padded output width (>= n_out, multiple of 8; a multiple of 64 keeps FP32
+                                 rows 256-byte aligned, which the output-layer kernels read whole lines of):
+                                 row length of W3^T rows, b3, Y, U */
     float *W1, *b1;           /* FP32 masters: W1 [n_in x n_hidden], b1 [n_hidden] */
     float *W2, *b2;           /* W2 [n_hidden x n_hidden], b2 [n_hidden] */
     float *W3, *b3;           /* W3 [ld_out x n_hidden] (one row per output), b3 [ld_out] */

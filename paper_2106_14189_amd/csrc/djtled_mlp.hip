@@ -8,8 +8,11 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <string>
+#include <type_traits>
 
 #include "../../include/djtled_mlp.h"
 
@@ -202,6 +205,501 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// The products with W3 (n_out x H, ~0.65 GB at full size) at batch B <= 256,
+// H <= 512, H % 16 == 0.  Persistent workgroups of 8 waves keep the whole
+// batch's H2 in registers as MFMA operands and stream the wide matrix once,
+// in panels of 32 rows (W3) or 32 columns (dY) staged through LDS:
+//   k_w3_fwd: wave w holds rows 32 w .. 32 w + 31 of H2 (all of K) as A
+//     operands; per W3 panel it forms its 32 x 32 block of H2 W3^T and runs
+//     the epilogue on it (bias; or loss, output gradient and its column sums
+//     db3);
+//   k_w3_dw: wave w holds columns 64 w .. 64 w + 63 of H2 (all B rows as K)
+//     as B operands; per 32-column panel of dY, staged transposed, it forms
+//     32 rows x 64 columns of dW3 = dY^T H2;
+//   k_w3_dh: partial sums of dH2 = dY W3 over runs of W3 rows (below).
+// dY is stored tiled by panel, [ceil(O / 32)][B][32]: a panel's 32 columns of
+// every row are one contiguous 16 KB block (B = 256), so each wave writes
+// whole 128-byte lines and the readers stream tiles in order.
+// Every byte of W3, U, dY and dW3 crosses HBM once; H2 is read once per
+// workgroup.  A panel is fetched into registers while the previous one is
+// multiplied, then stored to LDS between two barriers.  Operands past B or H
+// are zero, so every MFMA loop runs its full length.
+// ---------------------------------------------------------------------------
+constexpr int PNL = 32, KSMAX = 32, HMAX = 512, LDP = HMAX + 8, BMAX = 256, LDT = BMAX + 8;
+
+struct W3Args {
+    int B, H, N, O;             // batch, hidden width, columns written (<= O), rows of W3 = columns of U and dY
+    const uint16_t *H2;         // [B x H]
+    const uint16_t *W3;         // [O x H]
+    const float *bias;          // [O]
+    float *Y;                   // EPI_BIAS_F32: [B x O]
+    const float *U;             // EPI_LOSS: targets [B x O]
+    uint16_t *dY;               // EPI_LOSS: output gradient, tiled [ceil(O / 32)][B][32]
+    float *db3;                 // EPI_LOSS: column sums of dY [O]
+    int n_valid;                // EPI_LOSS: columns that carry a loss
+    float gscale;               // EPI_LOSS: output-gradient scale
+    double *loss_part;          // EPI_LOSS: one partial per workgroup
+};
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+template <int EPI>
+__global__ void __launch_bounds__(512) k_w3_fwd(W3Args g) {
+    constexpr int PPT = PNL * (HMAX / 8) / 512;  // 16-byte pieces of a panel per thread
+    __shared__ __align__(16) uint16_t Ws[PNL][LDP];
+    __shared__ float s_db[8][32];
+    __shared__ double s_loss[8];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int npc = g.H / 8, nact = min(8, (g.B + 31) / 32);
+    const bool active = wave < nact;
+    // columns past H stay zero: the panel stores below never reach them
+    for (int i = threadIdx.x; i < PNL * LDP / 8; i += 512)
+        reinterpret_cast<uint4 *>(&Ws[0][0])[i] = make_uint4(0, 0, 0, 0);
+    uint4 a[KSMAX];
+    {
+        const int row = wave * 32 + (lane & 31);
+#pragma unroll
+        for (int ks = 0; ks < KSMAX; ks++) {
+            const int k = 16 * ks + 8 * (lane >> 5);
+            a[ks] = make_uint4(0, 0, 0, 0);
+            if (k < g.H && row < g.B) a[ks] = *reinterpret_cast<const uint4 *>(g.H2 + int64_t(row) * g.H + k);
+        }
+    }
+    int pr[PPT], pc[PPT];  // panel row and 8-column group of each piece this thread moves
+#pragma unroll
+    for (int h = 0; h < PPT; h++) {
+        const int v = threadIdx.x + 512 * h;
+        pr[h] = v / npc;
+        pc[h] = (v - pr[h] * npc) * 8;
+    }
+    auto fetch = [&](int p, uint4 (&pf)[PPT]) {
+#pragma unroll
+        for (int h = 0; h < PPT; h++) {
+            const int n = p * PNL + pr[h];
+            pf[h] = make_uint4(0, 0, 0, 0);
+            if (pr[h] < PNL && n < g.O)
+                pf[h] = *reinterpret_cast<const uint4 *>(
+                    reinterpret_cast<const char *>(g.W3 + int64_t(p) * PNL * g.H) + 2u * uint32_t(pr[h] * g.H + pc[h]));
+        }
+    };
+    // db3 of the previous panel from the per-wave column sums
+    auto flush_db3 = [&](int pp) {
+        if (EPI == EPI_LOSS && pp >= 0 && threadIdx.x < 32 && pp * PNL + int(threadIdx.x) < g.O) {
+            float t = 0.0f;
+            for (int w = 0; w < nact; w++) t += s_db[w][threadIdx.x];
+            g.db3[pp * PNL + threadIdx.x] = t;
+        }
+    };
+    // element (m, n) of U, dY and Y (all [B x O]) sits at the uniform offset (8 (r / 4) + r % 4) O
+    // + 32 p plus the lane's own, (32 wave + 4 (lane / 32)) O + lane % 32, for m = 32 wave + 4 (lane /
+    // 32) + 8 (r / 4) + r % 4 and n = 32 p + lane % 32; the lane's part is kept as a 32-bit byte offset
+    const uint32_t L = uint32_t(wave * 32 + 4 * (lane >> 5)) * uint32_t(g.O) + uint32_t(lane & 31);
+    const uint32_t L4 = 4u * L;
+    // dY is tiled by panel: [O / 32][B][32], so the lane's byte offset within a tile is
+    const uint32_t LT = 2u * uint32_t((wave * 32 + 4 * (lane >> 5)) * PNL + (lane & 31));
+    // byte offset of row 8 (r / 4) + r % 4 (uniform, 32 bits)
+    auto roff = [&](int r, uint32_t esz) { return esz * uint32_t(8 * (r >> 2) + (r & 3)) * uint32_t(g.O); };
+    // the compiler would otherwise keep one offset per row live across the panel loop
+    auto opaque = [](uint32_t x) {
+        asm volatile("" : "+v"(x));
+        return x;
+    };
+    auto fetch_u = [&](int p, float (&u)[16]) {
+        const int n = p * PNL + (lane & 31);
+        const uint32_t l4 = opaque(L4);
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const int m = wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            u[r] = (m < g.B && n < g.n_valid)
+                       ? *reinterpret_cast<const float *>(reinterpret_cast<const char *>(g.U + int64_t(p) * PNL) +
+                                                          (l4 + roff(r, 4u)))
+                       : 0.0f;
+        }
+    };
+    double lsum = 0.0;
+    int prev = -1;
+    // one panel of W3 per iteration: stored to LDS from registers loaded two iterations earlier
+    // (W3) or one (U), then refilled; the two register sets alternate between iterations
+    auto panel = [&](int p, int p_end, uint4 (&pf)[PPT], float (&u_cur)[16], float (&u_nxt)[16]) {
+        __syncthreads();  // the previous panel and its column sums have been written and read
+        flush_db3(prev);
+        prev = p;
+#pragma unroll
+        for (int h = 0; h < PPT; h++)
+            if (pr[h] < PNL) *reinterpret_cast<uint4 *>(&Ws[pr[h]][pc[h]]) = pf[h];
+        __syncthreads();
+        if (p + 2 < p_end) fetch(p + 2, pf);
+        if (!active) return;
+        if (EPI == EPI_LOSS && p + 1 < p_end) fetch_u(p + 1, u_nxt);
+        const int n = p * PNL + (lane & 31);
+        const float bn = n < g.N ? g.bias[n] : 0.0f;
+        f32x16 acc;
+#pragma unroll
+        for (int r = 0; r < 16; r++) acc[r] = 0.0f;
+#pragma unroll
+        for (int ks = 0; ks < KSMAX; ks++) {
+            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Ws[lane & 31][16 * ks + 8 * (lane >> 5)]);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a[ks]), b, acc, 0, 0, 0);
+        }
+        // acc[r]: row 32 wave + 8 (r / 4) + 4 (lane / 32) + r % 4, column n
+        const uint32_t l4 = opaque(L4), lt = opaque(LT);
+        float csum = 0.0f;
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const int m = wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            if (m >= g.B || n >= g.N) continue;
+            if constexpr (EPI == EPI_BIAS_F32) {
+                *reinterpret_cast<float *>(reinterpret_cast<char *>(g.Y + int64_t(p) * PNL) + (l4 + roff(r, 4u))) =
+                    acc[r] + bn;
+            } else {
+                const float d = n < g.n_valid ? acc[r] + bn - u_cur[r] : 0.0f;
+                const uint16_t q = f2bf(d * g.gscale);
+                *reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(g.dY + int64_t(p) * PNL * g.B) +
+                                              (lt + 64u * uint32_t(8 * (r >> 2) + (r & 3)))) = q;
+                csum += bf2f(q);
+                lsum += double(d) * double(d);
+            }
+        }
+        if constexpr (EPI == EPI_LOSS) {
+            csum += __shfl_xor(csum, 32, 64);
+            if (lane < 32) s_db[wave][lane] = csum;
+        }
+    };
+    // each workgroup takes a contiguous run of panels, so the two halves of a 128-byte line of dY
+    // (and a line of U that straddles panels) meet in its L2
+    const int npan = (g.O + PNL - 1) / PNL, per = (npan + gridDim.x - 1) / gridDim.x;
+    const int p_beg = min(npan, int(blockIdx.x) * per), p_end = min(npan, p_beg + per);
+    uint4 pfA[PPT], pfB[PPT];
+    float uA[16], uB[16];
+    if (p_beg < p_end) {
+        fetch(p_beg, pfA);
+        if (p_beg + 1 < p_end) fetch(p_beg + 1, pfB);
+        if (EPI == EPI_LOSS && active) fetch_u(p_beg, uA);
+    }
+    for (int p = p_beg; p < p_end; p += 2) {
+        panel(p, p_end, pfA, uA, uB);
+        if (p + 1 < p_end) panel(p + 1, p_end, pfB, uB, uA);
+    }
+    __syncthreads();
+    flush_db3(prev);
+    if constexpr (EPI == EPI_LOSS) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
+        if (lane == 0) s_loss[wave] = lsum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < 8; w++) t += s_loss[w];
+            g.loss_part[blockIdx.x] = t;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(512) k_w3_dw(int B, int H, int O, const uint16_t *__restrict__ H2,
+                                               const uint16_t *__restrict__ dY, float *__restrict__ dW3) {
+    constexpr int KS = BMAX / 16;
+    __shared__ __align__(16) uint16_t Ts[PNL][LDT];  // the dY panel transposed: [column][batch row]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // b[ks][j]: H2 rows 16 ks + 8 (lane / 32) + 0..7 at column 64 wave + 32 j + lane % 32
+    uint4 b[KS][2];
+#pragma unroll
+    for (int ks = 0; ks < KS; ks++) {
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            const int h = 64 * wave + 32 * j + (lane & 31), m0 = 16 * ks + 8 * (lane >> 5);
+            const int hc = min(h, H - 1);
+            uint32_t e[4];
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int ma = m0 + 2 * i, mb = ma + 1;
+                const uint32_t lo = H2[int64_t(min(ma, B - 1)) * H + hc], hi = H2[int64_t(min(mb, B - 1)) * H + hc];
+                e[i] = (ma < B && h < H ? lo : 0u) | (mb < B && h < H ? hi << 16 : 0u);
+            }
+            b[ks][j] = make_uint4(e[0], e[1], e[2], e[3]);
+        }
+        __builtin_amdgcn_sched_barrier(0);  // bounds the 16-bit loads in flight
+    }
+    // each thread moves rows 2 mp, 2 mp + 1 of one 8-column group of the panel
+    const int cg = (threadIdx.x & 3) * 8, mp = threadIdx.x >> 2;
+    auto fetch = [&](int p, uint4 &r0, uint4 &r1) {
+        const int n = p * PNL + cg;
+        r0 = make_uint4(0, 0, 0, 0);
+        r1 = make_uint4(0, 0, 0, 0);
+        const uint16_t *tile = dY + int64_t(p) * PNL * B + 2 * mp * PNL + cg;
+        if (n < O && 2 * mp < B) r0 = *reinterpret_cast<const uint4 *>(tile);
+        if (n < O && 2 * mp + 1 < B) r1 = *reinterpret_cast<const uint4 *>(tile + PNL);
+    };
+    // one panel per iteration, stored to LDS from registers loaded two iterations earlier
+    auto panel = [&](int p, int p_end, uint4 &r0, uint4 &r1) {
+        __syncthreads();
+        {
+            const uint32_t x0[4] = {r0.x, r0.y, r0.z, r0.w}, x1[4] = {r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                *reinterpret_cast<uint32_t *>(&Ts[cg + 2 * i][2 * mp]) = (x0[i] & 0xffffu) | (x1[i] << 16);
+                *reinterpret_cast<uint32_t *>(&Ts[cg + 2 * i + 1][2 * mp]) = (x0[i] >> 16) | (x1[i] & 0xffff0000u);
+            }
+        }
+        __syncthreads();
+        if (p + 2 < p_end) fetch(p + 2, r0, r1);
+        if (64 * wave >= H) return;
+        const int n0 = p * PNL;
+        f32x16 acc[2];
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int r = 0; r < 16; r++) acc[j][r] = 0.0f;
+#pragma unroll
+        for (int ks = 0; ks < KS; ks++) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&Ts[lane & 31][16 * ks + 8 * (lane >> 5)]);
+#pragma unroll
+            for (int j = 0; j < 2; j++)
+                acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, as_bf16x8(b[ks][j]), acc[j], 0, 0, 0);
+        }
+        // acc[j][r]: dW3 row n0 + 8 (r / 4) + 4 (lane / 32) + r % 4, column 64 wave + 32 j + lane % 32
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            const int h = 64 * wave + 32 * j + (lane & 31);
+            const uint32_t lo = 4u * uint32_t(4 * (lane >> 5) * H + h);
+            char *base = reinterpret_cast<char *>(dW3 + int64_t(n0) * H);
+#pragma unroll
+            for (int r = 0; r < 16; r++) {
+                const int n = n0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                if (n < O && h < H)
+                    *reinterpret_cast<float *>(base + (lo + 4u * uint32_t((8 * (r >> 2) + (r & 3)) * H))) = acc[j][r];
+            }
+        }
+    };
+    // contiguous runs of panels: consecutive dY tiles
+    const int npan = (O + PNL - 1) / PNL, per = (npan + gridDim.x - 1) / gridDim.x;
+    const int p_beg = min(npan, int(blockIdx.x) * per), p_end = min(npan, p_beg + per);
+    uint4 a0, a1, b0, b1;
+    if (p_beg < p_end) fetch(p_beg, a0, a1);
+    if (p_beg + 1 < p_end) fetch(p_beg + 1, b0, b1);
+    for (int p = p_beg; p < p_end; p += 2) {
+        panel(p, p_end, a0, a1);
+        if (p + 1 < p_end) panel(p + 1, p_end, b0, b1);
+    }
+}
+
+// dH2 partial sums over runs of W3 rows: part[z][m][h] = sum over the n of run z of dY[m][n] W3[n][h].
+// Workgroup b takes run z and the 128-column slice sl of H; the slices of one run share b % 8 (one
+// XCD), so the dY tiles they all read meet in its L2.  Wave w owns rows 32 w .. 32 w + 31 and the
+// slice's four 32-column blocks.  dY operands come straight from the tiles (8 consecutive n of a row
+// are 16 contiguous bytes); 64 rows of W3 at a time are staged transposed ([h][n]) in LDS.
+constexpr int DHN = 64, DHS = 128, LDH = DHN + 8;
+
+__global__ void __launch_bounds__(512) k_w3_dh(int B, int H, int O, int nsplit, const uint16_t *__restrict__ dY,
+                                               const uint16_t *__restrict__ W3, float *__restrict__ part) {
+    __shared__ __align__(16) uint16_t Wt[DHS][LDH];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nhs = (H + DHS - 1) / DHS, b = blockIdx.x;
+    const int z = nsplit % 8 == 0 ? (b / (8 * nhs)) * 8 + b % 8 : b / nhs;
+    const int sl = nsplit % 8 == 0 ? (b / 8) % nhs : b % nhs;
+    const int h0 = sl * DHS;
+    const int nch = (O + DHN - 1) / DHN, per = (nch + nsplit - 1) / nsplit;
+    const int c_beg = min(nch, z * per), c_end = min(nch, c_beg + per);
+    const bool active = 32 * wave < B;
+    const int m = 32 * wave + (lane & 31);
+    // W3 staging: rows 2 q, 2 q + 1 of the chunk, 8 columns from hq
+    const int q = threadIdx.x >> 4, hq = (threadIdx.x & 15) * 8;
+    auto fetch_w = [&](int c, uint4 &w0, uint4 &w1) {
+        const int n = c * DHN + 2 * q, h = h0 + hq;
+        w0 = make_uint4(0, 0, 0, 0);
+        w1 = make_uint4(0, 0, 0, 0);
+        if (h < H && n < O) w0 = *reinterpret_cast<const uint4 *>(W3 + int64_t(n) * H + h);
+        if (h < H && n + 1 < O) w1 = *reinterpret_cast<const uint4 *>(W3 + int64_t(n + 1) * H + h);
+    };
+    // dY operands of chunk c: k-step ks covers n = 64 c + 16 ks + 8 (lane / 32) + 0..7
+    auto fetch_a = [&](int c, uint4 (&a)[4]) {
+#pragma unroll
+        for (int ks = 0; ks < 4; ks++) {
+            const int p = 2 * c + (ks >> 1), k = 16 * (ks & 1) + 8 * (lane >> 5);
+            a[ks] = make_uint4(0, 0, 0, 0);
+            if (active && m < B && p * PNL + k < O)
+                a[ks] = *reinterpret_cast<const uint4 *>(dY + (int64_t(p) * B + m) * PNL + k);
+        }
+    };
+    f32x16 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+#pragma unroll
+        for (int r = 0; r < 16; r++) acc[j][r] = 0.0f;
+    auto chunk = [&](int c, uint4 &w0, uint4 &w1, uint4 (&a)[4]) {
+        __syncthreads();
+        {
+            const uint32_t x0[4] = {w0.x, w0.y, w0.z, w0.w}, x1[4] = {w1.x, w1.y, w1.z, w1.w};
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                *reinterpret_cast<uint32_t *>(&Wt[hq + 2 * i][2 * q]) = (x0[i] & 0xffffu) | (x1[i] << 16);
+                *reinterpret_cast<uint32_t *>(&Wt[hq + 2 * i + 1][2 * q]) = (x0[i] >> 16) | (x1[i] & 0xffff0000u);
+            }
+        }
+        __syncthreads();
+        uint4 ac[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ks++) ac[ks] = a[ks];
+        if (c + 2 < c_end) {
+            fetch_w(c + 2, w0, w1);
+            fetch_a(c + 2, a);
+        }
+        if (!active) return;
+#pragma unroll
+        for (int ks = 0; ks < 4; ks++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(&Wt[32 * j + (lane & 31)][16 * ks + 8 * (lane >> 5)]);
+                acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ac[ks]), bw, acc[j], 0, 0, 0);
+            }
+    };
+    uint4 wA0, wA1, wB0, wB1, aA[4], aB[4];
+    if (c_beg < c_end) {
+        fetch_w(c_beg, wA0, wA1);
+        fetch_a(c_beg, aA);
+    }
+    if (c_beg + 1 < c_end) {
+        fetch_w(c_beg + 1, wB0, wB1);
+        fetch_a(c_beg + 1, aB);
+    }
+    for (int c = c_beg; c < c_end; c += 2) {
+        chunk(c, wA0, wA1, aA);
+        if (c + 1 < c_end) chunk(c + 1, wB0, wB1, aB);
+    }
+    if (!active) return;
+    // acc[j][r]: row 32 wave + 8 (r / 4) + 4 (lane / 32) + r % 4, column h0 + 32 j + lane % 32
+    float *out = part + int64_t(z) * B * H;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        const int h = h0 + 32 * j + (lane & 31);
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const int mr = 32 * wave + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            if (mr < B && h < H) out[int64_t(mr) * H + h] = acc[j][r];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The hidden layers at batch MM <= 2: Y[m, n] = bf16(relu(sum_k x[m, k] W[k, n]
+// + bias[n])) with W [K x N] (N contiguous) and x BF16 (or FP32 rounded to
+// BF16 on load).  256 threads per 64 columns: 8 groups of 8 columns (one
+// 16-byte piece of a W row) x 32 slices of K, summed through LDS in a fixed
+// order.
+// ---------------------------------------------------------------------------
+template <int MM, bool XF32>
+__global__ void __launch_bounds__(256) k_gemv_kn(const void *__restrict__ X, int64_t ldx, int K,
+                                                 const uint16_t *__restrict__ W, int N, const float *__restrict__ bias,
+                                                 uint16_t *__restrict__ Y, int64_t ldy) {
+    __shared__ float red[32][MM][65];
+    const int c8 = threadIdx.x & 7, sl = threadIdx.x >> 3;
+    const int n = blockIdx.x * 64 + c8 * 8;
+    float acc[MM][8];
+#pragma unroll
+    for (int m = 0; m < MM; m++)
+#pragma unroll
+        for (int i = 0; i < 8; i++) acc[m][i] = 0.0f;
+    if (n < N) {
+        for (int k = sl; k < K; k += 32) {
+            const uint4 w = *reinterpret_cast<const uint4 *>(W + int64_t(k) * N + n);
+            const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+            float x[MM];
+#pragma unroll
+            for (int m = 0; m < MM; m++)
+                x[m] = XF32 ? bf2f(f2bf(static_cast<const float *>(X)[int64_t(m) * ldx + k]))
+                            : bf2f(static_cast<const uint16_t *>(X)[int64_t(m) * ldx + k]);
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const float lo = __uint_as_float(ww[i] << 16), hi = __uint_as_float(ww[i] & 0xffff0000u);
+#pragma unroll
+                for (int m = 0; m < MM; m++) {
+                    acc[m][2 * i] += x[m] * lo;
+                    acc[m][2 * i + 1] += x[m] * hi;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < MM; m++)
+#pragma unroll
+        for (int i = 0; i < 8; i++) red[sl][m][c8 * 8 + i] = acc[m][i];
+    __syncthreads();
+    if (threadIdx.x < 64 * MM) {
+        const int m = threadIdx.x >> 6, c = threadIdx.x & 63, nn = blockIdx.x * 64 + c;
+        float s = 0.0f;
+        for (int q = 0; q < 32; q++) s += red[q][m][c];
+        if (nn < N) Y[int64_t(m) * ldy + nn] = f2bf(fmaxf(s + bias[nn], 0.0f));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Y[m, n] = sum_k X[m, k] W[n, k] + bias[n] for MM <= 2 rows (inference of the
+// output layer): a streaming product over W (n_out x K, K contiguous).  Each
+// wave takes 64 rows of W; per row every lane loads 16-byte pieces (a 1 KB row
+// is one wave-wide load when K = 512) and keeps a partial dot per row; a
+// butterfly of shuffles then halves the rows held per lane five times over,
+// leaving lane l with the fixed-order sum of row l.
+// ---------------------------------------------------------------------------
+template <int MM, int T>
+__global__ void __launch_bounds__(256) k_gemv(const uint16_t *__restrict__ X, int64_t ldx, int K,
+                                              const uint16_t *__restrict__ W, int64_t ldw, int N,
+                                              const float *__restrict__ bias, float *__restrict__ Y, int64_t ldy) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r0 = (blockIdx.x * 4 + wave) * 64;
+    if (r0 >= N) return;
+    const int nc = K / 8;  // 16-byte pieces per row
+    float x[MM][T][8];
+#pragma unroll
+    for (int m = 0; m < MM; m++)
+#pragma unroll
+        for (int t = 0; t < T; t++) {
+            const int c = lane + 64 * t;
+#pragma unroll
+            for (int i = 0; i < 8; i++) x[m][t][i] = c < nc ? bf2f(X[int64_t(m) * ldx + c * 8 + i]) : 0.0f;
+        }
+    float p[MM][64];
+#pragma unroll
+    for (int j = 0; j < 64; j++) {
+        const int row = min(r0 + j, N - 1);  // rows past the end are computed and dropped
+#pragma unroll
+        for (int m = 0; m < MM; m++) p[m][j] = 0.0f;
+#pragma unroll
+        for (int t = 0; t < T; t++) {
+            const int c = lane + 64 * t;
+            if (c < nc) {
+                const uint4 w = *reinterpret_cast<const uint4 *>(W + int64_t(row) * ldw + c * 8);
+                const uint32_t ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const float lo = __uint_as_float(ww[i] << 16), hi = __uint_as_float(ww[i] & 0xffff0000u);
+#pragma unroll
+                    for (int m = 0; m < MM; m++) p[m][j] += lo * x[m][t][2 * i] + hi * x[m][t][2 * i + 1];
+                }
+            }
+        }
+    }
+    // butterfly: after the step of offset o each lane keeps half of its rows
+#pragma unroll
+    for (int o = 32, h = 32; o > 0; o >>= 1, h >>= 1) {
+        const bool up = (lane & o) != 0;
+#pragma unroll
+        for (int j = 0; j < 32; j++) {
+            if (j < h) {
+#pragma unroll
+                for (int m = 0; m < MM; m++) {
+                    const float send = up ? p[m][j] : p[m][j + h];
+                    const float keep = up ? p[m][j + h] : p[m][j];
+                    p[m][j] = keep + __shfl_xor(send, o, 64);
+                }
+            }
+        }
+    }
+    const int n = r0 + lane;
+    if (n < N)
+#pragma unroll
+        for (int m = 0; m < MM; m++) Y[int64_t(m) * ldy + n] = p[m][0] + bias[n];
+}
+
 // split-K reduction with the ReLU mask: out = bf16(sum_z part[z]) where act > 0
 __global__ void k_splitk_mask(const float *__restrict__ part, int splits, int64_t mn, const uint16_t *__restrict__ act,
                               uint16_t *__restrict__ out) {
@@ -283,6 +781,30 @@ hipError_t gemm(GemmArgs a, int splits, hipStream_t s) {
     return hipGetLastError();
 }
 
+// the streaming W3 kernels: batch and width they hold in registers; a lane's byte offset into a
+// [B x O] FP32 matrix fits 32 bits
+bool w3_stream(int B, int H, int64_t O) {
+    return B <= BMAX && H <= HMAX && H % 16 == 0 && int64_t(BMAX) * O * 4 < (int64_t(1) << 32);
+}
+constexpr int MAX_PERSIST = 4096;  // loss partials the workspace holds
+
+// persistent grid: the resident workgroups of the device, at most `work`
+template <typename Kern>
+int persistent_grid(Kern kern, int slot, int work) {
+    static std::atomic<int> cache[3][64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    int n = cache[slot][dev].load(std::memory_order_relaxed);
+    if (n <= 0) {
+        int cus = 0, occ = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 512, 0) != hipSuccess || occ <= 0) occ = 1;
+        n = std::min(cus * occ, MAX_PERSIST);
+        cache[slot][dev].store(n, std::memory_order_relaxed);
+    }
+    return std::max(1, std::min(n, work));
+}
+
 GemmArgs ga(int M, int N, int K, const uint16_t *A, int64_t lda, const uint16_t *B, int64_t ldb) {
     GemmArgs g{};
     g.M = M;
@@ -317,8 +839,9 @@ int carve(const djtled_mlp *m, int B, void *base, size_t bytes, WS &w, size_t *n
         return o;
     };
     const size_t oPb = take(size_t(B) * 32 * 2), oH1 = take(size_t(B) * H * 2), oH2 = take(size_t(B) * H * 2);
-    const size_t odY = take(size_t(B) * O * 2), odZ2 = take(size_t(B) * H * 2), odZ1 = take(size_t(B) * H * 2);
-    const size_t opart = take(size_t(splits) * B * H * 4), olp = take(size_t(tiles) * 8), ol = take(8);
+    const size_t odY = take(size_t(B) * rup(O, 32) * 2), odZ2 = take(size_t(B) * H * 2), odZ1 = take(size_t(B) * H * 2);
+    const size_t opart = take(size_t(splits) * B * H * 4);
+    const size_t olp = take(size_t(std::max<int64_t>(tiles, MAX_PERSIST)) * 8), ol = take(8);
     if (need) *need = off;
     if (!base) return DJ_MLP_OK;
     if (bytes < off) return mfail(DJ_MLP_ERR_ARG, "workspace too small");
@@ -389,9 +912,59 @@ int djtled_mlp_forward(const djtled_mlp *m, int32_t batch, const float *P, float
     WS w;
     if ((rc = carve(m, batch, ws, ws_bytes, w, nullptr)) != DJ_MLP_OK) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const int H = m->n_hidden;
+    if (batch <= 2 && H <= 2048) {
+        // inference: streaming products, one launch per layer
+        const dim3 gh(unsigned((H + 63) / 64));
+        if (batch == 1) {
+            hipLaunchKernelGGL((k_gemv_kn<1, true>), gh, dim3(256), 0, s, P, int64_t(m->n_in), m->n_in, m->W1_bf16, H,
+                               m->b1, w.H1, int64_t(H));
+            hipLaunchKernelGGL((k_gemv_kn<1, false>), gh, dim3(256), 0, s, w.H1, int64_t(H), H, m->W2_bf16, H, m->b2,
+                               w.H2, int64_t(H));
+        } else {
+            hipLaunchKernelGGL((k_gemv_kn<2, true>), gh, dim3(256), 0, s, P, int64_t(m->n_in), m->n_in, m->W1_bf16, H,
+                               m->b1, w.H1, int64_t(H));
+            hipLaunchKernelGGL((k_gemv_kn<2, false>), gh, dim3(256), 0, s, w.H1, int64_t(H), H, m->W2_bf16, H, m->b2,
+                               w.H2, int64_t(H));
+        }
+        MLP_HIP(hipGetLastError());
+        // Y = H2 W3^T + b3: W3 is [ld_out x H] (K contiguous)
+        const dim3 grid(unsigned((m->n_out + 255) / 256));
+        const int T = (H / 8 + 63) / 64;
+        auto run = [&](auto mm, auto tt) {
+            hipLaunchKernelGGL((k_gemv<decltype(mm)::value, decltype(tt)::value>), grid, dim3(256), 0, s, w.H2,
+                               int64_t(H), H, m->W3_bf16, int64_t(H), m->n_out, m->b3, Y, int64_t(m->ld_out));
+        };
+        using I1 = std::integral_constant<int, 1>;
+        using I2 = std::integral_constant<int, 2>;
+        using I3 = std::integral_constant<int, 3>;
+        using I4 = std::integral_constant<int, 4>;
+        if (batch == 1) {
+            if (T == 1) run(I1(), I1()); else if (T == 2) run(I1(), I2()); else if (T == 3) run(I1(), I3()); else run(I1(), I4());
+        } else {
+            if (T == 1) run(I2(), I1()); else if (T == 2) run(I2(), I2()); else if (T == 3) run(I2(), I3()); else run(I2(), I4());
+        }
+        MLP_HIP(hipGetLastError());
+        return DJ_MLP_OK;
+    }
     MLP_HIP(hidden_forward(m, batch, P, w, s));
+    if (w3_stream(batch, H, m->ld_out)) {
+        W3Args a{};
+        a.B = batch;
+        a.H = H;
+        a.N = m->n_out;
+        a.O = m->ld_out;
+        a.H2 = w.H2;
+        a.W3 = m->W3_bf16;
+        a.bias = m->b3;
+        a.Y = Y;
+        const int grid = persistent_grid(k_w3_fwd<EPI_BIAS_F32>, 0, (a.O + PNL - 1) / PNL);
+        hipLaunchKernelGGL(k_w3_fwd<EPI_BIAS_F32>, dim3(grid), dim3(512), 0, s, a);
+        MLP_HIP(hipGetLastError());
+        return DJ_MLP_OK;
+    }
     // Y = H2 W3^T + b3: W3 is [ld_out x H] (K contiguous)
-    GemmArgs g = ga(batch, m->n_out, m->n_hidden, w.H2, m->n_hidden, m->W3_bf16, m->n_hidden);
+    GemmArgs g = ga(batch, m->n_out, H, w.H2, H, m->W3_bf16, H);
     g.C = Y;
     g.ldc = m->ld_out;
     g.bias = m->b3;
@@ -411,36 +984,75 @@ int djtled_mlp_loss_grad(const djtled_mlp *m, int32_t batch, const float *P, con
     const int B = batch, H = m->n_hidden, O = m->ld_out, NI = m->n_in;
     MLP_HIP(hidden_forward(m, B, P, w, s));
     // loss = mean over (batch, n_out) of (Y - U)^2; dY = 2 (Y - U) / (B n_out)
-    GemmArgs g = ga(B, O, H, w.H2, H, m->W3_bf16, H);
-    g.Cb = w.dY;
-    g.ldc = O;
-    g.bias = m->b3;
-    g.U = U;
-    g.n_valid = m->n_out;
-    g.gscale = float(2.0 / (double(B) * m->n_out));
-    g.loss_part = w.loss_part;
-    MLP_HIP((gemm<true, true, EPI_LOSS>(g, 1, s)));
-    const int tiles = ((O + BN - 1) / BN) * ((B + BM - 1) / BM);
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, w.loss_part, tiles, 1.0 / (double(B) * m->n_out), w.loss);
-    MLP_HIP(hipGetLastError());
-    // dW3 [O x H] = dY^T H2  (A = dY: M contiguous; B = H2: N contiguous)
-    g = ga(O, H, B, w.dY, O, w.H2, H);
-    g.C = gr->W3;
-    g.ldc = H;
-    MLP_HIP((gemm<false, false, EPI_F32>(g, 1, s)));
-    hipLaunchKernelGGL(k_colsum, dim3((O + 255) / 256), dim3(256), 0, s, w.dY, B, O, int64_t(O), gr->b3);
-    MLP_HIP(hipGetLastError());
-    // dH2 [B x H] = dY W3 (B operand W3 [O x H]: N contiguous), split over K = O; then the ReLU mask of H2
-    g = ga(B, H, O, w.dY, O, m->W3_bf16, H);
-    g.k_per_split = int(rup((O + w.splits - 1) / w.splits, BKT));
-    const int splits = (O + g.k_per_split - 1) / g.k_per_split;
-    g.C = w.part;
-    g.ldc = H;
-    MLP_HIP((gemm<true, false, EPI_SPLITK>(g, splits, s)));
-    const int64_t bh = int64_t(B) * H;
-    hipLaunchKernelGGL(k_splitk_mask, dim3(unsigned((bh + 255) / 256)), dim3(256), 0, s, w.part, splits, bh, w.H2,
-                       w.dZ2);
-    MLP_HIP(hipGetLastError());
+    const float gscale = float(2.0 / (double(B) * m->n_out));
+    GemmArgs g;
+    if (w3_stream(B, H, O)) {
+        W3Args a{};
+        a.B = B;
+        a.H = H;
+        a.N = O;
+        a.O = O;
+        a.H2 = w.H2;
+        a.W3 = m->W3_bf16;
+        a.bias = m->b3;
+        a.U = U;
+        a.dY = w.dY;
+        a.n_valid = m->n_out;
+        a.gscale = gscale;
+        a.loss_part = w.loss_part;
+        a.db3 = gr->b3;
+        const int grid = persistent_grid(k_w3_fwd<EPI_LOSS>, 1, (O + PNL - 1) / PNL);
+        hipLaunchKernelGGL(k_w3_fwd<EPI_LOSS>, dim3(grid), dim3(512), 0, s, a);
+        MLP_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, w.loss_part, grid, 1.0 / (double(B) * m->n_out),
+                           w.loss);
+        MLP_HIP(hipGetLastError());
+        // dW3 [O x H] = dY^T H2 (db3 came with dY)
+        const int gd = persistent_grid(k_w3_dw, 2, (O + PNL - 1) / PNL);
+        hipLaunchKernelGGL(k_w3_dw, dim3(gd), dim3(512), 0, s, B, H, O, w.H2, w.dY, gr->W3);
+        MLP_HIP(hipGetLastError());
+        // dH2 [B x H] = dY W3 as partial sums over runs of W3 rows; then their sum under the ReLU mask of H2
+        const int nsplit = int(std::min<int64_t>(w.splits, (O + DHN - 1) / DHN));
+        hipLaunchKernelGGL(k_w3_dh, dim3(unsigned(nsplit * ((H + DHS - 1) / DHS))), dim3(512), 0, s, B, H, O, nsplit,
+                           w.dY, m->W3_bf16, w.part);
+        MLP_HIP(hipGetLastError());
+        const int64_t bh = int64_t(B) * H;
+        hipLaunchKernelGGL(k_splitk_mask, dim3(unsigned((bh + 255) / 256)), dim3(256), 0, s, w.part, nsplit, bh, w.H2,
+                           w.dZ2);
+        MLP_HIP(hipGetLastError());
+    } else {
+        g = ga(B, O, H, w.H2, H, m->W3_bf16, H);
+        g.Cb = w.dY;
+        g.ldc = O;
+        g.bias = m->b3;
+        g.U = U;
+        g.n_valid = m->n_out;
+        g.gscale = gscale;
+        g.loss_part = w.loss_part;
+        MLP_HIP((gemm<true, true, EPI_LOSS>(g, 1, s)));
+        const int tiles = ((O + BN - 1) / BN) * ((B + BM - 1) / BM);
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, w.loss_part, tiles, 1.0 / (double(B) * m->n_out),
+                           w.loss);
+        MLP_HIP(hipGetLastError());
+        // dW3 [O x H] = dY^T H2  (A = dY: M contiguous; B = H2: N contiguous)
+        g = ga(O, H, B, w.dY, O, w.H2, H);
+        g.C = gr->W3;
+        g.ldc = H;
+        MLP_HIP((gemm<false, false, EPI_F32>(g, 1, s)));
+        hipLaunchKernelGGL(k_colsum, dim3((O + 255) / 256), dim3(256), 0, s, w.dY, B, O, int64_t(O), gr->b3);
+        MLP_HIP(hipGetLastError());
+        // dH2 [B x H] = dY W3 (B operand W3 [O x H]: N contiguous), split over K = O; then the ReLU mask of H2
+        g = ga(B, H, O, w.dY, O, m->W3_bf16, H);
+        g.k_per_split = int(rup((O + w.splits - 1) / w.splits, BKT));
+        const int splits = (O + g.k_per_split - 1) / g.k_per_split;
+        g.C = w.part;
+        g.ldc = H;
+        MLP_HIP((gemm<true, false, EPI_SPLITK>(g, splits, s)));
+        const int64_t bh = int64_t(B) * H;
+        hipLaunchKernelGGL(k_splitk_mask, dim3(unsigned((bh + 255) / 256)), dim3(256), 0, s, w.part, splits, bh, w.H2,
+                           w.dZ2);
+        MLP_HIP(hipGetLastError());
+    }
     // dW2 [H x H] = H1^T dZ2 ; db2
     g = ga(H, H, B, w.H1, H, w.dZ2, H);
     g.C = gr->W2;

@@ -31,7 +31,8 @@ class SurrogateMLP:
     def __init__(self, n_in: int, n_hidden: int, n_out: int, device=0, seed: int = 0):
         torch.cuda.init()
         self.n_in, self.n_hidden, self.n_out = int(n_in), int(n_hidden), int(n_out)
-        self.ld_out = (self.n_out + 7) // 8 * 8
+        # rows of Y, U and the output gradient start on 256-byte boundaries
+        self.ld_out = (self.n_out + 63) // 64 * 64
         self.device = torch.device("cuda", device)
         g = torch.Generator().manual_seed(seed)
         H, O = self.n_hidden, self.ld_out

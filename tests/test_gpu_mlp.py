@@ -1,8 +1,11 @@
 """The surrogate MLP's BF16 MFMA kernels against the float64 oracle.
 
-* GEMM (all four operand layouts, ragged sizes, split K): exact BF16 inputs,
+* GEMM (all four operand layouts, ragged sizes, split K, the one-row-tile
+  shape of the output layer): exact BF16 inputs,
   so the only difference is FP32 summation: |C_gpu - C_ref| <= 1e-5 sum_k |A||B|.
-* forward, loss and every gradient against the oracle with the same BF16
+* forward (batches of 1 and 2 take streaming products per layer; batches up
+  to 256 with H <= 512 the persistent W3 kernels; others the tiled GEMM),
+  loss and every gradient against the oracle with the same BF16
   roundings emulated: relative Frobenius error <= 1e-2 (an FP32-order
   difference can flip a BF16 rounding, or a ReLU mask at zero).
 * Adam: one step against the oracle's step on the same gradients, <= 1e-5.
@@ -39,7 +42,9 @@ def _bf(x):
 
 @pytest.mark.parametrize("M_,N_,K_,ak,bk,splits", [(200, 300, 100, 1, 1, 1), (129, 77, 64, 0, 1, 1),
                                                     (256, 130, 40, 1, 0, 1), (70, 512, 515, 0, 0, 1),
-                                                    (33, 260, 2000, 1, 0, 7), (1, 1000, 512, 1, 1, 1)])
+                                                    (33, 260, 2000, 1, 0, 7), (1, 1000, 512, 1, 1, 1),
+                                                    (200, 8300, 72, 1, 1, 1), (250, 8200, 40, 0, 0, 1),
+                                                    (130, 8192, 100, 1, 0, 2)])
 def test_gemm_layouts(M, M_, N_, K_, ak, bk, splits):
     L, _ = M
     rng = np.random.default_rng(M_ + N_ + K_)
@@ -90,7 +95,9 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-@pytest.mark.parametrize("B,H,n_out", [(70, 64, 1001), (256, 512, 4227)])
+@pytest.mark.parametrize("B,H,n_out", [(70, 64, 1001), (256, 512, 4227), (200, 512, 8500), (1, 512, 9001),
+                                       (2, 64, 300), (1, 2048, 333), (300, 64, 777), (33, 520, 250),
+                                       (96, 256, 65000)])
 def test_forward_loss_and_gradients_match_oracle(M, B, H, n_out):
     L, mlp = M
     net, prm = _net(mlp, 16, H, n_out, seed=B)
