@@ -19,6 +19,8 @@
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // FP32 -> BF16 bits, round to nearest even (NaN kept quiet)
@@ -244,17 +246,27 @@ struct W3Args {
 
 __device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
 
+// One wait per panel.  gfx950 counts vector loads and stores on one counter,
+// and a load result needed while stores are in flight can only be waited for
+// with a full wait.  So each panel starts with one full wait, and everything it
+// consumes was issued one panel earlier: its tile of the wide operand, its
+// targets and bias; the stores of the panel before it are issued from
+// registers only after this panel's tile is in LDS.  Loads use clamped
+// addresses and a select instead of a branch, and the last panel's prefetch
+// reloads itself, so every panel issues the same accesses.
+__device__ __forceinline__ void wait_all() { __builtin_amdgcn_s_waitcnt(0); }
+
 template <int EPI>
 __global__ void __launch_bounds__(512) k_w3_fwd(W3Args g) {
     constexpr int PPT = PNL * (HMAX / 8) / 512;  // 16-byte pieces of a panel per thread
-    __shared__ __align__(16) uint16_t Ws[PNL][LDP];
+    __shared__ __align__(16) uint16_t Ws[PNL + 1][LDP];
     __shared__ float s_db[8][32];
     __shared__ double s_loss[8];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int npc = g.H / 8, nact = min(8, (g.B + 31) / 32);
     const bool active = wave < nact;
     // columns past H stay zero: the panel stores below never reach them
-    for (int i = threadIdx.x; i < PNL * LDP / 8; i += 512)
+    for (int i = threadIdx.x; i < (PNL + 1) * LDP / 8; i += 512)
         reinterpret_cast<uint4 *>(&Ws[0][0])[i] = make_uint4(0, 0, 0, 0);
     uint4 a[KSMAX];
     {
@@ -270,70 +282,103 @@ __global__ void __launch_bounds__(512) k_w3_fwd(W3Args g) {
 #pragma unroll
     for (int h = 0; h < PPT; h++) {
         const int v = threadIdx.x + 512 * h;
-        pr[h] = v / npc;
-        pc[h] = (v - pr[h] * npc) * 8;
+        pr[h] = min(v / npc, PNL);  // row PNL of Ws takes the pieces past the panel (H < 512)
+        pc[h] = v / npc < PNL ? (v - (v / npc) * npc) * 8 : 0;
     }
+    // raw loads from clamped addresses; the pieces past the panel or past O are zeroed when stored
+    // (a select right after a load would wait for it at once)
     auto fetch = [&](int p, uint4 (&pf)[PPT]) {
 #pragma unroll
         for (int h = 0; h < PPT; h++) {
-            const int n = p * PNL + pr[h];
-            pf[h] = make_uint4(0, 0, 0, 0);
-            if (pr[h] < PNL && n < g.O)
-                pf[h] = *reinterpret_cast<const uint4 *>(
-                    reinterpret_cast<const char *>(g.W3 + int64_t(p) * PNL * g.H) + 2u * uint32_t(pr[h] * g.H + pc[h]));
+            const int r = min(pr[h], min(PNL, g.O - p * PNL) - 1);
+            pf[h] = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(g.W3 + int64_t(p) * PNL * g.H) +
+                                                     2u * uint32_t(r * g.H + pc[h]));
         }
     };
-    // db3 of the previous panel from the per-wave column sums
-    auto flush_db3 = [&](int pp) {
-        if (EPI == EPI_LOSS && pp >= 0 && threadIdx.x < 32 && pp * PNL + int(threadIdx.x) < g.O) {
-            float t = 0.0f;
-            for (int w = 0; w < nact; w++) t += s_db[w][threadIdx.x];
-            g.db3[pp * PNL + threadIdx.x] = t;
-        }
-    };
-    // element (m, n) of U, dY and Y (all [B x O]) sits at the uniform offset (8 (r / 4) + r % 4) O
-    // + 32 p plus the lane's own, (32 wave + 4 (lane / 32)) O + lane % 32, for m = 32 wave + 4 (lane /
-    // 32) + 8 (r / 4) + r % 4 and n = 32 p + lane % 32; the lane's part is kept as a 32-bit byte offset
-    const uint32_t L = uint32_t(wave * 32 + 4 * (lane >> 5)) * uint32_t(g.O) + uint32_t(lane & 31);
-    const uint32_t L4 = 4u * L;
-    // dY is tiled by panel: [O / 32][B][32], so the lane's byte offset within a tile is
+    // element (m, n) of U and Y ([B x O]) sits at the uniform offset (8 (r / 4) + r % 4) O + 32 p
+    // plus the lane's own, (32 wave + 4 (lane / 32)) O + lane % 32, for m = 32 wave + 4 (lane / 32)
+    // + 8 (r / 4) + r % 4 and n = 32 p + lane % 32; the lane's part is kept as a 32-bit byte offset
+    const uint32_t L4 = 4u * (uint32_t(wave * 32 + 4 * (lane >> 5)) * uint32_t(g.O) + uint32_t(lane & 31));
+    // dY is tiled by panel ([O / 32][B][32]): the lane's byte offset within a tile
     const uint32_t LT = 2u * uint32_t((wave * 32 + 4 * (lane >> 5)) * PNL + (lane & 31));
-    // byte offset of row 8 (r / 4) + r % 4 (uniform, 32 bits)
     auto roff = [&](int r, uint32_t esz) { return esz * uint32_t(8 * (r >> 2) + (r & 3)) * uint32_t(g.O); };
     // the compiler would otherwise keep one offset per row live across the panel loop
     auto opaque = [](uint32_t x) {
         asm volatile("" : "+v"(x));
         return x;
     };
+    // raw loads; rows past B and columns past n_valid read element (0, 32 p) instead, and the
+    // epilogue never uses them
     auto fetch_u = [&](int p, float (&u)[16]) {
         const int n = p * PNL + (lane & 31);
         const uint32_t l4 = opaque(L4);
 #pragma unroll
         for (int r = 0; r < 16; r++) {
             const int m = wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            u[r] = (m < g.B && n < g.n_valid)
-                       ? *reinterpret_cast<const float *>(reinterpret_cast<const char *>(g.U + int64_t(p) * PNL) +
-                                                          (l4 + roff(r, 4u)))
-                       : 0.0f;
+            const uint32_t o = m < g.B && n < g.n_valid ? l4 + roff(r, 4u) : 0u;
+            u[r] = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(g.U + int64_t(p) * PNL) + o);
         }
     };
+    auto fetch_bias = [&](int p) { return g.bias[min(p * PNL + (lane & 31), g.O - 1)]; };
+    // db3 of panel pp from the per-wave column sums
+    auto flush_db3 = [&](int pp) {
+        if (EPI == EPI_LOSS && threadIdx.x < 32 && pp * PNL + int(threadIdx.x) < g.O) {
+            float t = 0.0f;
+            for (int w = 0; w < nact; w++) t += s_db[w][threadIdx.x];
+            g.db3[pp * PNL + threadIdx.x] = t;
+        }
+    };
+    // the outputs of panel ph, held in registers until the next panel's tile is in LDS
+    float yh[16];
+    uint32_t qh[8];
+    int ph = -1;
+    auto store_held = [&]() {
+        if (ph < 0 || !active) return;
+        const int n = ph * PNL + (lane & 31);
+        const uint32_t l4 = opaque(L4), lt = opaque(LT);
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            const int m = wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            if (m >= g.B || n >= g.N) continue;
+            if constexpr (EPI == EPI_BIAS_F32) {
+                *reinterpret_cast<float *>(reinterpret_cast<char *>(g.Y + int64_t(ph) * PNL) + (l4 + roff(r, 4u))) = yh[r];
+            } else {
+                *reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(g.dY + int64_t(ph) * PNL * g.B) +
+                                              (lt + 64u * uint32_t(8 * (r >> 2) + (r & 3)))) =
+                    uint16_t(r & 1 ? qh[r >> 1] >> 16 : qh[r >> 1] & 0xffffu);
+            }
+        }
+    };
+    // each workgroup takes a contiguous run of panels
+    const int npan = (g.O + PNL - 1) / PNL, per = (npan + gridDim.x - 1) / gridDim.x;
+    const int p_beg = min(npan, int(blockIdx.x) * per), p_end = min(npan, p_beg + per);
+    uint4 pf[PPT];
+    float u[16], un[16], bn = 0.0f, bnn = 0.0f;
     double lsum = 0.0;
-    int prev = -1;
-    // one panel of W3 per iteration: stored to LDS from registers loaded two iterations earlier
-    // (W3) or one (U), then refilled; the two register sets alternate between iterations
-    auto panel = [&](int p, int p_end, uint4 (&pf)[PPT], float (&u_cur)[16], float (&u_nxt)[16]) {
-        __syncthreads();  // the previous panel and its column sums have been written and read
-        flush_db3(prev);
-        prev = p;
+    if (p_beg < p_end) {
+        fetch(p_beg, pf);
+        if (EPI == EPI_LOSS && active) fetch_u(p_beg, un);
+        bnn = fetch_bias(p_beg);
+    }
+    for (int p = p_beg; p < p_end; p++) {
+        wait_all();
+        __syncthreads();  // the previous panel's tile and column sums have been read and written
+        if (p > p_beg) flush_db3(p - 1);
 #pragma unroll
         for (int h = 0; h < PPT; h++)
-            if (pr[h] < PNL) *reinterpret_cast<uint4 *>(&Ws[pr[h]][pc[h]]) = pf[h];
+            *reinterpret_cast<uint4 *>(&Ws[pr[h]][pc[h]]) =
+                pr[h] < min(PNL, g.O - p * PNL) ? pf[h] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 16; r++) u[r] = un[r];
+        bn = bnn;
         __syncthreads();
-        if (p + 2 < p_end) fetch(p + 2, pf);
-        if (!active) return;
-        if (EPI == EPI_LOSS && p + 1 < p_end) fetch_u(p + 1, u_nxt);
-        const int n = p * PNL + (lane & 31);
-        const float bn = n < g.N ? g.bias[n] : 0.0f;
+        store_held();
+        const int pn = min(p + 1, p_end - 1);
+        fetch(pn, pf);
+        if (EPI == EPI_LOSS && active) fetch_u(pn, un);
+        bnn = fetch_bias(pn);
+        ph = p;
+        if (!active) continue;
         f32x16 acc;
 #pragma unroll
         for (int r = 0; r < 16; r++) acc[r] = 0.0f;
@@ -342,47 +387,37 @@ __global__ void __launch_bounds__(512) k_w3_fwd(W3Args g) {
             const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&Ws[lane & 31][16 * ks + 8 * (lane >> 5)]);
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(a[ks]), b, acc, 0, 0, 0);
         }
-        // acc[r]: row 32 wave + 8 (r / 4) + 4 (lane / 32) + r % 4, column n
-        const uint32_t l4 = opaque(L4), lt = opaque(LT);
-        float csum = 0.0f;
+        // acc[r]: row 32 wave + 8 (r / 4) + 4 (lane / 32) + r % 4, column 32 p + lane % 32
+        if constexpr (EPI == EPI_BIAS_F32) {
 #pragma unroll
-        for (int r = 0; r < 16; r++) {
-            const int m = wave * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            if (m >= g.B || n >= g.N) continue;
-            if constexpr (EPI == EPI_BIAS_F32) {
-                *reinterpret_cast<float *>(reinterpret_cast<char *>(g.Y + int64_t(p) * PNL) + (l4 + roff(r, 4u))) =
-                    acc[r] + bn;
-            } else {
-                const float d = n < g.n_valid ? acc[r] + bn - u_cur[r] : 0.0f;
-                const uint16_t q = f2bf(d * g.gscale);
-                *reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(g.dY + int64_t(p) * PNL * g.B) +
-                                              (lt + 64u * uint32_t(8 * (r >> 2) + (r & 3)))) = q;
-                csum += bf2f(q);
-                lsum += double(d) * double(d);
+            for (int r = 0; r < 16; r++) yh[r] = acc[r] + bn;
+        } else {
+            const int n = p * PNL + (lane & 31);
+            float csum = 0.0f, ls = 0.0f;
+#pragma unroll
+            for (int r = 0; r < 16; r += 2) {
+                float d[2];
+#pragma unroll
+                for (int t = 0; t < 2; t++) {
+                    const int m = wave * 32 + 8 * ((r + t) >> 2) + 4 * (lane >> 5) + ((r + t) & 3);
+                    d[t] = (m < g.B && n < g.n_valid) ? acc[r + t] + bn - u[r + t] : 0.0f;
+                    ls += d[t] * d[t];
+                }
+                // two BF16 roundings (to nearest even) in one conversion
+                const f32x2 sd = {d[0] * g.gscale, d[1] * g.gscale};
+                const uint32_t q2 = __builtin_bit_cast(uint32_t, __builtin_convertvector(sd, bf16x2));
+                csum += __uint_as_float(q2 << 16) + __uint_as_float(q2 & 0xffff0000u);
+                qh[r >> 1] = q2;
             }
-        }
-        if constexpr (EPI == EPI_LOSS) {
+            lsum += double(ls);  // 16 squares per lane and panel in FP32, the running sum in FP64
             csum += __shfl_xor(csum, 32, 64);
             if (lane < 32) s_db[wave][lane] = csum;
         }
-    };
-    // each workgroup takes a contiguous run of panels, so the two halves of a 128-byte line of dY
-    // (and a line of U that straddles panels) meet in its L2
-    const int npan = (g.O + PNL - 1) / PNL, per = (npan + gridDim.x - 1) / gridDim.x;
-    const int p_beg = min(npan, int(blockIdx.x) * per), p_end = min(npan, p_beg + per);
-    uint4 pfA[PPT], pfB[PPT];
-    float uA[16], uB[16];
-    if (p_beg < p_end) {
-        fetch(p_beg, pfA);
-        if (p_beg + 1 < p_end) fetch(p_beg + 1, pfB);
-        if (EPI == EPI_LOSS && active) fetch_u(p_beg, uA);
     }
-    for (int p = p_beg; p < p_end; p += 2) {
-        panel(p, p_end, pfA, uA, uB);
-        if (p + 1 < p_end) panel(p + 1, p_end, pfB, uB, uA);
-    }
+    wait_all();
     __syncthreads();
-    flush_db3(prev);
+    if (p_end > p_beg) flush_db3(p_end - 1);
+    store_held();
     if constexpr (EPI == EPI_LOSS) {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
@@ -420,49 +455,25 @@ __global__ void __launch_bounds__(512) k_w3_dw(int B, int H, int O, const uint16
         }
         __builtin_amdgcn_sched_barrier(0);  // bounds the 16-bit loads in flight
     }
-    // each thread moves rows 2 mp, 2 mp + 1 of one 8-column group of the panel
+    // each thread moves rows 2 mp, 2 mp + 1 of one 8-column group of a dY tile
     const int cg = (threadIdx.x & 3) * 8, mp = threadIdx.x >> 2;
+    // raw loads from clamped addresses, zeroed when stored (see k_w3_fwd)
     auto fetch = [&](int p, uint4 &r0, uint4 &r1) {
-        const int n = p * PNL + cg;
-        r0 = make_uint4(0, 0, 0, 0);
-        r1 = make_uint4(0, 0, 0, 0);
-        const uint16_t *tile = dY + int64_t(p) * PNL * B + 2 * mp * PNL + cg;
-        if (n < O && 2 * mp < B) r0 = *reinterpret_cast<const uint4 *>(tile);
-        if (n < O && 2 * mp + 1 < B) r1 = *reinterpret_cast<const uint4 *>(tile + PNL);
+        const uint16_t *tile = dY + int64_t(p) * PNL * B + (p * PNL + cg < O ? cg : 0);
+        r0 = *reinterpret_cast<const uint4 *>(tile + min(2 * mp, B - 1) * PNL);
+        r1 = *reinterpret_cast<const uint4 *>(tile + min(2 * mp + 1, B - 1) * PNL);
     };
-    // one panel per iteration, stored to LDS from registers loaded two iterations earlier
-    auto panel = [&](int p, int p_end, uint4 &r0, uint4 &r1) {
-        __syncthreads();
-        {
-            const uint32_t x0[4] = {r0.x, r0.y, r0.z, r0.w}, x1[4] = {r1.x, r1.y, r1.z, r1.w};
-#pragma unroll
-            for (int i = 0; i < 4; i++) {
-                *reinterpret_cast<uint32_t *>(&Ts[cg + 2 * i][2 * mp]) = (x0[i] & 0xffffu) | (x1[i] << 16);
-                *reinterpret_cast<uint32_t *>(&Ts[cg + 2 * i + 1][2 * mp]) = (x0[i] >> 16) | (x1[i] & 0xffff0000u);
-            }
-        }
-        __syncthreads();
-        if (p + 2 < p_end) fetch(p + 2, r0, r1);
-        if (64 * wave >= H) return;
-        const int n0 = p * PNL;
-        f32x16 acc[2];
-#pragma unroll
-        for (int j = 0; j < 2; j++)
-#pragma unroll
-            for (int r = 0; r < 16; r++) acc[j][r] = 0.0f;
-#pragma unroll
-        for (int ks = 0; ks < KS; ks++) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&Ts[lane & 31][16 * ks + 8 * (lane >> 5)]);
-#pragma unroll
-            for (int j = 0; j < 2; j++)
-                acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, as_bf16x8(b[ks][j]), acc[j], 0, 0, 0);
-        }
-        // acc[j][r]: dW3 row n0 + 8 (r / 4) + 4 (lane / 32) + r % 4, column 64 wave + 32 j + lane % 32
+    // acc of panel ph is stored only after the next panel's tile is in LDS (one wait per panel, as in k_w3_fwd)
+    f32x16 acc[2];
+    int ph = -1;
+    auto store_held = [&]() {
+        if (ph < 0 || 64 * wave >= H) return;
+        const int n0 = ph * PNL;
+        char *base = reinterpret_cast<char *>(dW3 + int64_t(n0) * H);
 #pragma unroll
         for (int j = 0; j < 2; j++) {
             const int h = 64 * wave + 32 * j + (lane & 31);
             const uint32_t lo = 4u * uint32_t(4 * (lane >> 5) * H + h);
-            char *base = reinterpret_cast<char *>(dW3 + int64_t(n0) * H);
 #pragma unroll
             for (int r = 0; r < 16; r++) {
                 const int n = n0 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -474,21 +485,51 @@ __global__ void __launch_bounds__(512) k_w3_dw(int B, int H, int O, const uint16
     // contiguous runs of panels: consecutive dY tiles
     const int npan = (O + PNL - 1) / PNL, per = (npan + gridDim.x - 1) / gridDim.x;
     const int p_beg = min(npan, int(blockIdx.x) * per), p_end = min(npan, p_beg + per);
-    uint4 a0, a1, b0, b1;
-    if (p_beg < p_end) fetch(p_beg, a0, a1);
-    if (p_beg + 1 < p_end) fetch(p_beg + 1, b0, b1);
-    for (int p = p_beg; p < p_end; p += 2) {
-        panel(p, p_end, a0, a1);
-        if (p + 1 < p_end) panel(p + 1, p_end, b0, b1);
+    uint4 r0, r1;
+    if (p_beg < p_end) fetch(p_beg, r0, r1);
+    for (int p = p_beg; p < p_end; p++) {
+        wait_all();
+        __syncthreads();
+        {
+            const bool okc = p * PNL + cg < O;
+            const uint4 z4 = make_uint4(0, 0, 0, 0);
+            const uint4 s0 = okc && 2 * mp < B ? r0 : z4, s1 = okc && 2 * mp + 1 < B ? r1 : z4;
+            const uint32_t x0[4] = {s0.x, s0.y, s0.z, s0.w}, x1[4] = {s1.x, s1.y, s1.z, s1.w};
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                *reinterpret_cast<uint32_t *>(&Ts[cg + 2 * i][2 * mp]) = (x0[i] & 0xffffu) | (x1[i] << 16);
+                *reinterpret_cast<uint32_t *>(&Ts[cg + 2 * i + 1][2 * mp]) = (x0[i] >> 16) | (x1[i] & 0xffff0000u);
+            }
+        }
+        __syncthreads();
+        store_held();
+        fetch(min(p + 1, p_end - 1), r0, r1);
+        ph = p;
+        if (64 * wave >= H) continue;
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int r = 0; r < 16; r++) acc[j][r] = 0.0f;
+#pragma unroll
+        for (int ks = 0; ks < KS; ks++) {
+            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&Ts[lane & 31][16 * ks + 8 * (lane >> 5)]);
+#pragma unroll
+            for (int j = 0; j < 2; j++)
+                acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, as_bf16x8(b[ks][j]), acc[j], 0, 0, 0);
+        }
     }
+    wait_all();
+    store_held();
 }
 
 // dH2 partial sums over runs of W3 rows: part[z][m][h] = sum over the n of run z of dY[m][n] W3[n][h].
 // Workgroup b takes run z and the 128-column slice sl of H; the slices of one run share b % 8 (one
 // XCD), so the dY tiles they all read meet in its L2.  Wave w owns rows 32 w .. 32 w + 31 and the
 // slice's four 32-column blocks.  dY operands come straight from the tiles (8 consecutive n of a row
-// are 16 contiguous bytes); 64 rows of W3 at a time are staged transposed ([h][n]) in LDS.
-constexpr int DHN = 64, DHS = 128, LDH = DHN + 8;
+// are 16 contiguous bytes); 128 rows of W3 at a time are staged transposed ([h][n]) in LDS.  Nothing
+// is stored inside the loop, so the compiler's waits count loads precisely: the loads of the next two
+// chunks stay in flight while this chunk multiplies.
+constexpr int DHN = 128, DHS = 128, LDH = DHN + 8, DKS = DHN / 16;
 
 __global__ void __launch_bounds__(512) k_w3_dh(int B, int H, int O, int nsplit, const uint16_t *__restrict__ dY,
                                                const uint16_t *__restrict__ W3, float *__restrict__ part) {
@@ -502,23 +543,27 @@ __global__ void __launch_bounds__(512) k_w3_dh(int B, int H, int O, int nsplit, 
     const int c_beg = min(nch, z * per), c_end = min(nch, c_beg + per);
     const bool active = 32 * wave < B;
     const int m = 32 * wave + (lane & 31);
-    // W3 staging: rows 2 q, 2 q + 1 of the chunk, 8 columns from hq
+    // W3 staging: rows 2 q, 2 q + 1 and 64 + 2 q, 65 + 2 q of the chunk, 8 columns from hq
     const int q = threadIdx.x >> 4, hq = (threadIdx.x & 15) * 8;
-    auto fetch_w = [&](int c, uint4 &w0, uint4 &w1) {
-        const int n = c * DHN + 2 * q, h = h0 + hq;
-        w0 = make_uint4(0, 0, 0, 0);
-        w1 = make_uint4(0, 0, 0, 0);
-        if (h < H && n < O) w0 = *reinterpret_cast<const uint4 *>(W3 + int64_t(n) * H + h);
-        if (h < H && n + 1 < O) w1 = *reinterpret_cast<const uint4 *>(W3 + int64_t(n + 1) * H + h);
-    };
-    // dY operands of chunk c: k-step ks covers n = 64 c + 16 ks + 8 (lane / 32) + 0..7
-    auto fetch_a = [&](int c, uint4 (&a)[4]) {
+    // raw loads from clamped addresses, zeroed when used (a select right after a load would wait for it)
+    auto fetch_w = [&](int c, uint4 (&w)[4]) {
+        const int h = h0 + hq, hc = h < H ? h : 0;
 #pragma unroll
-        for (int ks = 0; ks < 4; ks++) {
-            const int p = 2 * c + (ks >> 1), k = 16 * (ks & 1) + 8 * (lane >> 5);
-            a[ks] = make_uint4(0, 0, 0, 0);
-            if (active && m < B && p * PNL + k < O)
-                a[ks] = *reinterpret_cast<const uint4 *>(dY + (int64_t(p) * B + m) * PNL + k);
+        for (int i = 0; i < 4; i++) {
+            const int n = c * DHN + 64 * (i >> 1) + 2 * q + (i & 1);
+            w[i] = *reinterpret_cast<const uint4 *>(W3 + int64_t(min(n, O - 1)) * H + hc);
+        }
+    };
+    // dY operands of chunk c: k-step ks covers n = 128 c + 16 ks + 8 (lane / 32) + 0..7
+    auto a_ok = [&](int c, int ks) {
+        const int p = 4 * c + (ks >> 1), k = 16 * (ks & 1) + 8 * (lane >> 5);
+        return m < B && p * PNL + k < O;
+    };
+    auto fetch_a = [&](int c, uint4 (&a)[DKS]) {
+#pragma unroll
+        for (int ks = 0; ks < DKS; ks++) {
+            const int p = 4 * c + (ks >> 1), k = 16 * (ks & 1) + 8 * (lane >> 5);
+            a[ks] = *reinterpret_cast<const uint4 *>(dY + (a_ok(c, ks) ? (int64_t(p) * B + m) * PNL + k : 0));
         }
     };
     f32x16 acc[4];
@@ -526,45 +571,52 @@ __global__ void __launch_bounds__(512) k_w3_dh(int B, int H, int O, int nsplit, 
     for (int j = 0; j < 4; j++)
 #pragma unroll
         for (int r = 0; r < 16; r++) acc[j][r] = 0.0f;
-    auto chunk = [&](int c, uint4 &w0, uint4 &w1, uint4 (&a)[4]) {
-        __syncthreads();
+    // two register sets, two chunks ahead; an odd run ends with chunk nch, past the matrix, which adds zeros
+    auto chunk = [&](int c, uint4 (&w)[4], uint4 (&a)[DKS]) __attribute__((always_inline)) {
+        __syncthreads();  // the previous chunk's tile has been read
         {
-            const uint32_t x0[4] = {w0.x, w0.y, w0.z, w0.w}, x1[4] = {w1.x, w1.y, w1.z, w1.w};
+            const int h = h0 + hq;
+            const uint4 z4 = make_uint4(0, 0, 0, 0);
 #pragma unroll
-            for (int i = 0; i < 4; i++) {
-                *reinterpret_cast<uint32_t *>(&Wt[hq + 2 * i][2 * q]) = (x0[i] & 0xffffu) | (x1[i] << 16);
-                *reinterpret_cast<uint32_t *>(&Wt[hq + 2 * i + 1][2 * q]) = (x0[i] >> 16) | (x1[i] & 0xffff0000u);
+            for (int pr = 0; pr < 2; pr++) {
+                const int n = c * DHN + 64 * pr + 2 * q;
+                const uint4 s0 = h < H && n < O ? w[2 * pr] : z4;
+                const uint4 s1 = h < H && n + 1 < O ? w[2 * pr + 1] : z4;
+                const uint32_t x0[4] = {s0.x, s0.y, s0.z, s0.w}, x1[4] = {s1.x, s1.y, s1.z, s1.w};
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    *reinterpret_cast<uint32_t *>(&Wt[hq + 2 * i][64 * pr + 2 * q]) = (x0[i] & 0xffffu) | (x1[i] << 16);
+                    *reinterpret_cast<uint32_t *>(&Wt[hq + 2 * i + 1][64 * pr + 2 * q]) =
+                        (x0[i] >> 16) | (x1[i] & 0xffff0000u);
+                }
             }
         }
-        __syncthreads();
-        uint4 ac[4];
+        uint4 ac[DKS];
 #pragma unroll
-        for (int ks = 0; ks < 4; ks++) ac[ks] = a[ks];
-        if (c + 2 < c_end) {
-            fetch_w(c + 2, w0, w1);
-            fetch_a(c + 2, a);
-        }
+        for (int ks = 0; ks < DKS; ks++) ac[ks] = a_ok(c, ks) ? a[ks] : make_uint4(0, 0, 0, 0);
+        __syncthreads();
+        const int cn = min(c + 2, c_end - 1);
+        fetch_w(cn, w);
+        fetch_a(cn, a);
         if (!active) return;
 #pragma unroll
-        for (int ks = 0; ks < 4; ks++)
+        for (int ks = 0; ks < DKS; ks++)
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(&Wt[32 * j + (lane & 31)][16 * ks + 8 * (lane >> 5)]);
                 acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf16x8(ac[ks]), bw, acc[j], 0, 0, 0);
             }
     };
-    uint4 wA0, wA1, wB0, wB1, aA[4], aB[4];
+    uint4 wA[4], aA[DKS], wB[4], aB[DKS];
     if (c_beg < c_end) {
-        fetch_w(c_beg, wA0, wA1);
+        fetch_w(c_beg, wA);
         fetch_a(c_beg, aA);
-    }
-    if (c_beg + 1 < c_end) {
-        fetch_w(c_beg + 1, wB0, wB1);
-        fetch_a(c_beg + 1, aB);
+        fetch_w(min(c_beg + 1, c_end - 1), wB);
+        fetch_a(min(c_beg + 1, c_end - 1), aB);
     }
     for (int c = c_beg; c < c_end; c += 2) {
-        chunk(c, wA0, wA1, aA);
-        if (c + 1 < c_end) chunk(c + 1, wB0, wB1, aB);
+        chunk(c, wA, aA);
+        chunk(c + 1 < c_end ? c + 1 : nch, wB, aB);
     }
     if (!active) return;
     // acc[j][r]: row 32 wave + 8 (r / 4) + 4 (lane / 32) + r % 4, column h0 + 32 j + lane % 32
