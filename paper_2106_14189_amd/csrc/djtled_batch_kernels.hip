@@ -146,12 +146,13 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK), (Kinds<T, V>::WPE)) k_ba
         INSTR_T(t0);
         PhaseOut po{0.0, 0.0, 0, -1};
         int bad_kind = -1;
-        // FP32: runs of consecutive chunks of one kind, software-pipelined as in
-        // the single-mesh kernel: the copy data of chunk k + 1 is loaded while
-        // chunk k is summed and updated, the element data of a chunk is in
-        // flight during its scatter, and its load values are fetched after it.
-        // FP64 and the occupancy variants keep the plain order (their
-        // registers do not hold the pipeline).
+        // FP32: runs of consecutive chunks of one kind, software-pipelined: the
+        // element and copy data of chunk k + 1 are loaded while chunk k is
+        // summed and updated, and chunk k's node results are stored during chunk
+        // k + 1 (process_held; the LDS-staging variants load the copy data
+        // ahead and the element data during the scatter).  FP64 and the
+        // occupancy variant keep the plain order (their registers do not hold
+        // the pipeline).
         for (int w0 = 0; w0 < nmine; w0 += KMAXB) {
         const int wn = window(w0);
         if constexpr (!K::PIPE) {
@@ -176,6 +177,26 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK), (Kinds<T, V>::WPE)) k_ba
                 using CK = typename K::template C<KC>;
                 const StepPtrs<T> sp = kind_ptrs<T>(bd.k[KC], cur, prv, nxt, s, n);
                 typename CK::CopyRegs cp;
+                if constexpr (!K::PF) {
+                    // one wait per chunk; the node results go out during the next chunk
+                    typename CK::ElemRegs er;
+                    typename CK::Held held;
+                    CK::held_clear(held);
+                    CK::load_elems(bd.k[KC].tp, s_ch[k0], er);
+                    CK::template load_copies<1>(bd.k[KC].tp, s_ch[k0], sp, cp);
+                    for (int k = k0; k < k1; k++) {
+                        CK::process_held(
+                            s_ch[k], sp, smem, po, er, cp, held,
+                            [&](int j) {
+                                if (k + 1 < k1) CK::load_elem(bd.k[KC].tp, s_ch[k + 1], er, j);
+                            },
+                            [&]() {
+                                if (k + 1 < k1) CK::template load_copies<1>(bd.k[KC].tp, s_ch[k + 1], sp, cp);
+                            });
+                    }
+                    CK::held_store(held, sp);
+                    return;
+                }
                 CK::template load_copies<1>(bd.k[KC].tp, s_ch[k0], sp, cp);
                 for (int k = k0; k < k1; k++) {
                     const int kn = k + 1 < wn ? k + 1 : 0;

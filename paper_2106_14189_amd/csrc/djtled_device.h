@@ -506,31 +506,38 @@ __device__ __forceinline__ T ramp_rate(T q, T n1) {
 
 // u^{n+1} = u^n + B'(u^n - u^{n-1}) + A (R - F); prescribed components = s(t) target
 template <typename T>
-__device__ __forceinline__ void node_update(int l, uint32_t fl, const T (&f)[3], const T (&uc)[3], const T (&up)[3],
-                                            T A, T bp, T sv, const T (&rv)[3], const StepPtrs<T> &sp,
-                                            PhaseOut &po) {
+__device__ __forceinline__ void node_value(int l, uint32_t fl, const T (&f)[3], const T (&uc)[3], const T (&up)[3],
+                                           T A, T bp, T sv, const T (&rv)[3], const StepPtrs<T> &sp, PhaseOut &po,
+                                           T (&un)[3]) {
     bool fin = true;
 #pragma unroll
     for (int k = 0; k < 3; k++) {
         const bool pres = (fl >> k) & 1u;
-        T un;
         if (pres) {
-            un = sv * rv[k];
+            un[k] = sv * rv[k];
             if (sp.want_res && (fl & FLAG_CANON)) po.den += double(f[k]) * double(f[k]);
         } else {
-            un = uc[k] + bp * (uc[k] - up[k]) + A * (rv[k] - f[k]);
+            un[k] = uc[k] + bp * (uc[k] - up[k]) + A * (rv[k] - f[k]);
             if (sp.want_res && (fl & FLAG_CANON)) {
                 const double d = double(f[k]) - double(rv[k]);
                 po.num += d * d;
             }
         }
-        fin = fin && isfinite(un);
-        sp.un[k][l] = un;
+        fin = fin && isfinite(un[k]);
     }
     if (!fin && po.bad == 0) {
         po.bad = DJ_ERR_NONFINITE;
         po.bad_elem = -2 - l;  // node-level error: the copy
     }
+}
+template <typename T>
+__device__ __forceinline__ void node_update(int l, uint32_t fl, const T (&f)[3], const T (&uc)[3], const T (&up)[3],
+                                            T A, T bp, T sv, const T (&rv)[3], const StepPtrs<T> &sp,
+                                            PhaseOut &po) {
+    T un[3];
+    node_value<T>(l, fl, f, uc, up, A, bp, sv, rv, sp, po, un);
+#pragma unroll
+    for (int k = 0; k < 3; k++) sp.un[k][l] = un[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -553,6 +560,9 @@ struct SharedRegs {  // round-A data of one shared copy per chunk of a batch
 
 struct NoOp {
     __device__ void operator()() const {}
+};
+struct NoOpJ {
+    __device__ void operator()(int) const {}
 };
 
 typedef __attribute__((address_space(3))) void lds_void_t;
@@ -626,21 +636,22 @@ struct Chunk {
     // Element planes and slot positions (register path).  Lanes past the
     // chunk's end load its last element again: the loads are unconditional, so
     // no lane keeps an older value and nothing waits on them before use.
-    __device__ static void load_elems(const DevTopo &tp, const ChunkDesc &ch, ElemRegs &er) {
+    __device__ static void load_elem(const DevTopo &tp, const ChunkDesc &ch, ElemRegs &er, int j) {
         if constexpr (!PF) {
             const T *__restrict__ ep = static_cast<const T *>(tp.elem);
             const int64_t es = tp.estride;
+            const int e = min(int(threadIdx.x) + j * BLOCK, ch.elem_count - 1);
+            const T *src = ep + ch.elem_begin + e;
 #pragma unroll
-            for (int j = 0; j < EPT; j++) {
-                const int e = min(int(threadIdx.x) + j * BLOCK, ch.elem_count - 1);
-                const T *src = ep + ch.elem_begin + e;
+            for (int q = 0; q < NP; q++) er.cst[j][q] = src[q * es];
+            const uint16_t *w = tp.wpos + ch.elem_begin + e;
 #pragma unroll
-                for (int q = 0; q < NP; q++) er.cst[j][q] = src[q * es];
-                const uint16_t *w = tp.wpos + ch.elem_begin + e;
-#pragma unroll
-                for (int a = 0; a < NE; a++) er.wp[j][a] = w[a * es];
-            }
+            for (int a = 0; a < NE; a++) er.wp[j][a] = w[a * es];
         }
+    }
+    __device__ static void load_elems(const DevTopo &tp, const ChunkDesc &ch, ElemRegs &er) {
+#pragma unroll
+        for (int j = 0; j < EPT; j++) load_elem(tp, ch, er, j);
     }
 
     // Per-copy data of the chunk's node copies (MODE 1 adds what the update
@@ -702,22 +713,14 @@ struct Chunk {
         process<MODE, false>(tp, ch, sp, smem, po, er, cp, after);
     }
 
-    // One chunk from registers loaded beforehand (RV: fetch the load values
-    // here, after the scatter).  `after` runs once the element forces are in
-    // LDS and the chunk's registers are consumed or copied, so it may reload
-    // `er` and `cin` with the next chunk's data.
-    template <int MODE, bool RV, typename After>
-    __device__ static void process(const DevTopo &tp, const ChunkDesc &ch, const StepPtrs<T> &sp, unsigned char *smem,
-                                   PhaseOut &po, ElemRegs &er, CopyRegs &cin, After after) {
-        const int tid = threadIdx.x;
-        INSTR_T(i0);
-        T *lx = reinterpret_cast<T *>(smem);
+    // u^n (and the nodal pressure of the average-nodal-pressure step) of each
+    // copy over its contiguous incidence range
+    __device__ static void scatter_u(const ChunkDesc &ch, const StepPtrs<T> &sp, T *lx, const CopyRegs &cin) {
         T *ly = lx + NE * CMAX;
         T *lz = lx + 2 * NE * CMAX;
-        // ---- scatter u^n over each copy's contiguous incidence range
 #pragma unroll
         for (int m = 0; m < MC; m++) {
-            const int i = tid + m * BLOCK;
+            const int i = int(threadIdx.x) + m * BLOCK;
             if (i < ch.copy_count) {
                 const int b = cin.cr[m] & 0xffffu, n = cin.cr[m] >> 16;
                 for (int q = b; q < b + n; q++) {
@@ -730,28 +733,18 @@ struct Chunk {
                         for (int q = b; q < b + n; q++) lz[NE * CMAX + q] = cin.pn[m];
             }
         }
-        if constexpr (RV) load_rv<MODE>(ch, sp, cin);
-        if constexpr (PF) __builtin_amdgcn_s_waitcnt(0);  // this thread's staged loads have landed
-        __syncthreads();
-        INSTR_T(i1);
-        if constexpr (PF) {
-            const T *stage = reinterpret_cast<const T *>(smem + SLOTS);
-            const uint16_t *wstage = reinterpret_cast<const uint16_t *>(smem + SLOTS) + 2 * NP * PDW + (ch.elem_begin & 1);
-#pragma unroll
-            for (int j = 0; j < EPT; j++) {
-                const int e = tid + j * BLOCK;
-                if (e < ch.elem_count) {
-#pragma unroll
-                    for (int q = 0; q < NP; q++) er.cst[j][q] = stage[q * CMAX + e];
-#pragma unroll
-                    for (int a = 0; a < NE; a++) er.wp[j][a] = wstage[a * 2 * WDW + e];
-                }
-            }
-        }
-    // ---- element forces, written back over the element's own positions
+    }
+
+    // element forces from the slots, written back over the element's own positions;
+    // done(j) runs once element slot j's registers are consumed
+    template <typename Done = NoOpJ>
+    __device__ static void forces(const ChunkDesc &ch, const StepPtrs<T> &sp, T *lx, PhaseOut &po, ElemRegs &er,
+                                  Done done = Done()) {
+        T *ly = lx + NE * CMAX;
+        T *lz = lx + 2 * NE * CMAX;
 #pragma unroll
         for (int j = 0; j < EPT; j++) {
-            const int e = tid + j * BLOCK;
+            const int e = int(threadIdx.x) + j * BLOCK;
             if (e < ch.elem_count) {
                 T u[NE][3], F[NE][3];
 #pragma unroll
@@ -795,7 +788,70 @@ struct Chunk {
                     po.bad_elem = ch.elem_begin + e;
                 }
             }
+            done(j);
         }
+    }
+
+    // node sum of the thread's copy m over its range, in fixed order
+    __device__ static void copy_sum(const CopyRegs &c, int m, const T *lx, T (&f)[3]) {
+        const T *ly = lx + NE * CMAX;
+        const T *lz = lx + 2 * NE * CMAX;
+        const int b = c.cr[m] & 0xffffu, n = c.cr[m] >> 16;
+        f[0] = f[1] = f[2] = T(0);
+        // four slots' reads in flight per round, added in slot order (the same sums)
+        int q = b;
+        for (; q + 4 <= b + n; q += 4) {
+            T x[4], y[4], z[4];
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                x[t] = lx[q + t];
+                y[t] = ly[q + t];
+                z[t] = lz[q + t];
+            }
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                f[0] += x[t];
+                f[1] += y[t];
+                f[2] += z[t];
+            }
+        }
+        for (; q < b + n; q++) {
+            f[0] += lx[q];
+            f[1] += ly[q];
+            f[2] += lz[q];
+        }
+    }
+
+    // One chunk from registers loaded beforehand (RV: fetch the load values
+    // here, after the scatter).  `after` runs once the element forces are in
+    // LDS and the chunk's registers are consumed or copied, so it may reload
+    // `er` and `cin` with the next chunk's data.
+    template <int MODE, bool RV, typename After>
+    __device__ static void process(const DevTopo &tp, const ChunkDesc &ch, const StepPtrs<T> &sp, unsigned char *smem,
+                                   PhaseOut &po, ElemRegs &er, CopyRegs &cin, After after) {
+        const int tid = threadIdx.x;
+        INSTR_T(i0);
+        T *lx = reinterpret_cast<T *>(smem);
+        scatter_u(ch, sp, lx, cin);
+        if constexpr (RV) load_rv<MODE>(ch, sp, cin);
+        if constexpr (PF) __builtin_amdgcn_s_waitcnt(0);  // this thread's staged loads have landed
+        __syncthreads();
+        INSTR_T(i1);
+        if constexpr (PF) {
+            const T *stage = reinterpret_cast<const T *>(smem + SLOTS);
+            const uint16_t *wstage = reinterpret_cast<const uint16_t *>(smem + SLOTS) + 2 * NP * PDW + (ch.elem_begin & 1);
+#pragma unroll
+            for (int j = 0; j < EPT; j++) {
+                const int e = tid + j * BLOCK;
+                if (e < ch.elem_count) {
+#pragma unroll
+                    for (int q = 0; q < NP; q++) er.cst[j][q] = stage[q * CMAX + e];
+#pragma unroll
+                    for (int a = 0; a < NE; a++) er.wp[j][a] = wstage[a * 2 * WDW + e];
+                }
+            }
+        }
+        forces(ch, sp, lx, po, er);
         __syncthreads();
         INSTR_T(i2);
         const CopyRegs c = cin;
@@ -805,13 +861,8 @@ struct Chunk {
         for (int m = 0; m < MC; m++) {
             const int i = tid + m * BLOCK;
             if (i < ch.copy_count) {
-                const int b = c.cr[m] & 0xffffu, n = c.cr[m] >> 16;
-                T f[3] = {T(0), T(0), T(0)};
-                for (int q = b; q < b + n; q++) {
-                    f[0] += lx[q];
-                    f[1] += ly[q];
-                    f[2] += lz[q];
-                }
+                T f[3];
+                copy_sum(c, m, lx, f);
                 const int l = ch.copy_begin + i;
                 if (i >= ch.n_interior) {
                     const int q = c.pb[m] + int((c.fl[m] >> FLAG_RANK_SHIFT) & 255u);
@@ -840,6 +891,103 @@ struct Chunk {
         instr_add(4, i2 - i1);
         instr_add(5, i3 - i2);
         instr_add(6, 1);
+#endif
+    }
+
+    // The node results of one chunk, kept in registers until the next chunk
+    // has waited for its loads: copy index (< 0: none), partial entry (>= 0 for
+    // a shared copy's force sum, else the copy's new displacement), values.
+    struct Held {
+        int l[MC], q[MC];
+        T v[MC][3];
+    };
+    __device__ static void held_clear(Held &h) {
+#pragma unroll
+        for (int m = 0; m < MC; m++) h.l[m] = -1;
+    }
+    __device__ static void held_store(const Held &h, const StepPtrs<T> &sp) {
+#pragma unroll
+        for (int m = 0; m < MC; m++) {
+            if (h.l[m] < 0) continue;
+            if (h.q[m] >= 0) {
+                put_partial(sp.pp, h.q[m], h.v[m]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 3; k++) sp.un[k][h.l[m]] = h.v[m][k];
+            }
+        }
+    }
+
+    // Time-step chunk (register path, per-copy coefficients) with one wait for
+    // memory per phase.  gfx950 counts vector loads and stores on one counter,
+    // so waiting for a load while stores are in flight waits for every access
+    // in flight.  Here a chunk waits for everything once at its start (its
+    // element and copy data, loaded during the previous chunk, and that chunk's
+    // stores are then complete), requests its load values, scatters, computes
+    // the element forces while requesting the next chunk's element data
+    // (`reload(j)` after slot j), waits for those loads, issues the next
+    // chunk's copy loads (`after`) and then the previous chunk's stores, and
+    // keeps its own node results in `held` for the next chunk to store.
+    template <typename Reload, typename After>
+    __device__ static void process_held(const ChunkDesc &ch, const StepPtrs<T> &sp, unsigned char *smem, PhaseOut &po,
+                                        ElemRegs &er, CopyRegs &cin, Held &held, Reload reload, After after) {
+        static_assert(PC && !PF, "batch register path");
+        const int tid = threadIdx.x;
+        INSTR_T(i0);
+        T *lx = reinterpret_cast<T *>(smem);
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_sched_barrier(0);
+        load_rv<1>(ch, sp, cin);
+        scatter_u(ch, sp, lx, cin);
+        __syncthreads();
+        INSTR_T(i1);
+        forces(ch, sp, lx, po, er, reload);  // the next chunk's element data is requested slot by slot
+        __syncthreads();
+        INSTR_T(i2);
+        __builtin_amdgcn_s_waitcnt(0);  // the load values and the next element data
+        __builtin_amdgcn_sched_barrier(0);
+        INSTR_T(ia);
+        const CopyRegs c = cin;
+        after();
+        held_store(held, sp);
+        __builtin_amdgcn_sched_barrier(0);
+        INSTR_T(ib);
+#pragma unroll
+        for (int m = 0; m < MC; m++) {
+            const int i = tid + m * BLOCK;
+            held.l[m] = -1;
+            if (i < ch.copy_count) {
+                T f[3];
+                copy_sum(c, m, lx, f);
+                const int l = ch.copy_begin + i;
+                held.l[m] = l;
+                if (i >= ch.n_interior) {
+                    held.q[m] = c.pb[m] + int((c.fl[m] >> FLAG_RANK_SHIFT) & 255u);
+#pragma unroll
+                    for (int k = 0; k < 3; k++) held.v[m][k] = f[k];
+                    if (!(isfinite(f[0]) && isfinite(f[1]) && isfinite(f[2])) && po.bad == 0) {
+                        po.bad = DJ_ERR_NONFINITE;
+                        po.bad_elem = -2 - l;
+                    }
+                } else {
+                    held.q[m] = -1;
+                    node_value<T>(l, c.fl[m], f, c.ux[m], c.upv[m], c.A[m], c.Bp[m], ramp_rate(c.rr[m], sp.n1), c.rv[m],
+                                  sp, po, held.v[m]);
+                }
+            }
+        }
+        INSTR_T(ic);
+        __syncthreads();  // LDS is reused by the next chunk
+#ifdef DJ_INSTR
+        INSTR_T(i3);
+        instr_add(3, i1 - i0);
+        instr_add(4, i2 - i1);
+        instr_add(5, i3 - i2);
+        instr_add(6, 1);
+        instr_add(9, ia - i2);
+        instr_add(10, ib - ia);
+        instr_add(11, ic - ib);
+        instr_add(12, i3 - ic);
 #endif
     }
 

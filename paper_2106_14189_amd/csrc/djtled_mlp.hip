@@ -763,12 +763,25 @@ __global__ void k_splitk_mask(const float *__restrict__ part, int splits, int64_
 }
 
 // column sums of a BF16 matrix [M x N] (bias gradients), fixed order
-__global__ void k_colsum(const uint16_t *__restrict__ X, int M, int N, int64_t ld, float *__restrict__ out) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
+__global__ void __launch_bounds__(256) k_colsum(const uint16_t *__restrict__ X, int M, int N, int64_t ld,
+                                                float *__restrict__ out) {
+    // 32 columns x 8 row slices per block; the slices' sums are added in slice order
+    __shared__ float part[8][33];
+    const int c = threadIdx.x & 31, sl = threadIdx.x >> 5, n = blockIdx.x * 32 + c;
     float s = 0.0f;
-    for (int m = 0; m < M; m++) s += bf2f(X[int64_t(m) * ld + n]);
-    out[n] = s;
+    if (n < N) {
+        const int m0 = sl * ((M + 7) / 8), m1 = min(M, m0 + (M + 7) / 8);
+#pragma unroll 8
+        for (int m = m0; m < m1; m++) s += bf2f(X[int64_t(m) * ld + n]);
+    }
+    part[sl][c] = s;
+    __syncthreads();
+    if (sl == 0 && n < N) {
+        float t = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 8; q++) t += part[q][c];
+        out[n] = t;
+    }
 }
 
 // FP32 [M x K] -> BF16 [M x ldo] (columns K..ldo zero)
@@ -1091,7 +1104,7 @@ int djtled_mlp_loss_grad(const djtled_mlp *m, int32_t batch, const float *P, con
         g.C = gr->W3;
         g.ldc = H;
         MLP_HIP((gemm<false, false, EPI_F32>(g, 1, s)));
-        hipLaunchKernelGGL(k_colsum, dim3((O + 255) / 256), dim3(256), 0, s, w.dY, B, O, int64_t(O), gr->b3);
+        hipLaunchKernelGGL(k_colsum, dim3((O + 31) / 32), dim3(256), 0, s, w.dY, B, O, int64_t(O), gr->b3);
         MLP_HIP(hipGetLastError());
         // dH2 [B x H] = dY W3 (B operand W3 [O x H]: N contiguous), split over K = O; then the ReLU mask of H2
         g = ga(B, H, O, w.dY, O, m->W3_bf16, H);
@@ -1110,7 +1123,7 @@ int djtled_mlp_loss_grad(const djtled_mlp *m, int32_t batch, const float *P, con
     g.C = gr->W2;
     g.ldc = H;
     MLP_HIP((gemm<false, false, EPI_F32>(g, 1, s)));
-    hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, s, w.dZ2, B, H, int64_t(H), gr->b2);
+    hipLaunchKernelGGL(k_colsum, dim3((H + 31) / 32), dim3(256), 0, s, w.dZ2, B, H, int64_t(H), gr->b2);
     MLP_HIP(hipGetLastError());
     // dZ1 [B x H] = (dZ2 W2^T) masked by H1 (B operand W2^T: K contiguous rows of W2)
     g = ga(B, H, H, w.dZ2, H, m->W2_bf16, H);
@@ -1123,7 +1136,7 @@ int djtled_mlp_loss_grad(const djtled_mlp *m, int32_t batch, const float *P, con
     g.C = gr->W1;
     g.ldc = H;
     MLP_HIP((gemm<false, false, EPI_F32>(g, 1, s)));
-    hipLaunchKernelGGL(k_colsum, dim3((H + 255) / 256), dim3(256), 0, s, w.dZ1, B, H, int64_t(H), gr->b1);
+    hipLaunchKernelGGL(k_colsum, dim3((H + 31) / 32), dim3(256), 0, s, w.dZ1, B, H, int64_t(H), gr->b1);
     MLP_HIP(hipGetLastError());
     if (loss) {
         MLP_HIP(hipMemcpyAsync(loss, w.loss, sizeof(double), hipMemcpyDeviceToHost, s));
