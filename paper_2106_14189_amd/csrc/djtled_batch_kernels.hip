@@ -223,10 +223,21 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK), (Kinds<T, V>::WPE)) k_ba
         SharedRegs<T, KB> sr;
         const int nb0 = nmine > 0 ? batch_len(0, wn0) : 0;
         const int kind0 = nmine > 0 ? __builtin_amdgcn_readfirstlane(s_kind[0]) : 0;
+        // FP32 register and staging variants with one window: one memory round per
+        // shared batch (Chunk::shared_fetch); its first round A goes out before the barrier
+        bool spipe = false;
+        if constexpr (K::PIPE) spipe = nmine > 0 && nmine <= KMAXB;
+        typename CS::template SharedIdx<KB> xa;
         if (nmine > 0)
             on_kind(kind0, [&](auto kc) {
                 constexpr int KC = decltype(kc)::value;
                 const StepPtrs<T> sp = kind_ptrs<T>(bd.k[KC], cur, prv, nxt, s, n);
+                if constexpr (K::PIPE) {
+                    if (spipe) {
+                        CS::template shared_idx<KB>(bd.k[KC].tp, s_ch, nb0, 0, sp, xa);
+                        return;
+                    }
+                }
                 CS::template shared_load<1, KB>(bd.k[KC].tp, s_ch, nb0, 0, sp, sr);
             });
         int32_t *errw = &bd.status[5 + (s & 1)];
@@ -250,6 +261,78 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK), (Kinds<T, V>::WPE)) k_ba
             code = s_flag;
             break;
         }
+        int late_kind = -1;
+        bool shared_done = false;
+        if constexpr (K::PIPE) {
+            if (spipe) {
+                // items (batch of chunks, pass), in runs of one kind; per item one
+                // round: its state and partials, the next item's indices, the
+                // previous item's stores.  The first item's indices went out
+                // before the barrier; a later run fetches its first ones on entry.
+                auto more_pass = [&](int k0, int nb, int pass) {
+                    bool more = false;
+                    for (int kb = 0; kb < nb; kb++)
+                        more |= s_ch[k0 + kb].n_interior + (pass + 1) * BLOCK < s_ch[k0 + kb].copy_count;
+                    return more;
+                };
+                for (int r0 = 0; r0 < wn0;) {
+                    const int kind = __builtin_amdgcn_readfirstlane(s_kind[r0]);
+                    int r1 = r0 + 1;
+                    while (r1 < wn0 && s_kind[r1] == kind) r1++;
+                    on_kind(kind, [&](auto kc) {
+                        constexpr int KC = decltype(kc)::value;
+                        const StepPtrs<T> sp = kind_ptrs<T>(bd.k[KC], cur, prv, nxt, s, n);
+                        const DevTopo &tp = bd.k[KC].tp;
+                        int ck0 = r0, cnb = batch_len(r0, wn0), cpass = 0;
+                        if (r0 > 0) CS::template shared_idx<KB>(tp, s_ch + ck0, cnb, 0, sp, xa);
+                        typename CS::template SharedIdx<KB> xb;
+                        typename CS::template SharedPart<KB> pt;
+                        typename CS::template SharedHeld<KB> hs;
+#pragma unroll
+                        for (int kb = 0; kb < KB; kb++) hs.l[kb] = -1;
+                        for (;;) {
+                            CS::template shared_fetch<KB>(s_ch + ck0, cnb, cpass, sp, xa, sr, pt);
+                            int nk0 = ck0, nnb = cnb, npass = cpass;
+                            bool live = true;
+                            if (more_pass(ck0, cnb, cpass)) {
+                                npass++;
+                            } else {
+                                nk0 += cnb;
+                                live = nk0 < r1;
+                                if (live) {
+                                    nnb = batch_len(nk0, wn0);
+                                    npass = 0;
+                                }
+                            }
+                            if (live) CS::template shared_idx<KB>(tp, s_ch + nk0, nnb, npass, sp, xb);
+#pragma unroll
+                            for (int kb = 0; kb < KB; kb++)
+                                if (hs.l[kb] >= 0)
+#pragma unroll
+                                    for (int k = 0; k < 3; k++) sp.un[k][hs.l[kb]] = hs.v[kb][k];
+                            __builtin_amdgcn_s_waitcnt(0);
+                            __builtin_amdgcn_sched_barrier(0);
+                            const bool was_bad = po.bad != 0;
+                            CS::template shared_values<KB>(sr, pt, sp, po, hs);
+                            if (!was_bad && po.bad) late_kind = kind;
+                            if (!live) break;
+                            xa = xb;
+                            ck0 = nk0;
+                            cnb = nnb;
+                            cpass = npass;
+                        }
+#pragma unroll
+                        for (int kb = 0; kb < KB; kb++)
+                            if (hs.l[kb] >= 0)
+#pragma unroll
+                                for (int k = 0; k < 3; k++) sp.un[k][hs.l[kb]] = hs.v[kb][k];
+                    });
+                    r0 = r1;
+                }
+                shared_done = true;
+            }
+        }
+        if (!shared_done) {
         // the first batch (its round A is in registers), then the rest
         if (nmine > 0)
             on_kind(kind0, [&](auto kc) {
@@ -258,7 +341,7 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK), (Kinds<T, V>::WPE)) k_ba
                 CS::template shared_finish<1, KB>(bd.k[KC].tp, sr, sp, po);
                 CS::template shared_batch<1, KB>(bd.k[KC].tp, s_ch, nb0, 1, sp, po);
             });
-        int late_kind = po.bad ? kind0 : -1;
+        late_kind = po.bad ? kind0 : -1;
         for (int w0 = 0; w0 < nmine; w0 += KMAXB) {
             const int wn = w0 == 0 ? wn0 : window(w0);
             for (int k0 = w0 == 0 ? nb0 : 0; k0 < wn;) {
@@ -272,6 +355,7 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK), (Kinds<T, V>::WPE)) k_ba
                 if (po.bad && late_kind < 0) late_kind = kind;
                 k0 += nb;
             }
+        }
         }
         // a node-level error of the shared-node phase stops the run at the next barrier
         if (po.bad && po.bad_elem <= -2)

@@ -1158,6 +1158,109 @@ struct Chunk {
     }
 
     // all passes of one batch of chunks
+    // Shared-node phase of the batch path with one memory round per batch of
+    // chunks.  Round A is only what the partial loads need (flags and
+    // partial-group index per shared copy); every other value of a copy is
+    // addressed by its index, which the chunk descriptor gives, and is loaded
+    // together with the partials.  So the kernel issues, in one round, the
+    // state and partials of batch b, the indices of batch b + 1 and the stores
+    // of batch b - 1 (the results wait in registers, SharedHeld).
+    static constexpr int SUNR = 4;  // partials per copy loaded with the state (more are read on the spot)
+    template <int KB>
+    struct SharedIdx {
+        uint32_t fl[KB];
+        int pb[KB];
+    };
+    template <int KB>
+    struct SharedPart {
+        T px[KB][SUNR][3];
+    };
+    template <int KB>
+    struct SharedHeld {
+        int l[KB];  // < 0: nothing to store
+        T v[KB][3];
+    };
+    template <int KB>
+    __device__ static void shared_idx(const DevTopo &tp, const ChunkDesc *chs, int nb, int pass, const StepPtrs<T> &sp,
+                                      SharedIdx<KB> &x) {
+#pragma unroll
+        for (int kb = 0; kb < KB; kb++) {
+            x.fl[kb] = 0u;
+            x.pb[kb] = 0;
+            if (kb < nb) {
+                const ChunkDesc &ch = chs[kb];
+                const int i = ch.n_interior + int(threadIdx.x) + pass * BLOCK;
+                if (i < ch.copy_count) {
+                    const int l = ch.copy_begin + i;
+                    x.fl[kb] = sp.flags[l];
+                    x.pb[kb] = tp.pidx[l];
+                }
+            }
+        }
+    }
+    template <int KB>
+    __device__ static void shared_fetch(const ChunkDesc *chs, int nb, int pass, const StepPtrs<T> &sp,
+                                        const SharedIdx<KB> &x, SharedRegs<T, KB> &r, SharedPart<KB> &pt) {
+        static_assert(PC, "batch path");
+#pragma unroll
+        for (int kb = 0; kb < KB; kb++) {
+            r.ok[kb] = false;
+            if (kb < nb) {
+                const ChunkDesc &ch = chs[kb];
+                const int i = ch.n_interior + int(threadIdx.x) + pass * BLOCK;
+                if (i < ch.copy_count) {
+                    const int l = ch.copy_begin + i;
+                    r.li[kb] = l;
+                    r.ok[kb] = true;
+                    r.fl[kb] = x.fl[kb];
+                    r.pb[kb] = x.pb[kb];
+                    r.A[kb] = sp.acoef[l];
+#pragma unroll
+                    for (int k = 0; k < 3; k++) {
+                        r.uc[kb][k] = sp.uc[k][l];
+                        r.up[kb][k] = sp.up[k][l];
+                        r.rv[kb][k] = sp.ru[0] ? sp.ru[k][l] : T(0);
+                    }
+                    r.bp[kb] = sp.bpc[l];
+                    r.rr[kb] = sp.rrate ? sp.rrate[l] : T(0);
+                    const int cnt = (x.fl[kb] >> FLAG_NCOPY_SHIFT) & 255u;
+#pragma unroll
+                    for (int q = 0; q < SUNR; q++)
+                        if (q < cnt) get_partial(sp.pp, x.pb[kb] + q, pt.px[kb][q]);
+                }
+            }
+        }
+    }
+    template <int KB>
+    __device__ static void shared_values(SharedRegs<T, KB> &r, const SharedPart<KB> &pt, const StepPtrs<T> &sp,
+                                         PhaseOut &po, SharedHeld<KB> &h) {
+        static_assert(PC, "batch path");
+#pragma unroll
+        for (int kb = 0; kb < KB; kb++) {
+            h.l[kb] = -1;
+            if (!r.ok[kb]) continue;
+            const int cnt = (r.fl[kb] >> FLAG_NCOPY_SHIFT) & 255u;
+            T f[3] = {T(0), T(0), T(0)};
+#pragma unroll
+            for (int q = 0; q < SUNR; q++)
+                if (q < cnt)
+#pragma unroll
+                    for (int k = 0; k < 3; k++) f[k] += pt.px[kb][q][k];
+            for (int q = SUNR; q < cnt; q++) {  // nodes in more than SUNR chunks
+                T g[3];
+                get_partial(sp.pp, r.pb[kb] + q, g);
+#pragma unroll
+                for (int k = 0; k < 3; k++) f[k] += g[k];
+            }
+            if (!(r.fl[kb] & FLAG_RU))
+#pragma unroll
+                for (int k = 0; k < 3; k++) r.rv[kb][k] = T(0);
+            node_value<T>(r.li[kb], r.fl[kb], f, r.uc[kb], r.up[kb], r.A[kb], r.bp[kb],
+                          ramp_rate((r.fl[kb] & FLAG_RU) ? r.rr[kb] : T(0), sp.n1), r.rv[kb], sp, po, h.v[kb]);
+            h.l[kb] = r.li[kb];
+        }
+    }
+
     template <int MODE, int KB>
     __device__ static void shared_batch(const DevTopo &tp, const ChunkDesc *chs, int nb, int first_pass,
                                         const StepPtrs<T> &sp, PhaseOut &po) {
