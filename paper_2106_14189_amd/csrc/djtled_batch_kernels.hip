@@ -90,8 +90,10 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK), (Kinds<T, V>::WPE)) k_ba
     constexpr int KB = 4;  // chunks per shared-phase batch
     using CS = typename K::template C<0>;  // the shared-node phase does not depend on the kind
     extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int SS = 2;  // shared copies per thread per round (single-window FP32 path)
     __shared__ ChunkDesc s_ch[KMAXB];
     __shared__ int s_kind[KMAXB];
+    __shared__ int s_pre[KMAXB + 1];  // shared copies of the workgroup's chunks before chunk k
     __shared__ int s_flag;
     const uint32_t G = gridDim.x;
     const int nmine = int(blockIdx.x) < bd.n_items ? (bd.n_items - int(blockIdx.x) + int(G) - 1) / int(G) : 0;
@@ -120,7 +122,16 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK), (Kinds<T, V>::WPE)) k_ba
         return wn;
     };
     fill(0, min(nmine, KMAXB));
-    if (threadIdx.x == 0) s_flag = bd.status[0];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s_flag = bd.status[0];
+        int acc = 0;
+        for (int k = 0; k < min(nmine, KMAXB); k++) {
+            s_pre[k] = acc;
+            acc += s_ch[k].copy_count - s_ch[k].n_interior;
+        }
+        s_pre[min(nmine, KMAXB)] = acc;
+    }
     __syncthreads();
     if (s_flag != 0) return;  // an earlier launch of this run stopped on an error
     if (threadIdx.x == 0 && bd.first_launch) bd.tstamp[2 * blockIdx.x] = uint64_t(wall_clock64());
@@ -227,14 +238,39 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK), (Kinds<T, V>::WPE)) k_ba
         // shared batch (Chunk::shared_fetch); its first round A goes out before the barrier
         bool spipe = false;
         if constexpr (K::PIPE) spipe = nmine > 0 && nmine <= KMAXB;
-        typename CS::template SharedIdx<KB> xa;
+        // the shared copies of a run of chunks of one kind, concatenated in chunk
+        // order: copy g goes to thread g % BLOCK, slot (g / BLOCK) % SS of round g / (SS BLOCK)
+        auto slots = [&](int r0, int r1, int g, int (&ls)[SS]) {
+#pragma unroll
+            for (int q = 0; q < SS; q++) {
+                const int gq = g + q * BLOCK + int(threadIdx.x);
+                ls[q] = -1;
+                if (gq < s_pre[r1]) {
+                    int lo = r0, hi = r1 - 1;  // the chunk k with s_pre[k] <= gq < s_pre[k + 1]
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (s_pre[mid] <= gq) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    ls[q] = s_ch[lo].copy_begin + s_ch[lo].n_interior + (gq - s_pre[lo]);
+                }
+            }
+        };
+        auto run_end = [&](int r0) {
+            int r1 = r0 + 1;
+            while (r1 < wn0 && s_kind[r1] == s_kind[r0]) r1++;
+            return r1;
+        };
+        typename CS::template SharedIdx<SS> xa;
+        int la[SS];
         if (nmine > 0)
             on_kind(kind0, [&](auto kc) {
                 constexpr int KC = decltype(kc)::value;
                 const StepPtrs<T> sp = kind_ptrs<T>(bd.k[KC], cur, prv, nxt, s, n);
                 if constexpr (K::PIPE) {
                     if (spipe) {
-                        CS::template shared_idx<KB>(bd.k[KC].tp, s_ch, nb0, 0, sp, xa);
+                        slots(0, run_end(0), s_pre[0], la);
+                        CS::template shared_idx_l<SS>(bd.k[KC].tp, sp, la, xa);
                         return;
                     }
                 }
@@ -265,67 +301,56 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK), (Kinds<T, V>::WPE)) k_ba
         bool shared_done = false;
         if constexpr (K::PIPE) {
             if (spipe) {
-                // items (batch of chunks, pass), in runs of one kind; per item one
-                // round: its state and partials, the next item's indices, the
-                // previous item's stores.  The first item's indices went out
+                // runs of chunks of one kind; per round of SS x BLOCK shared copies one
+                // memory round: their state and partials, the next round's indices
+                // and the previous round's stores.  The first round's indices went out
                 // before the barrier; a later run fetches its first ones on entry.
-                auto more_pass = [&](int k0, int nb, int pass) {
-                    bool more = false;
-                    for (int kb = 0; kb < nb; kb++)
-                        more |= s_ch[k0 + kb].n_interior + (pass + 1) * BLOCK < s_ch[k0 + kb].copy_count;
-                    return more;
-                };
+                SharedRegs<T, SS> rs;
                 for (int r0 = 0; r0 < wn0;) {
                     const int kind = __builtin_amdgcn_readfirstlane(s_kind[r0]);
-                    int r1 = r0 + 1;
-                    while (r1 < wn0 && s_kind[r1] == kind) r1++;
+                    const int r1 = run_end(r0);
                     on_kind(kind, [&](auto kc) {
                         constexpr int KC = decltype(kc)::value;
                         const StepPtrs<T> sp = kind_ptrs<T>(bd.k[KC], cur, prv, nxt, s, n);
                         const DevTopo &tp = bd.k[KC].tp;
-                        int ck0 = r0, cnb = batch_len(r0, wn0), cpass = 0;
-                        if (r0 > 0) CS::template shared_idx<KB>(tp, s_ch + ck0, cnb, 0, sp, xa);
-                        typename CS::template SharedIdx<KB> xb;
-                        typename CS::template SharedPart<KB> pt;
-                        typename CS::template SharedHeld<KB> hs;
+                        const int g1 = s_pre[r1];
+                        if (r0 > 0) {
+                            slots(r0, r1, s_pre[r0], la);
+                            CS::template shared_idx_l<SS>(tp, sp, la, xa);
+                        }
+                        typename CS::template SharedIdx<SS> xb;
+                        typename CS::template SharedPart<SS> pt;
+                        typename CS::template SharedHeld<SS> hs;
 #pragma unroll
-                        for (int kb = 0; kb < KB; kb++) hs.l[kb] = -1;
-                        for (;;) {
-                            CS::template shared_fetch<KB>(s_ch + ck0, cnb, cpass, sp, xa, sr, pt);
-                            int nk0 = ck0, nnb = cnb, npass = cpass;
-                            bool live = true;
-                            if (more_pass(ck0, cnb, cpass)) {
-                                npass++;
-                            } else {
-                                nk0 += cnb;
-                                live = nk0 < r1;
-                                if (live) {
-                                    nnb = batch_len(nk0, wn0);
-                                    npass = 0;
-                                }
+                        for (int q = 0; q < SS; q++) hs.l[q] = -1;
+                        for (int g = s_pre[r0]; g < g1; g += SS * BLOCK) {
+                            CS::template shared_fetch_l<SS>(sp, la, xa, rs, pt);
+                            const bool live = g + SS * BLOCK < g1;
+                            int lb[SS];
+                            if (live) {
+                                slots(r0, r1, g + SS * BLOCK, lb);
+                                CS::template shared_idx_l<SS>(tp, sp, lb, xb);
                             }
-                            if (live) CS::template shared_idx<KB>(tp, s_ch + nk0, nnb, npass, sp, xb);
 #pragma unroll
-                            for (int kb = 0; kb < KB; kb++)
-                                if (hs.l[kb] >= 0)
+                            for (int q = 0; q < SS; q++)
+                                if (hs.l[q] >= 0)
 #pragma unroll
-                                    for (int k = 0; k < 3; k++) sp.un[k][hs.l[kb]] = hs.v[kb][k];
+                                    for (int k = 0; k < 3; k++) sp.un[k][hs.l[q]] = hs.v[q][k];
                             __builtin_amdgcn_s_waitcnt(0);
                             __builtin_amdgcn_sched_barrier(0);
                             const bool was_bad = po.bad != 0;
-                            CS::template shared_values<KB>(sr, pt, sp, po, hs);
+                            CS::template shared_values<SS>(rs, pt, sp, po, hs);
                             if (!was_bad && po.bad) late_kind = kind;
                             if (!live) break;
                             xa = xb;
-                            ck0 = nk0;
-                            cnb = nnb;
-                            cpass = npass;
+#pragma unroll
+                            for (int q = 0; q < SS; q++) la[q] = lb[q];
                         }
 #pragma unroll
-                        for (int kb = 0; kb < KB; kb++)
-                            if (hs.l[kb] >= 0)
+                        for (int q = 0; q < SS; q++)
+                            if (hs.l[q] >= 0)
 #pragma unroll
-                                for (int k = 0; k < 3; k++) sp.un[k][hs.l[kb]] = hs.v[kb][k];
+                                for (int k = 0; k < 3; k++) sp.un[k][hs.l[q]] = hs.v[q][k];
                     });
                     r0 = r1;
                 }

@@ -1198,6 +1198,53 @@ struct Chunk {
             }
         }
     }
+    // the same two loads by copy index (l < 0: no copy in this slot)
+    template <int KB>
+    __device__ static void shared_idx_l(const DevTopo &tp, const StepPtrs<T> &sp, const int (&ls)[KB], SharedIdx<KB> &x) {
+#pragma unroll
+        for (int kb = 0; kb < KB; kb++) {
+            x.fl[kb] = 0u;
+            x.pb[kb] = 0;
+            if (ls[kb] >= 0) {
+                x.fl[kb] = sp.flags[ls[kb]];
+                x.pb[kb] = tp.pidx[ls[kb]];
+            }
+        }
+    }
+    // state and partials by copy index; the load values only for loaded copies
+    template <int KB>
+    __device__ static void shared_fetch_l(const StepPtrs<T> &sp, const int (&ls)[KB], const SharedIdx<KB> &x,
+                                          SharedRegs<T, KB> &r, SharedPart<KB> &pt) {
+        static_assert(PC, "batch path");
+#pragma unroll
+        for (int kb = 0; kb < KB; kb++) {
+            r.ok[kb] = ls[kb] >= 0;
+            if (ls[kb] >= 0) {
+                const int l = ls[kb];
+                r.li[kb] = l;
+                r.fl[kb] = x.fl[kb];
+                r.pb[kb] = x.pb[kb];
+                r.A[kb] = sp.acoef[l];
+                r.bp[kb] = sp.bpc[l];
+#pragma unroll
+                for (int k = 0; k < 3; k++) {
+                    r.uc[kb][k] = sp.uc[k][l];
+                    r.up[kb][k] = sp.up[k][l];
+                    r.rv[kb][k] = T(0);
+                }
+                r.rr[kb] = T(0);
+                if ((x.fl[kb] & FLAG_RU) && sp.ru[0]) {
+#pragma unroll
+                    for (int k = 0; k < 3; k++) r.rv[kb][k] = sp.ru[k][l];
+                    if (sp.rrate) r.rr[kb] = sp.rrate[l];
+                }
+                const int cnt = (x.fl[kb] >> FLAG_NCOPY_SHIFT) & 255u;
+#pragma unroll
+                for (int q = 0; q < SUNR; q++)
+                    if (q < cnt) get_partial(sp.pp, x.pb[kb] + q, pt.px[kb][q]);
+            }
+        }
+    }
     template <int KB>
     __device__ static void shared_fetch(const ChunkDesc *chs, int nb, int pass, const StepPtrs<T> &sp,
                                         const SharedIdx<KB> &x, SharedRegs<T, KB> &r, SharedPart<KB> &pt) {
