@@ -633,11 +633,41 @@ struct Chunk {
     // LDS of the average-nodal-pressure step: a fourth slot plane carries p_n
     static constexpr size_t LDS_ANP = LDS + size_t(NE) * CMAX * sizeof(T);
 
+    // FP32 batches read the interleaved element copy (elem4): NP + NE / 2 words
+    // per element in 16-byte loads; the slot positions stay packed two to a
+    // word in wp[j][2i] until they are used (slot(), after the chunk's wait)
+    static constexpr bool PK = PC && !PF && sizeof(T) == 4;
+    __device__ static int slot(const ElemRegs &er, int j, int a) {
+        if constexpr (PK) return int((uint32_t(er.wp[j][a & ~1]) >> (16 * (a & 1))) & 0xffffu);
+        else return er.wp[j][a];
+    }
+
     // Element planes and slot positions (register path).  Lanes past the
     // chunk's end load its last element again: the loads are unconditional, so
     // no lane keeps an older value and nothing waits on them before use.
     __device__ static void load_elem(const DevTopo &tp, const ChunkDesc &ch, ElemRegs &er, int j) {
-        if constexpr (!PF) {
+        if constexpr (PK) {
+            constexpr int D = NP + NE / 2, G = D / 4, R = D % 4;
+            const int64_t es = tp.estride;
+            const int64_t e = ch.elem_begin + min(int(threadIdx.x) + j * BLOCK, ch.elem_count - 1);
+            const uint4 *__restrict__ g4 = static_cast<const uint4 *>(tp.elem4);
+            const uint32_t *__restrict__ g1 = static_cast<const uint32_t *>(tp.elem4) + 4 * G * es;
+            uint32_t w[D];
+#pragma unroll
+            for (int g = 0; g < G; g++) {
+                const uint4 v = g4[g * es + e];
+                w[4 * g] = v.x;
+                w[4 * g + 1] = v.y;
+                w[4 * g + 2] = v.z;
+                w[4 * g + 3] = v.w;
+            }
+#pragma unroll
+            for (int r = 0; r < R; r++) w[4 * G + r] = g1[r * es + e];
+#pragma unroll
+            for (int q = 0; q < NP; q++) er.cst[j][q] = __uint_as_float(w[q]);
+#pragma unroll
+            for (int a = 0; a < NE; a += 2) er.wp[j][a] = int(w[NP + a / 2]);
+        } else if constexpr (!PF) {
             const T *__restrict__ ep = static_cast<const T *>(tp.elem);
             const int64_t es = tp.estride;
             const int e = min(int(threadIdx.x) + j * BLOCK, ch.elem_count - 1);
@@ -749,9 +779,9 @@ struct Chunk {
                 T u[NE][3], F[NE][3];
 #pragma unroll
                 for (int a = 0; a < NE; a++) {
-                    u[a][0] = lx[er.wp[j][a]];
-                    u[a][1] = ly[er.wp[j][a]];
-                    u[a][2] = lz[er.wp[j][a]];
+                    u[a][0] = lx[slot(er, j, a)];
+                    u[a][1] = ly[slot(er, j, a)];
+                    u[a][2] = lz[slot(er, j, a)];
                 }
                 T J;
                 if constexpr (ANPM) {
@@ -764,7 +794,7 @@ struct Chunk {
                     if (sp.pn) {
                         T pb = 0;
 #pragma unroll
-                        for (int a = 0; a < NE; a++) pb += lz[NE * CMAX + er.wp[j][a]];
+                        for (int a = 0; a < NE; a++) pb += lz[NE * CMAX + slot(er, j, a)];
                         cst[Planes<NE, MODEL>::KAV] *= pb * T(1.0 / NE);
                     }
                     J = element_force<T, NE, MODEL>(cst, u, F);
@@ -776,9 +806,9 @@ struct Chunk {
                 const bool ok = J > T(0);
 #pragma unroll
                 for (int a = 0; a < NE; a++) {
-                    lx[er.wp[j][a]] = ok ? F[a][0] : T(0);
-                    ly[er.wp[j][a]] = ok ? F[a][1] : T(0);
-                    lz[er.wp[j][a]] = ok ? F[a][2] : T(0);
+                    lx[slot(er, j, a)] = ok ? F[a][0] : T(0);
+                    ly[slot(er, j, a)] = ok ? F[a][1] : T(0);
+                    lz[slot(er, j, a)] = ok ? F[a][2] : T(0);
                 }
                 if (!isfinite(J)) {
                     po.bad = DJ_ERR_NONFINITE;
@@ -1118,13 +1148,13 @@ struct Chunk {
                 T u[NE][3];
 #pragma unroll
                 for (int a = 0; a < NE; a++) {
-                    u[a][0] = lx[er.wp[j][a]];
-                    u[a][1] = ly[er.wp[j][a]];
-                    u[a][2] = lz[er.wp[j][a]];
+                    u[a][0] = lx[slot(er, j, a)];
+                    u[a][1] = ly[slot(er, j, a)];
+                    u[a][2] = lz[slot(er, j, a)];
                 }
                 const T jw = er.cst[j][Planes<NE, MODEL>::KAV] * T(1.0 / NE) * element_jm1<T, NE, MODEL>(er.cst[j], u);
 #pragma unroll
-                for (int a = 0; a < NE; a++) lx[er.wp[j][a]] = jw;
+                for (int a = 0; a < NE; a++) lx[slot(er, j, a)] = jw;
             }
         }
         __syncthreads();

@@ -99,6 +99,11 @@ struct DevTopo {
     const int32_t *cnode = nullptr;      // caller node index of each copy
     int32_t n_part = 0;                  // partial-force entries (one per shared copy)
     const void *elem = nullptr;          // element planes (context precision)
+    // FP32 batches: the same planes and slot positions interleaved per element,
+    // D = NP + NE / 2 words (two positions per word): words 4g .. 4g + 3 of
+    // element e at 16-byte entry g * estride + e (g < D / 4), the last D % 4
+    // words as single planes after them (word 4 (D / 4) + r at r * estride + e)
+    const void *elem4 = nullptr;
     int64_t estride = 0;
     const void *acoef = nullptr;         // per copy A_i = 2 dt^2 / ((2 + alpha dt) m_i)
     const void *bpc = nullptr;           // batches: per copy B' = (2 - alpha dt) / (2 + alpha dt)
@@ -237,6 +242,8 @@ hipError_t launch_precompute(Ctx &c, const double *dX, const int32_t *dconn, con
                              double *d_dtmin, int32_t *d_bad, hipStream_t s);
 // c2: per internal node 2 dt^2 / (2 + alpha dt) of its instance; bp: per node
 // B' (written per copy to c.d_bpc when that is allocated)
+// FP32 batches: interleave the element planes and slot positions into elem4
+hipError_t launch_pack_elem4(Ctx &c, void *dst, hipStream_t s);
 hipError_t launch_mass_acoef(Ctx &c, const int32_t *d_ne_off, const int32_t *d_ne_list, const double *d_c2,
                              const double *d_bp, hipStream_t s);
 hipError_t launch_forces(Ctx &c, const void *u, void *f, hipStream_t s);

@@ -340,6 +340,36 @@ hipError_t launch_precompute(Ctx &c, const double *dX, const int32_t *dconn, con
     return hipGetLastError();
 }
 
+// one thread per element position (padding included): word d of the element
+// goes to its 16-byte group or, past the last full group, to its own plane
+__global__ void k_pack_elem4(const uint32_t *__restrict__ planes, const uint16_t *__restrict__ wpos, int np, int ne,
+                             int64_t es, uint32_t *__restrict__ dst) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= es) return;
+    const int D = np + ne / 2, G = D / 4;
+    for (int d = 0; d < D; d++) {
+        uint32_t w;
+        if (d < np) {
+            w = planes[d * es + e];
+        } else {
+            const int a = 2 * (d - np);
+            w = uint32_t(wpos[a * es + e]) | (uint32_t(wpos[(a + 1) * es + e]) << 16);
+        }
+        if (d < 4 * G) dst[((d / 4) * es + e) * 4 + (d % 4)] = w;
+        else dst[4 * G * es + (d - 4 * G) * es + e] = w;
+    }
+}
+
+hipError_t launch_pack_elem4(Ctx &c, void *dst, hipStream_t s) {
+    if (c.prec != DJ_FP32) return hipErrorInvalidValue;
+    const int B = 256;
+    const int64_t es = c.topo.estride;
+    hipLaunchKernelGGL(k_pack_elem4, dim3(unsigned((es + B - 1) / B)), dim3(B), 0, s,
+                       static_cast<const uint32_t *>(c.d_elem), c.topo.wpos, n_planes(c.ne, c.model), c.ne, es,
+                       static_cast<uint32_t *>(dst));
+    return hipGetLastError();
+}
+
 hipError_t launch_mass_acoef(Ctx &c, const int32_t *d_ne_off, const int32_t *d_ne_list, const double *d_c2,
                              const double *d_bp, hipStream_t s) {
     const int B = 256;
