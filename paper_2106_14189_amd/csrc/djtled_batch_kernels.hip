@@ -62,11 +62,12 @@ __device__ __forceinline__ StepPtrs<T> kind_ptrs(const BatchKind &kd, int cur, i
     const T *uc = cur == 0 ? u0 : (cur == 1 ? u1 : u2);
     const T *up = prv == 0 ? u0 : (prv == 1 ? u1 : u2);
     T *un = const_cast<T *>(nxt == 0 ? u0 : (nxt == 1 ? u1 : u2));
+    // copy-major state: component k of copy l at 3 l + k (ld_u3 / st_u3 read p[0])
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-        sp.uc[k] = uc + k * L;
-        sp.up[k] = up + k * L;
-        sp.un[k] = un + k * L;
+        sp.uc[k] = uc + k;
+        sp.up[k] = up + k;
+        sp.un[k] = un + k;
         sp.ru[k] = ru ? ru + k * L : nullptr;
     }
     for (int k = 0; k < 3; k++) sp.pp[k] = static_cast<T *>(kd.part) + ((s & 1) * 3 + k) * int64_t(kd.tp.n_part);
@@ -334,8 +335,7 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK), (Kinds<T, V>::WPE)) k_ba
 #pragma unroll
                             for (int q = 0; q < SS; q++)
                                 if (hs.l[q] >= 0)
-#pragma unroll
-                                    for (int k = 0; k < 3; k++) sp.un[k][hs.l[q]] = hs.v[q][k];
+                                    st_u3<true>(sp.un, hs.l[q], hs.v[q]);
                             __builtin_amdgcn_s_waitcnt(0);
                             __builtin_amdgcn_sched_barrier(0);
                             const bool was_bad = po.bad != 0;
@@ -349,8 +349,7 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK), (Kinds<T, V>::WPE)) k_ba
 #pragma unroll
                         for (int q = 0; q < SS; q++)
                             if (hs.l[q] >= 0)
-#pragma unroll
-                                for (int k = 0; k < 3; k++) sp.un[k][hs.l[q]] = hs.v[q][k];
+                                st_u3<true>(sp.un, hs.l[q], hs.v[q]);
                     });
                     r0 = r1;
                 }
@@ -436,9 +435,9 @@ __global__ void k_gather_canon(const uint32_t *__restrict__ flags, const int32_t
     if (l >= n_copies || !(flags[l] & FLAG_CANON)) return;
     const int nd = cnode[l];
 #pragma unroll
-    for (int k = 0; k < 3; k++) {
-        oc[3 * int64_t(nd) + k] = uc[int64_t(k) * n_copies + l];
-        op[3 * int64_t(nd) + k] = up[int64_t(k) * n_copies + l];
+    for (int k = 0; k < 3; k++) {  // copy-major state
+        oc[3 * int64_t(nd) + k] = uc[3 * int64_t(l) + k];
+        op[3 * int64_t(nd) + k] = up[3 * int64_t(l) + k];
     }
 }
 
@@ -532,11 +531,11 @@ hipError_t launch_scatter_state(const BatchKind &kd, int prec, int cur, const vo
     const int L = kd.tp.n_copies, B = 256;
     const int prv = (cur + 2) % 3;
     if (prec == DJ_FP32)
-        hipLaunchKernelGGL(k_scatter_in<float>, dim3((L + B - 1) / B), dim3(B), 0, s, kd.tp.cnode, L,
+        hipLaunchKernelGGL((k_scatter_in<float, true>), dim3((L + B - 1) / B), dim3(B), 0, s, kd.tp.cnode, L,
                            static_cast<const float *>(ic), static_cast<const float *>(ip),
                            static_cast<float *>(kd.ubuf[cur]), static_cast<float *>(kd.ubuf[prv]));
     else
-        hipLaunchKernelGGL(k_scatter_in<double>, dim3((L + B - 1) / B), dim3(B), 0, s, kd.tp.cnode, L,
+        hipLaunchKernelGGL((k_scatter_in<double, true>), dim3((L + B - 1) / B), dim3(B), 0, s, kd.tp.cnode, L,
                            static_cast<const double *>(ic), static_cast<const double *>(ip),
                            static_cast<double *>(kd.ubuf[cur]), static_cast<double *>(kd.ubuf[prv]));
     return hipGetLastError();

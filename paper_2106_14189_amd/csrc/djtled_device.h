@@ -134,6 +134,33 @@ __device__ __forceinline__ void get_partial(T *const (&pp)[3], int q, T (&f)[3])
     for (int k = 0; k < 3; k++) f[k] = ld_dev(&pp[k][q]);
 }
 
+// Displacement of copy l in one of the rotating state buffers.  Single meshes
+// keep three planes (p[k] = plane k); batches keep the three components of a
+// copy together (p[0] = buffer start, component k of copy l at 3 l + k), so
+// that one 12-byte access moves a copy's vector.
+template <bool AOS, typename T>
+__device__ __forceinline__ void ld_u3(const T *const (&p)[3], int l, T (&v)[3]) {
+    if constexpr (AOS) {
+        const T *q = p[0] + 3 * int64_t(l);
+#pragma unroll
+        for (int k = 0; k < 3; k++) v[k] = q[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3; k++) v[k] = p[k][l];
+    }
+}
+template <bool AOS, typename T>
+__device__ __forceinline__ void st_u3(T *const (&p)[3], int l, const T (&v)[3]) {
+    if constexpr (AOS) {
+        T *q = p[0] + 3 * int64_t(l);
+#pragma unroll
+        for (int k = 0; k < 3; k++) q[k] = v[k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < 3; k++) p[k][l] = v[k];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // element force (register-resident).  cst: the element's planes.  u: nodal
 // displacements.  F: nodal forces.  Returns J.
@@ -530,14 +557,13 @@ __device__ __forceinline__ void node_value(int l, uint32_t fl, const T (&f)[3], 
         po.bad_elem = -2 - l;  // node-level error: the copy
     }
 }
-template <typename T>
+template <typename T, bool AOS = false>
 __device__ __forceinline__ void node_update(int l, uint32_t fl, const T (&f)[3], const T (&uc)[3], const T (&up)[3],
                                             T A, T bp, T sv, const T (&rv)[3], const StepPtrs<T> &sp,
                                             PhaseOut &po) {
     T un[3];
     node_value<T>(l, fl, f, uc, up, A, bp, sv, rv, sp, po, un);
-#pragma unroll
-    for (int k = 0; k < 3; k++) sp.un[k][l] = un[k];
+    st_u3<AOS>(sp.un, l, un);
 }
 
 // ---------------------------------------------------------------------------
@@ -637,6 +663,7 @@ struct Chunk {
     // per element in 16-byte loads; the slot positions stay packed two to a
     // word in wp[j][2i] until they are used (slot(), after the chunk's wait)
     static constexpr bool PK = PC && !PF && sizeof(T) == 4;
+    static constexpr bool AOS = PC;  // batches: copy displacements as 3-vectors (ld_u3)
     __device__ static int slot(const ElemRegs &er, int j, int a) {
         if constexpr (PK) return int((uint32_t(er.wp[j][a & ~1]) >> (16 * (a & 1))) & 0xffffu);
         else return er.wp[j][a];
@@ -696,15 +723,13 @@ struct Chunk {
             const int l = ch.copy_begin + min(i, ch.copy_count - 1);
             c.cr[m] = tp.crange[l];
             c.fl[m] = sp.flags[l];
-#pragma unroll
-            for (int k = 0; k < 3; k++) c.ux[m][k] = sp.uc[k][l];
+            ld_u3<AOS>(sp.uc, l, c.ux[m]);
             if constexpr (ANPM) c.pn[m] = sp.pn ? sp.pn[l] : T(0);
             if (i < ch.copy_count) {
                 if (i >= ch.n_interior) {
                     c.pb[m] = tp.pidx[l];
                 } else if (MODE == 1) {
-#pragma unroll
-                    for (int k = 0; k < 3; k++) c.upv[m][k] = sp.up[k][l];
+                    ld_u3<AOS>(sp.up, l, c.upv[m]);
                     c.A[m] = sp.acoef[l];
                     if constexpr (PC) c.Bp[m] = sp.bpc[l];
                 }
@@ -907,10 +932,10 @@ struct Chunk {
                     sp.fout[3 * nd + 1] = f[1];
                     sp.fout[3 * nd + 2] = f[2];
                 } else if constexpr (PC) {
-                    node_update<T>(l, c.fl[m], f, c.ux[m], c.upv[m], c.A[m], c.Bp[m], ramp_rate(c.rr[m], sp.n1), c.rv[m],
+                    node_update<T, AOS>(l, c.fl[m], f, c.ux[m], c.upv[m], c.A[m], c.Bp[m], ramp_rate(c.rr[m], sp.n1), c.rv[m],
                                    sp, po);
                 } else {
-                    node_update<T>(l, c.fl[m], f, c.ux[m], c.upv[m], c.A[m], sp.bprime, sp.sval, c.rv[m], sp, po);
+                    node_update<T, AOS>(l, c.fl[m], f, c.ux[m], c.upv[m], c.A[m], sp.bprime, sp.sval, c.rv[m], sp, po);
                 }
             }
         }
@@ -942,8 +967,7 @@ struct Chunk {
             if (h.q[m] >= 0) {
                 put_partial(sp.pp, h.q[m], h.v[m]);
             } else {
-#pragma unroll
-                for (int k = 0; k < 3; k++) sp.un[k][h.l[m]] = h.v[m][k];
+                st_u3<AOS>(sp.un, h.l[m], h.v[m]);
             }
         }
     }
@@ -1041,12 +1065,10 @@ struct Chunk {
                     r.pb[kb] = tp.pidx[l];
                     if (MODE == 1) {
                         r.A[kb] = sp.acoef[l];
+                        ld_u3<AOS>(sp.uc, l, r.uc[kb]);
+                        ld_u3<AOS>(sp.up, l, r.up[kb]);
 #pragma unroll
-                        for (int k = 0; k < 3; k++) {
-                            r.uc[kb][k] = sp.uc[k][l];
-                            r.up[kb][k] = sp.up[k][l];
-                            r.rv[kb][k] = sp.ru[0] ? sp.ru[k][l] : T(0);
-                        }
+                        for (int k = 0; k < 3; k++) r.rv[kb][k] = sp.ru[0] ? sp.ru[k][l] : T(0);
                         if constexpr (PC) {
                             r.bp[kb] = sp.bpc[l];
                             r.rr[kb] = sp.rrate ? sp.rrate[l] : T(0);
@@ -1102,10 +1124,10 @@ struct Chunk {
 #pragma unroll
                     for (int k = 0; k < 3; k++) r.rv[kb][k] = T(0);
                 if constexpr (PC)
-                    node_update<T>(l, r.fl[kb], f, r.uc[kb], r.up[kb], r.A[kb], r.bp[kb],
+                    node_update<T, AOS>(l, r.fl[kb], f, r.uc[kb], r.up[kb], r.A[kb], r.bp[kb],
                                    ramp_rate((r.fl[kb] & FLAG_RU) ? r.rr[kb] : T(0), sp.n1), r.rv[kb], sp, po);
                 else
-                    node_update<T>(l, r.fl[kb], f, r.uc[kb], r.up[kb], r.A[kb], sp.bprime, sp.sval, r.rv[kb], sp,
+                    node_update<T, AOS>(l, r.fl[kb], f, r.uc[kb], r.up[kb], r.A[kb], sp.bprime, sp.sval, r.rv[kb], sp,
                                    po);
             }
         }
@@ -1256,12 +1278,10 @@ struct Chunk {
                 r.pb[kb] = x.pb[kb];
                 r.A[kb] = sp.acoef[l];
                 r.bp[kb] = sp.bpc[l];
+                ld_u3<AOS>(sp.uc, l, r.uc[kb]);
+                ld_u3<AOS>(sp.up, l, r.up[kb]);
 #pragma unroll
-                for (int k = 0; k < 3; k++) {
-                    r.uc[kb][k] = sp.uc[k][l];
-                    r.up[kb][k] = sp.up[k][l];
-                    r.rv[kb][k] = T(0);
-                }
+                for (int k = 0; k < 3; k++) r.rv[kb][k] = T(0);
                 r.rr[kb] = T(0);
                 if ((x.fl[kb] & FLAG_RU) && sp.ru[0]) {
 #pragma unroll
@@ -1292,12 +1312,10 @@ struct Chunk {
                     r.fl[kb] = x.fl[kb];
                     r.pb[kb] = x.pb[kb];
                     r.A[kb] = sp.acoef[l];
+                    ld_u3<AOS>(sp.uc, l, r.uc[kb]);
+                    ld_u3<AOS>(sp.up, l, r.up[kb]);
 #pragma unroll
-                    for (int k = 0; k < 3; k++) {
-                        r.uc[kb][k] = sp.uc[k][l];
-                        r.up[kb][k] = sp.up[k][l];
-                        r.rv[kb][k] = sp.ru[0] ? sp.ru[k][l] : T(0);
-                    }
+                    for (int k = 0; k < 3; k++) r.rv[kb][k] = sp.ru[0] ? sp.ru[k][l] : T(0);
                     r.bp[kb] = sp.bpc[l];
                     r.rr[kb] = sp.rrate ? sp.rrate[l] : T(0);
                     const int cnt = (x.fl[kb] >> FLAG_NCOPY_SHIFT) & 255u;
@@ -1462,8 +1480,9 @@ __device__ __forceinline__ bool grid_barrier(uint32_t *sync, uint32_t nblocks, u
 // ---------------------------------------------------------------------------
 // Kernels
 // ---------------------------------------------------------------------------
-// copies <- caller arrays (both state vectors at once when src1 != null)
-template <typename T>
+// copies <- caller arrays (both state vectors at once when src1 != null);
+// AOS: the batches' copy-major state layout
+template <typename T, bool AOS = false>
 __global__ void k_scatter_in(const int32_t *__restrict__ cnode, int n_copies, const T *__restrict__ src0,
                              const T *__restrict__ src1, T *__restrict__ d0, T *__restrict__ d1) {
     const int l = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1471,8 +1490,9 @@ __global__ void k_scatter_in(const int32_t *__restrict__ cnode, int n_copies, co
     const int n = cnode[l];
 #pragma unroll
     for (int k = 0; k < 3; k++) {
-        d0[int64_t(k) * n_copies + l] = src0[3 * n + k];
-        if (src1) d1[int64_t(k) * n_copies + l] = src1[3 * n + k];
+        const int64_t o = AOS ? 3 * int64_t(l) + k : int64_t(k) * n_copies + l;
+        d0[o] = src0[3 * n + k];
+        if (src1) d1[o] = src1[3 * n + k];
     }
 }
 
