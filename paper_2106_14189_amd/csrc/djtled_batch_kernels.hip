@@ -70,7 +70,8 @@ __device__ __forceinline__ StepPtrs<T> kind_ptrs(const BatchKind &kd, int cur, i
         sp.un[k] = un + k;
         sp.ru[k] = ru ? ru + k * L : nullptr;
     }
-    for (int k = 0; k < 3; k++) sp.pp[k] = static_cast<T *>(kd.part) + ((s & 1) * 3 + k) * int64_t(kd.tp.n_part);
+    // partial entries entry-major per parity (put_partial3 / get_partial3 read pp[0])
+    for (int k = 0; k < 3; k++) sp.pp[k] = static_cast<T *>(kd.part) + (s & 1) * 3 * int64_t(kd.tp.n_part) + k;
     sp.flags = kd.flags;
     sp.acoef = static_cast<const T *>(kd.tp.acoef);
     sp.bprime = T(0);

@@ -118,11 +118,15 @@ __device__ __forceinline__ T ld_dev(const T *p) {
     return __hip_atomic_load(const_cast<T *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Partial node forces: three planes (x, y, z) over the partial entries of
-// one step parity; each component is published and read with a device-scope
-// access.  Entries of neighbouring nodes are adjacent in each plane, so a
-// wave's stores of one component fall on few cache lines.  (One 16-byte entry
-// per partial, read as two 64-bit words, measured no faster.)
+// cache-policy bit of a buffer access for device-scope coherence (gfx950: SC1)
+constexpr int CPOL_SC1 = 16;
+
+// Partial node forces of single meshes: three planes (x, y, z) over the
+// partial entries of one step parity; each component is published and read
+// with a device-scope access.  Entries of neighbouring nodes are adjacent in
+// each plane, so a wave's stores of one component fall on few cache lines.
+// (One 16-byte entry per partial, read as two 64-bit words, measured no
+// faster.)
 template <typename T>
 __device__ __forceinline__ void put_partial(T *const (&pp)[3], int q, const T (&f)[3]) {
 #pragma unroll
@@ -132,6 +136,44 @@ template <typename T>
 __device__ __forceinline__ void get_partial(T *const (&pp)[3], int q, T (&f)[3]) {
 #pragma unroll
     for (int k = 0; k < 3; k++) f[k] = ld_dev(&pp[k][q]);
+}
+
+// Batches keep a partial entry's three components together (pp[0] = the
+// parity's first entry, component k of entry q at 3 q + k).  In FP32 one
+// 12-byte buffer access with the same cache policy as the device-scope
+// relaxed atomics (sc1: through to the coherence point) moves an entry.
+template <bool AOS, typename T>
+__device__ __forceinline__ void put_partial3(T *const (&pp)[3], int q, const T (&f)[3]) {
+    if constexpr (AOS && sizeof(T) == 4) {
+        typedef float f3v __attribute__((ext_vector_type(3)));
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(pp[0], 0, 0xffffffff, 0x00020000);
+        f3v v;
+        v.x = f[0];
+        v.y = f[1];
+        v.z = f[2];
+        __builtin_amdgcn_raw_buffer_store_b96(v, r, 12 * q, 0, CPOL_SC1);
+    } else if constexpr (AOS) {
+#pragma unroll
+        for (int k = 0; k < 3; k++) st_dev(&pp[0][3 * int64_t(q) + k], f[k]);
+    } else {
+        put_partial(pp, q, f);
+    }
+}
+template <bool AOS, typename T>
+__device__ __forceinline__ void get_partial3(T *const (&pp)[3], int q, T (&f)[3]) {
+    if constexpr (AOS && sizeof(T) == 4) {
+        typedef float f3v __attribute__((ext_vector_type(3)));
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(pp[0], 0, 0xffffffff, 0x00020000);
+        const f3v v = __builtin_amdgcn_raw_buffer_load_b96(r, 12 * q, 0, CPOL_SC1);
+        f[0] = v.x;
+        f[1] = v.y;
+        f[2] = v.z;
+    } else if constexpr (AOS) {
+#pragma unroll
+        for (int k = 0; k < 3; k++) f[k] = ld_dev(&pp[0][3 * int64_t(q) + k]);
+    } else {
+        get_partial(pp, q, f);
+    }
 }
 
 // Displacement of copy l in one of the rotating state buffers.  Single meshes
@@ -921,7 +963,7 @@ struct Chunk {
                 const int l = ch.copy_begin + i;
                 if (i >= ch.n_interior) {
                     const int q = c.pb[m] + int((c.fl[m] >> FLAG_RANK_SHIFT) & 255u);
-                    put_partial(sp.pp, q, f);
+                    put_partial3<AOS>(sp.pp, q, f);
                     if (!(isfinite(f[0]) && isfinite(f[1]) && isfinite(f[2])) && po.bad == 0) {
                         po.bad = DJ_ERR_NONFINITE;
                         po.bad_elem = -2 - l;
@@ -965,7 +1007,7 @@ struct Chunk {
         for (int m = 0; m < MC; m++) {
             if (h.l[m] < 0) continue;
             if (h.q[m] >= 0) {
-                put_partial(sp.pp, h.q[m], h.v[m]);
+                put_partial3<AOS>(sp.pp, h.q[m], h.v[m]);
             } else {
                 st_u3<AOS>(sp.un, h.l[m], h.v[m]);
             }
@@ -1092,7 +1134,7 @@ struct Chunk {
                 const int cnt = (r.fl[kb] >> FLAG_NCOPY_SHIFT) & 255u;
 #pragma unroll
                 for (int q = 0; q < UNR; q++)
-                    if (q < cnt) get_partial(sp.pp, r.pb[kb] + q, px[kb][q]);
+                    if (q < cnt) get_partial3<AOS>(sp.pp, r.pb[kb] + q, px[kb][q]);
             }
         }
 #pragma unroll
@@ -1107,7 +1149,7 @@ struct Chunk {
                     for (int k = 0; k < 3; k++) f[k] += px[kb][q][k];
             for (int q = UNR; q < cnt; q++) {
                 T g[3];
-                get_partial(sp.pp, r.pb[kb] + q, g);
+                get_partial3<AOS>(sp.pp, r.pb[kb] + q, g);
 #pragma unroll
                 for (int k = 0; k < 3; k++) f[k] += g[k];
             }
@@ -1291,7 +1333,7 @@ struct Chunk {
                 const int cnt = (x.fl[kb] >> FLAG_NCOPY_SHIFT) & 255u;
 #pragma unroll
                 for (int q = 0; q < SUNR; q++)
-                    if (q < cnt) get_partial(sp.pp, x.pb[kb] + q, pt.px[kb][q]);
+                    if (q < cnt) get_partial3<AOS>(sp.pp, x.pb[kb] + q, pt.px[kb][q]);
             }
         }
     }
@@ -1321,7 +1363,7 @@ struct Chunk {
                     const int cnt = (x.fl[kb] >> FLAG_NCOPY_SHIFT) & 255u;
 #pragma unroll
                     for (int q = 0; q < SUNR; q++)
-                        if (q < cnt) get_partial(sp.pp, x.pb[kb] + q, pt.px[kb][q]);
+                        if (q < cnt) get_partial3<AOS>(sp.pp, x.pb[kb] + q, pt.px[kb][q]);
                 }
             }
         }
@@ -1343,7 +1385,7 @@ struct Chunk {
                     for (int k = 0; k < 3; k++) f[k] += pt.px[kb][q][k];
             for (int q = SUNR; q < cnt; q++) {  // nodes in more than SUNR chunks
                 T g[3];
-                get_partial(sp.pp, r.pb[kb] + q, g);
+                get_partial3<AOS>(sp.pp, r.pb[kb] + q, g);
 #pragma unroll
                 for (int k = 0; k < 3; k++) f[k] += g[k];
             }
