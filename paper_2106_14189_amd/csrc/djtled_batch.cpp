@@ -30,6 +30,7 @@ struct Batch {
     std::vector<int> members[4];                   // instances of each kind, by position
     std::vector<std::vector<int>> inst_wgs;        // workgroups holding chunks of each instance
     std::vector<void *> allocs;
+    void *d_ab[4] = {}, *d_rq[4] = {};  // per kind: (A, B') pairs and (load, rate) quads of the copies
     int32_t *d_work = nullptr;
     uint32_t *d_bar = nullptr;
     int32_t *d_status = nullptr;
@@ -234,6 +235,17 @@ int build_batch(Batch &b, const std::vector<int> &sel, const djtled_mesh *meshes
         rc = make_loadset(*c, &uld, rate.data(), &ls);
         if (rc != DJ_OK) return rc;
         b.kls[k] = ls;
+        {
+            const size_t L = size_t(c->topo.n_copies), tsz = b.prec == DJ_FP32 ? 4 : 8;
+            DJ_HIP(hipMalloc(&b.d_ab[k], std::max<size_t>(L, 1) * 2 * tsz));
+            b.allocs.push_back(b.d_ab[k]);
+            if (ls->d_ru) {
+                DJ_HIP(hipMalloc(&b.d_rq[k], std::max<size_t>(L, 1) * 4 * tsz));
+                b.allocs.push_back(b.d_rq[k]);
+            }
+            DJ_HIP(launch_pack_copy_pairs(b.prec, int(L), c->d_acoef, c->d_bpc, ls->d_ru, ls->d_rate, b.d_ab[k],
+                                          b.d_rq[k], nullptr));
+        }
         const size_t ts = b.prec == DJ_FP32 ? 4 : 8;
         for (int q = 0; q < 3; q++) DJ_HIP(hipMemset(c->d_ubuf[q], 0, size_t(3) * c->topo.n_copies * ts));
         b.n_elems += E;
@@ -318,6 +330,8 @@ BatchDev make_dev(const Batch &b) {
         kd.rate = b.kls[k]->d_rate;
         for (int q = 0; q < 3; q++) kd.ubuf[q] = c.d_ubuf[q];
         kd.part = c.d_part;
+        kd.ab = b.d_ab[k];
+        kd.rq = b.d_rq[k];
     }
     bd.work = b.d_work;
     bd.n_items = b.n_items;

@@ -17,6 +17,8 @@ struct BatchKind {
     const void *rate = nullptr;     // per copy signed ramp rate, or null
     void *ubuf[3] = {nullptr, nullptr, nullptr};
     void *part = nullptr;
+    const void *ab = nullptr;       // per copy (A, B') side by side
+    const void *rq = nullptr;       // per copy (target x, y, z, ramp rate), or null (no loads)
 };
 
 struct BatchDev {
@@ -32,6 +34,9 @@ struct BatchDev {
 };
 
 bool batch_variant_ok(int prec, int v);
+// ab[2l..2l+1] = (A_l, B'_l); with ru: rq[4l..4l+3] = (ru_x, ru_y, ru_z, rate_l or 0)
+hipError_t launch_pack_copy_pairs(int prec, int n_copies, const void *acoef, const void *bpc, const void *ru,
+                                  const void *rate, void *ab, void *rq, hipStream_t s);
 int batch_geometry(int v);  // the step-kernel variant whose chunk geometry batch variant v uses
 #ifdef DJ_INSTR
 hipError_t instr_set(uint64_t *p);  // instrumented build: the sub-phase counter array

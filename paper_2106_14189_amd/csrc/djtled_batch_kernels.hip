@@ -56,7 +56,6 @@ template <typename T>
 __device__ __forceinline__ StepPtrs<T> kind_ptrs(const BatchKind &kd, int cur, int prv, int nxt, int s, int64_t n) {
     StepPtrs<T> sp;
     const int64_t L = kd.tp.n_copies;
-    const T *ru = static_cast<const T *>(kd.ru);
     const T *u0 = static_cast<const T *>(kd.ubuf[0]), *u1 = static_cast<const T *>(kd.ubuf[1]),
             *u2 = static_cast<const T *>(kd.ubuf[2]);
     const T *uc = cur == 0 ? u0 : (cur == 1 ? u1 : u2);
@@ -68,18 +67,18 @@ __device__ __forceinline__ StepPtrs<T> kind_ptrs(const BatchKind &kd, int cur, i
         sp.uc[k] = uc + k;
         sp.up[k] = up + k;
         sp.un[k] = un + k;
-        sp.ru[k] = ru ? ru + k * L : nullptr;
+        sp.ru[k] = static_cast<const T *>(kd.rq);  // (x, y, z, rate) per copy (Chunk::ld_rq)
     }
     // partial entries entry-major per parity (put_partial3 / get_partial3 read pp[0])
     for (int k = 0; k < 3; k++) sp.pp[k] = static_cast<T *>(kd.part) + (s & 1) * 3 * int64_t(kd.tp.n_part) + k;
     sp.flags = kd.flags;
-    sp.acoef = static_cast<const T *>(kd.tp.acoef);
+    sp.acoef = static_cast<const T *>(kd.ab);  // (A, B') per copy (Chunk::ld_ab)
     sp.bprime = T(0);
     sp.sval = T(0);
     sp.want_res = false;
     sp.fout = nullptr;
-    sp.bpc = static_cast<const T *>(kd.tp.bpc);
-    sp.rrate = static_cast<const T *>(kd.rate);
+    sp.bpc = nullptr;
+    sp.rrate = nullptr;
     sp.n1 = T(n + 1);
     sp.pn = nullptr;
     return sp;
@@ -427,6 +426,21 @@ __global__ void k_batch_reset(uint32_t *sync, int n_sync, int32_t *status, int c
     }
 }
 
+template <typename T>
+__global__ void k_pack_copy_pairs(int n_copies, const T *__restrict__ A, const T *__restrict__ bp,
+                                  const T *__restrict__ ru, const T *__restrict__ rate, T *__restrict__ ab,
+                                  T *__restrict__ rq) {
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= n_copies) return;
+    ab[2 * int64_t(l)] = A[l];
+    ab[2 * int64_t(l) + 1] = bp[l];
+    if (rq) {
+#pragma unroll
+        for (int k = 0; k < 3; k++) rq[4 * int64_t(l) + k] = ru[int64_t(k) * n_copies + l];
+        rq[4 * int64_t(l) + 3] = rate ? rate[l] : T(0);
+    }
+}
+
 // canonical copies -> caller-order arrays of the kind's instances
 template <typename T>
 __global__ void k_gather_canon(const uint32_t *__restrict__ flags, const int32_t *__restrict__ cnode, int n_copies,
@@ -510,6 +524,21 @@ hipError_t launch_batch_step(const BatchDev &bd, int prec, int v, int grid, hipS
 hipError_t launch_batch_reset(uint32_t *bar, int n_sync, int32_t *status, bool clear_status, hipStream_t s) {
     hipLaunchKernelGGL(k_batch_reset, dim3((n_sync + 255) / 256), dim3(256), 0, s, bar, n_sync, status,
                        clear_status ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_copy_pairs(int prec, int n_copies, const void *acoef, const void *bpc, const void *ru,
+                                  const void *rate, void *ab, void *rq, hipStream_t s) {
+    const int B = 256;
+    const dim3 g((n_copies + B - 1) / B);
+    if (prec == DJ_FP32)
+        hipLaunchKernelGGL(k_pack_copy_pairs<float>, g, dim3(B), 0, s, n_copies, static_cast<const float *>(acoef),
+                           static_cast<const float *>(bpc), static_cast<const float *>(ru),
+                           static_cast<const float *>(rate), static_cast<float *>(ab), static_cast<float *>(rq));
+    else
+        hipLaunchKernelGGL(k_pack_copy_pairs<double>, g, dim3(B), 0, s, n_copies, static_cast<const double *>(acoef),
+                           static_cast<const double *>(bpc), static_cast<const double *>(ru),
+                           static_cast<const double *>(rate), static_cast<double *>(ab), static_cast<double *>(rq));
     return hipGetLastError();
 }
 

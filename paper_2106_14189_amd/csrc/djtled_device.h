@@ -706,6 +706,25 @@ struct Chunk {
     // word in wp[j][2i] until they are used (slot(), after the chunk's wait)
     static constexpr bool PK = PC && !PF && sizeof(T) == 4;
     static constexpr bool AOS = PC;  // batches: copy displacements as 3-vectors (ld_u3)
+    // batches: a copy's (A, B') side by side, and its (load x, y, z, ramp rate)
+    struct alignas(2 * sizeof(T)) ABPair {
+        T a, b;
+    };
+    struct alignas(4 * sizeof(T)) RQuad {
+        T x, y, z, r;
+    };
+    __device__ static void ld_ab(const StepPtrs<T> &sp, int l, T &A, T &Bp) {
+        const ABPair p = reinterpret_cast<const ABPair *>(sp.acoef)[l];
+        A = p.a;
+        Bp = p.b;
+    }
+    __device__ static void ld_rq(const StepPtrs<T> &sp, int l, T (&rv)[3], T &rr) {
+        const RQuad q = reinterpret_cast<const RQuad *>(sp.ru[0])[l];
+        rv[0] = q.x;
+        rv[1] = q.y;
+        rv[2] = q.z;
+        rr = q.r;
+    }
     __device__ static int slot(const ElemRegs &er, int j, int a) {
         if constexpr (PK) return int((uint32_t(er.wp[j][a & ~1]) >> (16 * (a & 1))) & 0xffffu);
         else return er.wp[j][a];
@@ -772,8 +791,8 @@ struct Chunk {
                     c.pb[m] = tp.pidx[l];
                 } else if (MODE == 1) {
                     ld_u3<AOS>(sp.up, l, c.upv[m]);
-                    c.A[m] = sp.acoef[l];
-                    if constexpr (PC) c.Bp[m] = sp.bpc[l];
+                    if constexpr (PC) ld_ab(sp, l, c.A[m], c.Bp[m]);
+                    else c.A[m] = sp.acoef[l];
                 }
             }
         }
@@ -790,9 +809,12 @@ struct Chunk {
             if constexpr (PC) c.rr[m] = T(0);
             if (MODE == 1 && i < ch.n_interior && (c.fl[m] & FLAG_RU)) {
                 const int l = ch.copy_begin + i;
+                if constexpr (PC) {
+                    ld_rq(sp, l, c.rv[m], c.rr[m]);
+                } else {
 #pragma unroll
-                for (int k = 0; k < 3; k++) c.rv[m][k] = sp.ru[k][l];
-                if constexpr (PC) c.rr[m] = sp.rrate[l];
+                    for (int k = 0; k < 3; k++) c.rv[m][k] = sp.ru[k][l];
+                }
             }
         }
     }
@@ -1106,14 +1128,18 @@ struct Chunk {
                     r.fl[kb] = sp.flags[l];
                     r.pb[kb] = tp.pidx[l];
                     if (MODE == 1) {
-                        r.A[kb] = sp.acoef[l];
                         ld_u3<AOS>(sp.uc, l, r.uc[kb]);
                         ld_u3<AOS>(sp.up, l, r.up[kb]);
-#pragma unroll
-                        for (int k = 0; k < 3; k++) r.rv[kb][k] = sp.ru[0] ? sp.ru[k][l] : T(0);
                         if constexpr (PC) {
-                            r.bp[kb] = sp.bpc[l];
-                            r.rr[kb] = sp.rrate ? sp.rrate[l] : T(0);
+                            ld_ab(sp, l, r.A[kb], r.bp[kb]);
+#pragma unroll
+                            for (int k = 0; k < 3; k++) r.rv[kb][k] = T(0);
+                            r.rr[kb] = T(0);
+                            if (sp.ru[0]) ld_rq(sp, l, r.rv[kb], r.rr[kb]);
+                        } else {
+                            r.A[kb] = sp.acoef[l];
+#pragma unroll
+                            for (int k = 0; k < 3; k++) r.rv[kb][k] = sp.ru[0] ? sp.ru[k][l] : T(0);
                         }
                     }
                 }
@@ -1318,18 +1344,13 @@ struct Chunk {
                 r.li[kb] = l;
                 r.fl[kb] = x.fl[kb];
                 r.pb[kb] = x.pb[kb];
-                r.A[kb] = sp.acoef[l];
-                r.bp[kb] = sp.bpc[l];
+                ld_ab(sp, l, r.A[kb], r.bp[kb]);
                 ld_u3<AOS>(sp.uc, l, r.uc[kb]);
                 ld_u3<AOS>(sp.up, l, r.up[kb]);
 #pragma unroll
                 for (int k = 0; k < 3; k++) r.rv[kb][k] = T(0);
                 r.rr[kb] = T(0);
-                if ((x.fl[kb] & FLAG_RU) && sp.ru[0]) {
-#pragma unroll
-                    for (int k = 0; k < 3; k++) r.rv[kb][k] = sp.ru[k][l];
-                    if (sp.rrate) r.rr[kb] = sp.rrate[l];
-                }
+                if ((x.fl[kb] & FLAG_RU) && sp.ru[0]) ld_rq(sp, l, r.rv[kb], r.rr[kb]);
                 const int cnt = (x.fl[kb] >> FLAG_NCOPY_SHIFT) & 255u;
 #pragma unroll
                 for (int q = 0; q < SUNR; q++)
@@ -1353,13 +1374,13 @@ struct Chunk {
                     r.ok[kb] = true;
                     r.fl[kb] = x.fl[kb];
                     r.pb[kb] = x.pb[kb];
-                    r.A[kb] = sp.acoef[l];
+                    ld_ab(sp, l, r.A[kb], r.bp[kb]);
                     ld_u3<AOS>(sp.uc, l, r.uc[kb]);
                     ld_u3<AOS>(sp.up, l, r.up[kb]);
 #pragma unroll
-                    for (int k = 0; k < 3; k++) r.rv[kb][k] = sp.ru[0] ? sp.ru[k][l] : T(0);
-                    r.bp[kb] = sp.bpc[l];
-                    r.rr[kb] = sp.rrate ? sp.rrate[l] : T(0);
+                    for (int k = 0; k < 3; k++) r.rv[kb][k] = T(0);
+                    r.rr[kb] = T(0);
+                    if (sp.ru[0]) ld_rq(sp, l, r.rv[kb], r.rr[kb]);
                     const int cnt = (x.fl[kb] >> FLAG_NCOPY_SHIFT) & 255u;
 #pragma unroll
                     for (int q = 0; q < SUNR; q++)
