@@ -480,8 +480,8 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
     DJ_HIP(hipMemcpy(&bad, dbad, sizeof(int32_t), hipMemcpyDeviceToHost));
     DJ_HIP(hipMemcpy(dtc.data(), ddt, NI * sizeof(double), hipMemcpyDeviceToHost));
     if (bad) return fail(DJ_ERR_BAD_MESH, std::to_string(bad) + " element(s) with det(0J) <= 0 or zero fibre");
-    if (mi && mi->batch && c.prec == DJ_FP32) {
-        // the batch kernel's register path reads the interleaved copy (16-byte loads)
+    if (c.prec == DJ_FP32) {
+        // the register path of the FP32 kernels reads the interleaved copy (16-byte loads)
         DJ_HIP(dalloc(c, &p, size_t(NP + NE / 2) * c.topo.estride * 4));
         DJ_HIP(launch_pack_elem4(c, p, nullptr));
         DJ_HIP(hipDeviceSynchronize());

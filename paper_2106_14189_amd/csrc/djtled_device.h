@@ -701,10 +701,12 @@ struct Chunk {
     // LDS of the average-nodal-pressure step: a fourth slot plane carries p_n
     static constexpr size_t LDS_ANP = LDS + size_t(NE) * CMAX * sizeof(T);
 
-    // FP32 batches read the interleaved element copy (elem4): NP + NE / 2 words
-    // per element in 16-byte loads; the slot positions stay packed two to a
-    // word in wp[j][2i] until they are used (slot(), after the chunk's wait)
-    static constexpr bool PK = PC && !PF && sizeof(T) == 4;
+    // FP32 contexts read the interleaved element copy (elem4): NP + NE / 2
+    // words per element in 16-byte loads; the slot positions stay packed two
+    // to a word in wp[j][2i] until they are used (slot(), after the chunk's
+    // wait).  The average-nodal-pressure step and forces read the planes (the
+    // force pass takes a modified kappa plane).
+    static constexpr bool PK = !PF && sizeof(T) == 4 && !ANPM;
     static constexpr bool AOS = PC;  // batches: copy displacements as 3-vectors (ld_u3)
     // batches: a copy's (A, B') side by side, and its (load x, y, z, ramp rate)
     struct alignas(2 * sizeof(T)) ABPair {
