@@ -99,7 +99,7 @@ struct DevTopo {
     const int32_t *cnode = nullptr;      // caller node index of each copy
     int32_t n_part = 0;                  // partial-force entries (one per shared copy)
     const void *elem = nullptr;          // element planes (context precision)
-    // FP32 batches: the same planes and slot positions interleaved per element,
+    // FP32 contexts: the same planes and slot positions interleaved per element,
     // D = NP + NE / 2 words (two positions per word): words 4g .. 4g + 3 of
     // element e at 16-byte entry g * estride + e (g < D / 4), the last D % 4
     // words as single planes after them (word 4 (D / 4) + r at r * estride + e)
