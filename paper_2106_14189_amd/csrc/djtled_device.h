@@ -1287,7 +1287,7 @@ struct Chunk {
     // together with the partials.  So the kernel issues, in one round, the
     // state and partials of batch b, the indices of batch b + 1 and the stores
     // of batch b - 1 (the results wait in registers, SharedHeld).
-    static constexpr int SUNR = 4;  // partials per copy loaded with the state (more are read on the spot)
+    static constexpr int SUNR = 8;  // partials per copy loaded with the state (more are read on the spot)
     template <int KB>
     struct SharedIdx {
         uint32_t fl[KB];
