@@ -282,10 +282,13 @@ int build(Ctx &c, const djtled_mesh *mesh, const djtled_material *mat, const djt
             for (int a = 0; a < NE; a++) cnt[local_of[conn[int64_t(NE) * e + a]]]++;
         std::vector<int32_t> pos(order.size());
         int32_t acc = 0;
+        // ranges start an odd distance apart (a padding slot after an even
+        // count): a wave's copies then walk their ranges on distinct LDS banks;
+        // at most one padding slot per copy, which the kernels' slot planes hold
         for (size_t i = 0; i < order.size(); i++) {
             pos[i] = acc;
             crange.push_back(uint32_t(acc) | (uint32_t(cnt[i]) << 16));
-            acc += cnt[i];
+            acc += cnt[i] + ((cnt[i] & 1) ? 0 : 1);
         }
         for (int e = eb; e < ee; e++)
             for (int a = 0; a < NE; a++) {

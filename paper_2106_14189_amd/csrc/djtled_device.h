@@ -644,7 +644,11 @@ template <typename T, int NE, int MODEL, int BLOCK, int EPT, int MC, bool PC = f
 struct Chunk {
     static constexpr int CMAX = BLOCK * EPT;
     static constexpr int NP = Planes<NE, MODEL>::N;
-    static constexpr size_t SLOTS = size_t(3) * NE * CMAX * sizeof(T);
+    // slot plane: the chunk's NE x CMAX incidences and up to one padding slot
+    // per copy (each copy's range starts an odd distance after the previous
+    // one, so the copies of a wave walk their ranges on distinct LDS banks)
+    static constexpr int SP = NE * CMAX + MC * BLOCK;
+    static constexpr size_t SLOTS = size_t(3) * SP * sizeof(T);
     static constexpr int PDW = CMAX * int(sizeof(T)) / 4;  // dwords of one staged plane
     static constexpr int WDW = CMAX / 2 + 2;               // dwords of one staged slot-position plane
     static constexpr size_t STAGE = PF ? size_t(4) * (size_t(NP) * PDW + size_t(NE) * WDW) : 0;
@@ -699,7 +703,7 @@ struct Chunk {
     };
     static constexpr bool ANPM = (MODEL & DJ_FORM_ANP) != 0;
     // LDS of the average-nodal-pressure step: a fourth slot plane carries p_n
-    static constexpr size_t LDS_ANP = LDS + size_t(NE) * CMAX * sizeof(T);
+    static constexpr size_t LDS_ANP = LDS + size_t(SP) * sizeof(T);
 
     // FP32 contexts read the interleaved element copy (elem4): NP + NE / 2
     // words per element in 16-byte loads; the slot positions stay packed two
@@ -837,8 +841,8 @@ struct Chunk {
     // u^n (and the nodal pressure of the average-nodal-pressure step) of each
     // copy over its contiguous incidence range
     __device__ static void scatter_u(const ChunkDesc &ch, const StepPtrs<T> &sp, T *lx, const CopyRegs &cin) {
-        T *ly = lx + NE * CMAX;
-        T *lz = lx + 2 * NE * CMAX;
+        T *ly = lx + SP;
+        T *lz = lx + 2 * SP;
 #pragma unroll
         for (int m = 0; m < MC; m++) {
             const int i = int(threadIdx.x) + m * BLOCK;
@@ -851,7 +855,7 @@ struct Chunk {
                 }
                 if constexpr (ANPM)
                     if (sp.pn)
-                        for (int q = b; q < b + n; q++) lz[NE * CMAX + q] = cin.pn[m];
+                        for (int q = b; q < b + n; q++) lz[SP + q] = cin.pn[m];
             }
         }
     }
@@ -861,8 +865,8 @@ struct Chunk {
     template <typename Done = NoOpJ>
     __device__ static void forces(const ChunkDesc &ch, const StepPtrs<T> &sp, T *lx, PhaseOut &po, ElemRegs &er,
                                   Done done = Done()) {
-        T *ly = lx + NE * CMAX;
-        T *lz = lx + 2 * NE * CMAX;
+        T *ly = lx + SP;
+        T *lz = lx + 2 * SP;
 #pragma unroll
         for (int j = 0; j < EPT; j++) {
             const int e = int(threadIdx.x) + j * BLOCK;
@@ -885,7 +889,7 @@ struct Chunk {
                     if (sp.pn) {
                         T pb = 0;
 #pragma unroll
-                        for (int a = 0; a < NE; a++) pb += lz[NE * CMAX + slot(er, j, a)];
+                        for (int a = 0; a < NE; a++) pb += lz[SP + slot(er, j, a)];
                         cst[Planes<NE, MODEL>::KAV] *= pb * T(1.0 / NE);
                     }
                     J = element_force<T, NE, MODEL>(cst, u, F);
@@ -915,8 +919,8 @@ struct Chunk {
 
     // node sum of the thread's copy m over its range, in fixed order
     __device__ static void copy_sum(const CopyRegs &c, int m, const T *lx, T (&f)[3]) {
-        const T *ly = lx + NE * CMAX;
-        const T *lz = lx + 2 * NE * CMAX;
+        const T *ly = lx + SP;
+        const T *lz = lx + 2 * SP;
         const int b = c.cr[m] & 0xffffu, n = c.cr[m] >> 16;
         f[0] = f[1] = f[2] = T(0);
         // four slots' reads in flight per round, added in slot order (the same sums)
@@ -1217,8 +1221,8 @@ struct Chunk {
         load_elems(tp, ch, er);
         load_copies<0>(tp, ch, sp, cp);
         T *lx = reinterpret_cast<T *>(smem);
-        T *ly = lx + NE * CMAX;
-        T *lz = lx + 2 * NE * CMAX;
+        T *ly = lx + SP;
+        T *lz = lx + 2 * SP;
 #pragma unroll
         for (int m = 0; m < MC; m++) {
             const int i = tid + m * BLOCK;
