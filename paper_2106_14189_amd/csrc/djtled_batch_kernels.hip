@@ -236,7 +236,8 @@ __global__ void __launch_bounds__((Kinds<T, V>::BLOCK), (Kinds<T, V>::WPE)) k_ba
         const int nb0 = nmine > 0 ? batch_len(0, wn0) : 0;
         const int kind0 = nmine > 0 ? __builtin_amdgcn_readfirstlane(s_kind[0]) : 0;
         // FP32 register and staging variants with one window: one memory round per
-        // shared batch (Chunk::shared_fetch); its first round A goes out before the barrier
+        // round of shared copies (Chunk::shared_fetch_l); the first round's indices
+        // go out before the barrier
         bool spipe = false;
         if constexpr (K::PIPE) spipe = nmine > 0 && nmine <= KMAXB;
         // the shared copies of a run of chunks of one kind, concatenated in chunk

@@ -1283,14 +1283,13 @@ struct Chunk {
         }
     }
 
-    // all passes of one batch of chunks
-    // Shared-node phase of the batch path with one memory round per batch of
-    // chunks.  Round A is only what the partial loads need (flags and
+    // Shared-node phase of the batch path with one memory round per round of
+    // copies.  The index round is only what the partial loads need (flags and
     // partial-group index per shared copy); every other value of a copy is
-    // addressed by its index, which the chunk descriptor gives, and is loaded
-    // together with the partials.  So the kernel issues, in one round, the
-    // state and partials of batch b, the indices of batch b + 1 and the stores
-    // of batch b - 1 (the results wait in registers, SharedHeld).
+    // addressed by its copy index and is loaded together with the partials.
+    // So the kernel issues, in one round, the state and partials of round r,
+    // the indices of round r + 1 and the stores of round r - 1 (the results
+    // wait in registers, SharedHeld).
     static constexpr int SUNR = 8;  // partials per copy loaded with the state (more are read on the spot)
     template <int KB>
     struct SharedIdx {
@@ -1306,24 +1305,6 @@ struct Chunk {
         int l[KB];  // < 0: nothing to store
         T v[KB][3];
     };
-    template <int KB>
-    __device__ static void shared_idx(const DevTopo &tp, const ChunkDesc *chs, int nb, int pass, const StepPtrs<T> &sp,
-                                      SharedIdx<KB> &x) {
-#pragma unroll
-        for (int kb = 0; kb < KB; kb++) {
-            x.fl[kb] = 0u;
-            x.pb[kb] = 0;
-            if (kb < nb) {
-                const ChunkDesc &ch = chs[kb];
-                const int i = ch.n_interior + int(threadIdx.x) + pass * BLOCK;
-                if (i < ch.copy_count) {
-                    const int l = ch.copy_begin + i;
-                    x.fl[kb] = sp.flags[l];
-                    x.pb[kb] = tp.pidx[l];
-                }
-            }
-        }
-    }
     // the same two loads by copy index (l < 0: no copy in this slot)
     template <int KB>
     __device__ static void shared_idx_l(const DevTopo &tp, const StepPtrs<T> &sp, const int (&ls)[KB], SharedIdx<KB> &x) {
@@ -1365,37 +1346,6 @@ struct Chunk {
         }
     }
     template <int KB>
-    __device__ static void shared_fetch(const ChunkDesc *chs, int nb, int pass, const StepPtrs<T> &sp,
-                                        const SharedIdx<KB> &x, SharedRegs<T, KB> &r, SharedPart<KB> &pt) {
-        static_assert(PC, "batch path");
-#pragma unroll
-        for (int kb = 0; kb < KB; kb++) {
-            r.ok[kb] = false;
-            if (kb < nb) {
-                const ChunkDesc &ch = chs[kb];
-                const int i = ch.n_interior + int(threadIdx.x) + pass * BLOCK;
-                if (i < ch.copy_count) {
-                    const int l = ch.copy_begin + i;
-                    r.li[kb] = l;
-                    r.ok[kb] = true;
-                    r.fl[kb] = x.fl[kb];
-                    r.pb[kb] = x.pb[kb];
-                    ld_ab(sp, l, r.A[kb], r.bp[kb]);
-                    ld_u3<AOS>(sp.uc, l, r.uc[kb]);
-                    ld_u3<AOS>(sp.up, l, r.up[kb]);
-#pragma unroll
-                    for (int k = 0; k < 3; k++) r.rv[kb][k] = T(0);
-                    r.rr[kb] = T(0);
-                    if (sp.ru[0]) ld_rq(sp, l, r.rv[kb], r.rr[kb]);
-                    const int cnt = (x.fl[kb] >> FLAG_NCOPY_SHIFT) & 255u;
-#pragma unroll
-                    for (int q = 0; q < SUNR; q++)
-                        if (q < cnt) get_partial3<AOS>(sp.pp, x.pb[kb] + q, pt.px[kb][q]);
-                }
-            }
-        }
-    }
-    template <int KB>
     __device__ static void shared_values(SharedRegs<T, KB> &r, const SharedPart<KB> &pt, const StepPtrs<T> &sp,
                                          PhaseOut &po, SharedHeld<KB> &h) {
         static_assert(PC, "batch path");
@@ -1425,6 +1375,7 @@ struct Chunk {
         }
     }
 
+    // all passes of one batch of chunks (round A, then the partial groups and the update)
     template <int MODE, int KB>
     __device__ static void shared_batch(const DevTopo &tp, const ChunkDesc *chs, int nb, int first_pass,
                                         const StepPtrs<T> &sp, PhaseOut &po) {
