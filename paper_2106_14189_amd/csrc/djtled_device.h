@@ -648,7 +648,12 @@ struct Chunk {
     // per copy (each copy's range starts an odd distance after the previous
     // one, so the copies of a wave walk their ranges on distinct LDS banks)
     static constexpr int SP = NE * CMAX + MC * BLOCK;
-    static constexpr size_t SLOTS = size_t(3) * SP * sizeof(T);
+    static constexpr bool ANPM = (MODEL & DJ_FORM_ANP) != 0;
+    // FP32 (not the average-nodal-pressure passes): a slot's x, y, z side by
+    // side in one 16-byte entry, so a gather, a scatter or a sum step is one
+    // LDS access; otherwise three planes of SP slots
+    static constexpr bool L4 = sizeof(T) == 4 && !ANPM;
+    static constexpr size_t SLOTS = (L4 ? size_t(4) : size_t(3)) * SP * sizeof(T);
     static constexpr int PDW = CMAX * int(sizeof(T)) / 4;  // dwords of one staged plane
     static constexpr int WDW = CMAX / 2 + 2;               // dwords of one staged slot-position plane
     static constexpr size_t STAGE = PF ? size_t(4) * (size_t(NP) * PDW + size_t(NE) * WDW) : 0;
@@ -701,7 +706,6 @@ struct Chunk {
         T ux[MC][3], upv[MC][3], A[MC], Bp[MC], rr[MC], rv[MC][3];
         T pn[MC];  // average-nodal-pressure step: the copy's nodal pressure
     };
-    static constexpr bool ANPM = (MODEL & DJ_FORM_ANP) != 0;
     // LDS of the average-nodal-pressure step: a fourth slot plane carries p_n
     static constexpr size_t LDS_ANP = LDS + size_t(SP) * sizeof(T);
 
@@ -838,24 +842,43 @@ struct Chunk {
         process<MODE, false>(tp, ch, sp, smem, po, er, cp, after);
     }
 
+    struct alignas(16) Slot4 {
+        float x, y, z, w;
+    };
+    __device__ static void slot_put(T *lx, int q, T a, T b, T c) {
+        if constexpr (L4) {
+            reinterpret_cast<Slot4 *>(lx)[q] = Slot4{a, b, c, 0.0f};
+        } else {
+            lx[q] = a;
+            lx[SP + q] = b;
+            lx[2 * SP + q] = c;
+        }
+    }
+    __device__ static void slot_get(const T *lx, int q, T &a, T &b, T &c) {
+        if constexpr (L4) {
+            const Slot4 v = reinterpret_cast<const Slot4 *>(lx)[q];
+            a = v.x;
+            b = v.y;
+            c = v.z;
+        } else {
+            a = lx[q];
+            b = lx[SP + q];
+            c = lx[2 * SP + q];
+        }
+    }
+
     // u^n (and the nodal pressure of the average-nodal-pressure step) of each
     // copy over its contiguous incidence range
     __device__ static void scatter_u(const ChunkDesc &ch, const StepPtrs<T> &sp, T *lx, const CopyRegs &cin) {
-        T *ly = lx + SP;
-        T *lz = lx + 2 * SP;
 #pragma unroll
         for (int m = 0; m < MC; m++) {
             const int i = int(threadIdx.x) + m * BLOCK;
             if (i < ch.copy_count) {
                 const int b = cin.cr[m] & 0xffffu, n = cin.cr[m] >> 16;
-                for (int q = b; q < b + n; q++) {
-                    lx[q] = cin.ux[m][0];
-                    ly[q] = cin.ux[m][1];
-                    lz[q] = cin.ux[m][2];
-                }
+                for (int q = b; q < b + n; q++) slot_put(lx, q, cin.ux[m][0], cin.ux[m][1], cin.ux[m][2]);
                 if constexpr (ANPM)
                     if (sp.pn)
-                        for (int q = b; q < b + n; q++) lz[SP + q] = cin.pn[m];
+                        for (int q = b; q < b + n; q++) lx[3 * SP + q] = cin.pn[m];
             }
         }
     }
@@ -865,19 +888,13 @@ struct Chunk {
     template <typename Done = NoOpJ>
     __device__ static void forces(const ChunkDesc &ch, const StepPtrs<T> &sp, T *lx, PhaseOut &po, ElemRegs &er,
                                   Done done = Done()) {
-        T *ly = lx + SP;
-        T *lz = lx + 2 * SP;
 #pragma unroll
         for (int j = 0; j < EPT; j++) {
             const int e = int(threadIdx.x) + j * BLOCK;
             if (e < ch.elem_count) {
                 T u[NE][3], F[NE][3];
 #pragma unroll
-                for (int a = 0; a < NE; a++) {
-                    u[a][0] = lx[slot(er, j, a)];
-                    u[a][1] = ly[slot(er, j, a)];
-                    u[a][2] = lz[slot(er, j, a)];
-                }
+                for (int a = 0; a < NE; a++) slot_get(lx, slot(er, j, a), u[a][0], u[a][1], u[a][2]);
                 T J;
                 if constexpr (ANPM) {
                     // average nodal pressure: with sp.pn the kappa plane holds 0V and the
@@ -889,7 +906,7 @@ struct Chunk {
                     if (sp.pn) {
                         T pb = 0;
 #pragma unroll
-                        for (int a = 0; a < NE; a++) pb += lz[SP + slot(er, j, a)];
+                        for (int a = 0; a < NE; a++) pb += lx[3 * SP + slot(er, j, a)];
                         cst[Planes<NE, MODEL>::KAV] *= pb * T(1.0 / NE);
                     }
                     J = element_force<T, NE, MODEL>(cst, u, F);
@@ -900,11 +917,8 @@ struct Chunk {
                 // left out so that the error is reported at the element itself
                 const bool ok = J > T(0);
 #pragma unroll
-                for (int a = 0; a < NE; a++) {
-                    lx[slot(er, j, a)] = ok ? F[a][0] : T(0);
-                    ly[slot(er, j, a)] = ok ? F[a][1] : T(0);
-                    lz[slot(er, j, a)] = ok ? F[a][2] : T(0);
-                }
+                for (int a = 0; a < NE; a++)
+                    slot_put(lx, slot(er, j, a), ok ? F[a][0] : T(0), ok ? F[a][1] : T(0), ok ? F[a][2] : T(0));
                 if (!isfinite(J)) {
                     po.bad = DJ_ERR_NONFINITE;
                     po.bad_elem = ch.elem_begin + e;
@@ -919,8 +933,6 @@ struct Chunk {
 
     // node sum of the thread's copy m over its range, in fixed order
     __device__ static void copy_sum(const CopyRegs &c, int m, const T *lx, T (&f)[3]) {
-        const T *ly = lx + SP;
-        const T *lz = lx + 2 * SP;
         const int b = c.cr[m] & 0xffffu, n = c.cr[m] >> 16;
         f[0] = f[1] = f[2] = T(0);
         // four slots' reads in flight per round, added in slot order (the same sums)
@@ -928,11 +940,7 @@ struct Chunk {
         for (; q + 4 <= b + n; q += 4) {
             T x[4], y[4], z[4];
 #pragma unroll
-            for (int t = 0; t < 4; t++) {
-                x[t] = lx[q + t];
-                y[t] = ly[q + t];
-                z[t] = lz[q + t];
-            }
+            for (int t = 0; t < 4; t++) slot_get(lx, q + t, x[t], y[t], z[t]);
 #pragma unroll
             for (int t = 0; t < 4; t++) {
                 f[0] += x[t];
@@ -941,9 +949,11 @@ struct Chunk {
             }
         }
         for (; q < b + n; q++) {
-            f[0] += lx[q];
-            f[1] += ly[q];
-            f[2] += lz[q];
+            T x, y, z;
+            slot_get(lx, q, x, y, z);
+            f[0] += x;
+            f[1] += y;
+            f[2] += z;
         }
     }
 
