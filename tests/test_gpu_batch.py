@@ -30,10 +30,11 @@ def S():
     return solver
 
 
-def _mixed(n_steps, seed=7):
+def _mixed(n_steps, seed=7, spec=None):
     """Six small instances: every element kind, uneven sizes, own loads and damping."""
-    spec = [(300, W.T4, W.NH), (900, W.T4, W.TI), (120, W.H8, W.NH), (250, W.H8, W.TI), (2000, W.T4, W.NH),
-            (60, W.H8, W.NH)]
+    if spec is None:
+        spec = [(300, W.T4, W.NH), (900, W.T4, W.TI), (120, W.H8, W.NH), (250, W.H8, W.TI), (2000, W.T4, W.NH),
+                (60, W.H8, W.NH)]
     out = []
     for k, (ne, elem, model) in enumerate(spec):
         rng = np.random.default_rng(seed + 11 * k)
@@ -91,6 +92,33 @@ def test_batch_matches_oracle_per_instance(S, prec, variant):
     for i, (mesh, mat, ld, alpha) in enumerate(spec):
         d = b.instance(i)
         assert d["n_nodes"] == mesh.n_nodes and d["n_elems"] == mesh.n_elems and d["alpha"] == alpha
+        uo = _oracle_run(mesh, mat, ld, alpha, d["dt"], n_steps)
+        ug = b.read(i).double().cpu().numpy()
+        err = np.abs(ug - uo).max() / np.abs(uo).max()
+        say(f"  instance {i} ({mesh.ne}-node, model {mat.model}, {mesh.n_elems} el): rel error {err:.2e}")
+        assert err <= tol
+    b.close()
+
+
+@pytest.mark.parametrize("prec,variant", [("fp32", 2), ("fp32", 8), ("fp64", 0)])
+def test_batch_tiny_chunks_nodes_in_many_chunks(S, prec, variant):
+    """Chunks of 8 elements: a tetrahedral node then lies in many chunks (its
+    partial group is longer than the partials fetched with a copy's state),
+    every workgroup holds several chunks of several kinds (several runs of one
+    kind, each starting its own rounds of shared copies), and most node copies
+    are shared."""
+    n_steps = 100
+    spec = _mixed(n_steps, seed=13, spec=[(6000, W.T4, W.NH), (3000, W.T4, W.TI), (1500, W.H8, W.NH),
+                                           (800, W.H8, W.TI)])
+    b = S.Batch(_instances(S, spec), precision=prec, variant=variant, chunk_elems=8)
+    inf = b.info()
+    say(f"{prec} v{variant}: {inf['n_items']} chunks of {inf['chunk_elems']} on {inf['grid_blocks']} workgroups")
+    assert inf["chunk_elems"] == 8 and inf["n_items"] > 2 * inf["grid_blocks"]
+    st = b.run(n_steps)
+    assert st.code == 0 and st.steps_done == n_steps
+    tol = 1e-4 if prec == "fp32" else 1e-10
+    for i, (mesh, mat, ld, alpha) in enumerate(spec):
+        d = b.instance(i)
         uo = _oracle_run(mesh, mat, ld, alpha, d["dt"], n_steps)
         ug = b.read(i).double().cpu().numpy()
         err = np.abs(ug - uo).max() / np.abs(uo).max()
