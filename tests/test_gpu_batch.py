@@ -103,7 +103,7 @@ def test_batch_matches_oracle_per_instance(S, prec, variant):
 @pytest.mark.parametrize("prec,variant", [("fp32", 2), ("fp32", 8), ("fp64", 0)])
 def test_batch_tiny_chunks_nodes_in_many_chunks(S, prec, variant):
     """Chunks of 8 elements: a tetrahedral node then lies in many chunks (its
-    partial group is longer than the partials fetched with a copy's state),
+    partial group can be longer than the partials fetched with a copy's state),
     every workgroup holds several chunks of several kinds (several runs of one
     kind, each starting its own rounds of shared copies), and most node copies
     are shared."""
