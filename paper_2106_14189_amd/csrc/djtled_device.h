@@ -651,7 +651,7 @@ struct Chunk {
     static constexpr bool ANPM = (MODEL & DJ_FORM_ANP) != 0;
     // FP32 (not the average-nodal-pressure passes): a slot's x, y, z side by
     // side in one 16-byte entry, so a gather, a scatter or a sum step is one
-    // LDS access; otherwise three planes of SP slots
+    // 12-byte LDS access; otherwise three planes of SP slots
     static constexpr bool L4 = sizeof(T) == 4 && !ANPM;
     static constexpr size_t SLOTS = (L4 ? size_t(4) : size_t(3)) * SP * sizeof(T);
     static constexpr int PDW = CMAX * int(sizeof(T)) / 4;  // dwords of one staged plane
@@ -842,12 +842,12 @@ struct Chunk {
         process<MODE, false>(tp, ch, sp, smem, po, er, cp, after);
     }
 
-    struct alignas(16) Slot4 {
-        float x, y, z, w;
+    struct alignas(16) Slot4 {  // 12 bytes used of 16
+        float x, y, z;
     };
     __device__ static void slot_put(T *lx, int q, T a, T b, T c) {
         if constexpr (L4) {
-            reinterpret_cast<Slot4 *>(lx)[q] = Slot4{a, b, c, 0.0f};
+            reinterpret_cast<Slot4 *>(lx)[q] = Slot4{a, b, c};
         } else {
             lx[q] = a;
             lx[SP + q] = b;
